@@ -1,0 +1,265 @@
+/*
+ * rc_oracle.c -- brute-force CPU oracle for batched ray-cast rendering.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP renderer.
+ *
+ * What it computes (paper, Sec. III-D "Exteroceptive Sensors"):
+ *   - each environment's mesh is the union of its sub-meshes, each moved by
+ *     its own transform (world vertex = A[:, :3] v + A[:, 3]);
+ *   - one ray is cast per pixel (pinhole camera) or per beam (LiDAR) from the
+ *     sensor origin;
+ *   - the reported value is the distance from the image plane for cameras
+ *     (depth) and the sensor-to-hit distance for LiDARs (range).
+ * The paper builds a BVH only to accelerate this query; the result is the
+ * nearest intersection over *every* triangle of the environment, which is
+ * what this file computes, triangle by triangle, with no acceleration
+ * structure.
+ *
+ * Precision: the vertex transform and the ray directions are FP32 with a
+ * fixed fused-multiply-add order (the renderer's input precision); the
+ * intersection itself is evaluated in FP64 on those FP32 values.
+ *
+ * Readings where the paper is silent (numbered as in the design notes):
+ *   near/far is an interval on the ray parameter t (closed); triangles are
+ *   two-sided; no epsilon in the determinant test (reject det == 0 only);
+ *   equal t is resolved by the lower environment-local triangle id; misses
+ *   report t = -1, triangle -1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define ORC_API __attribute__((visibility("default")))
+
+/* classification bits (per ray) */
+#define ORC_HIT 1
+#define ORC_B_BARY 2      /* winner's barycentric margin <= 1e-4 */
+#define ORC_B_GAP 4       /* another candidate within 1e-4 relative depth */
+#define ORC_B_RANGE 8     /* winner within 1e-4 relative of near or far */
+#define ORC_B_GRAZE 16    /* |cos| between ray and winner normal < 1e-3 */
+#define ORC_B_NEARMISS 32 /* miss ray with a near-miss candidate */
+
+static const double MARGIN = 1e-4;
+static const double GRAZE = 1e-3;
+
+/* ---------------------------------------------------------------------- */
+/* Sub-mesh transform: one world triangle per entry.                        */
+/* corner_xyz: [n][9] prototype coordinates of the triangle's 3 corners      */
+/* inst_T:     [n_inst][12] row-major 3x4 affine;  tri_inst: [n] instance    */
+/* out:        [n][9] world coordinates                                      */
+/* ---------------------------------------------------------------------- */
+ORC_API void orc_transform(int64_t n, const float *corner_xyz, const int32_t *tri_inst,
+                           const float *inst_T, float *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *A = inst_T + 12 * (int64_t)tri_inst[i];
+        for (int c = 0; c < 3; ++c) {
+            const float x = corner_xyz[9 * i + 3 * c + 0];
+            const float y = corner_xyz[9 * i + 3 * c + 1];
+            const float z = corner_xyz[9 * i + 3 * c + 2];
+            for (int r = 0; r < 3; ++r) {
+                const float *row = A + 4 * r;
+                out[9 * i + 3 * c + r] = fmaf(row[0], x, fmaf(row[1], y, fmaf(row[2], z, row[3])));
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Constant-velocity instance motion: for every instance with dyn != 0 the   */
+/* translation column becomes fma(v, float(step) * dt, c0) (FP32), where c0  */
+/* is the translation at step 0; the linear part is unchanged.               */
+/* ---------------------------------------------------------------------- */
+ORC_API void orc_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn,
+                      int32_t step, float dt, float *T)
+{
+    const float sdt = (float)step * dt;
+    for (int64_t i = 0; i < n_inst; ++i) {
+        for (int k = 0; k < 12; ++k)
+            T[12 * i + k] = T0[12 * i + k];
+        if (dyn[i])
+            for (int r = 0; r < 3; ++r)
+                T[12 * i + 4 * r + 3] = fmaf(vel[3 * i + r], sdt, T0[12 * i + 4 * r + 3]);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Ray generation.                                                          */
+/* kind 0 pinhole: ray r = row*W + col; pixel centre (col+1/2, row+1/2),      */
+/*   row 0 at the top; square pixels with focal length (W/2)/tan(hfov/2);    */
+/*   local direction (1, -(col+1/2-W/2)*s, -(row+1/2-H/2)*s), s = 1/f, so    */
+/*   the forward component is exactly 1 and t is depth.                      */
+/* kind 1 LiDAR: ray r = ch*W + az with W azimuths and H channels;           */
+/*   elevation vmax - ch*(vmax-vmin)/(H-1) (channel 0 on top), azimuth       */
+/*   hmin + az*(hmax-hmin)/W counter-clockwise from +x; unit direction, so   */
+/*   t is range.                                                             */
+/* kind 2 table: local direction = table[r].                                 */
+/* World ray: origin = pose column 3, dir_i = A_i0 dx + A_i1 dy + A_i2 dz.   */
+/* ---------------------------------------------------------------------- */
+ORC_API void orc_rays(int32_t kind, int32_t W, int32_t H, float hfov, float vmin, float vmax,
+                      float hmin, float hmax, const float *table, const float *pose,
+                      int64_t n, const int64_t *ray_idx, float *o, float *d)
+{
+    const float s = (float)(tan((double)hfov * 0.5) / ((double)W * 0.5));
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t r = ray_idx[i];
+        float dl[3];
+        if (kind == 0) {
+            const int64_t row = r / W, col = r % W;
+            const float hw = (float)W * 0.5f, hh = (float)H * 0.5f;
+            dl[0] = 1.0f;
+            dl[1] = -((((float)col + 0.5f) - hw) * s);
+            dl[2] = -((((float)row + 0.5f) - hh) * s);
+        } else if (kind == 1) {
+            const int64_t ch = r / W, az = r % W;
+            const double el = H > 1 ? (double)vmax - (double)ch * ((double)vmax - (double)vmin) / (double)(H - 1)
+                                    : (double)vmax;
+            const double a = (double)hmin + (double)az * ((double)hmax - (double)hmin) / (double)W;
+            dl[0] = (float)(cos(el) * cos(a));
+            dl[1] = (float)(cos(el) * sin(a));
+            dl[2] = (float)sin(el);
+        } else {
+            dl[0] = table[3 * r + 0];
+            dl[1] = table[3 * r + 1];
+            dl[2] = table[3 * r + 2];
+        }
+        for (int k = 0; k < 3; ++k) {
+            const float *row = pose + 4 * k;
+            o[3 * i + k] = row[3];
+            d[3 * i + k] = fmaf(row[0], dl[0], fmaf(row[1], dl[1], row[2] * dl[2]));
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Nearest hit by exhaustive search.                                        */
+/* tris:     [N][9] world triangles (FP32), environment e owns the env-local */
+/*           triangles tris[env_off[e] .. env_off[e+1])                      */
+/* per ray:  env, origin o[3], direction d[3], near, far (FP32)              */
+/* outputs (all [n_rays], hit as [n][3]): t (-1 on miss), tri (env-local,    */
+/*   -1 on miss), u, v, hit point o + t d, bary margin, depth margin,        */
+/*   grazing cosine, classification bits.                                    */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    double t;
+    int64_t id;
+} orc_cand;
+
+static int cand_less(double ta, int64_t ia, double tb, int64_t ib)
+{
+    return ta < tb || (ta == tb && ia < ib);
+}
+
+ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
+                      const int32_t *ray_env, const float *o, const float *d,
+                      const float *nearv, const float *farv, int32_t nthreads,
+                      double *t_out, int32_t *tri_out, double *u_out, double *v_out,
+                      double *hit_out, double *mb_out, double *md_out, double *g_out,
+                      int32_t *cls_out)
+{
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t r = 0; r < n_rays; ++r) {
+        const int32_t e = ray_env[r];
+        const double ox = o[3 * r], oy = o[3 * r + 1], oz = o[3 * r + 2];
+        const double dx = d[3 * r], dy = d[3 * r + 1], dz = d[3 * r + 2];
+        const double tn = nearv[r], tf = farv[r];
+        const double lo = tn * (1.0 - MARGIN), hi = tf * (1.0 + MARGIN);
+
+        double bt = INFINITY, bu = 0, bv = 0;
+        int64_t bid = -1;
+        /* the two smallest (t, id) among loose candidates */
+        orc_cand c1 = {INFINITY, -1}, c2 = {INFINITY, -1};
+
+        const int64_t base = env_off[e], n = env_off[e + 1] - env_off[e];
+        for (int64_t k = 0; k < n; ++k) {
+            const float *T = tris + 9 * (base + k);
+            const double ax = T[0], ay = T[1], az = T[2];
+            const double e1x = (double)T[3] - ax, e1y = (double)T[4] - ay, e1z = (double)T[5] - az;
+            const double e2x = (double)T[6] - ax, e2y = (double)T[7] - ay, e2z = (double)T[8] - az;
+            /* p = d x e2, det = e1 . p */
+            const double px = dy * e2z - dz * e2y;
+            const double py = dz * e2x - dx * e2z;
+            const double pz = dx * e2y - dy * e2x;
+            const double det = e1x * px + e1y * py + e1z * pz;
+            if (det == 0.0)
+                continue;
+            const double inv = 1.0 / det;
+            const double sx = ox - ax, sy = oy - ay, sz = oz - az;
+            const double u = (sx * px + sy * py + sz * pz) * inv;
+            /* q = s x e1 */
+            const double qx = sy * e1z - sz * e1y;
+            const double qy = sz * e1x - sx * e1z;
+            const double qz = sx * e1y - sy * e1x;
+            const double v = (dx * qx + dy * qy + dz * qz) * inv;
+            const double t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+            const double w = 1.0 - u - v;
+            const double m = fmin(u, fmin(v, w));
+            if (m >= -MARGIN && t >= lo && t <= hi) {
+                if (cand_less(t, k, c1.t, c1.id)) {
+                    c2 = c1;
+                    c1.t = t;
+                    c1.id = k;
+                } else if (cand_less(t, k, c2.t, c2.id)) {
+                    c2.t = t;
+                    c2.id = k;
+                }
+            }
+            if (u >= 0.0 && v >= 0.0 && u + v <= 1.0 && t >= tn && t <= tf) {
+                if (cand_less(t, k, bt, bid)) {
+                    bt = t;
+                    bid = k;
+                    bu = u;
+                    bv = v;
+                }
+            }
+        }
+
+        int32_t cls = 0;
+        if (bid >= 0) {
+            cls |= ORC_HIT;
+            t_out[r] = bt;
+            tri_out[r] = (int32_t)bid;
+            u_out[r] = bu;
+            v_out[r] = bv;
+            hit_out[3 * r + 0] = ox + bt * dx;
+            hit_out[3 * r + 1] = oy + bt * dy;
+            hit_out[3 * r + 2] = oz + bt * dz;
+            const double mb = fmin(bu, fmin(bv, 1.0 - bu - bv));
+            /* nearest other candidate: c1 unless c1 is the winner itself */
+            const orc_cand other = (c1.id == bid) ? c2 : c1;
+            double md = fmin((bt - tn) / bt, (tf - bt) / bt);
+            if (other.id >= 0)
+                md = fmin(md, (other.t - bt) / bt);
+            /* grazing cosine |n.d| / (|n| |d|) */
+            const float *T = tris + 9 * (base + bid);
+            const double e1x = (double)T[3] - T[0], e1y = (double)T[4] - T[1], e1z = (double)T[5] - T[2];
+            const double e2x = (double)T[6] - T[0], e2y = (double)T[7] - T[1], e2z = (double)T[8] - T[2];
+            const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+            const double g = fabs(nx * dx + ny * dy + nz * dz) /
+                             (sqrt(nx * nx + ny * ny + nz * nz) * sqrt(dx * dx + dy * dy + dz * dz));
+            mb_out[r] = mb;
+            md_out[r] = md;
+            g_out[r] = g;
+            if (mb <= MARGIN)
+                cls |= ORC_B_BARY;
+            if (other.id >= 0 && (other.t - bt) / bt <= MARGIN)
+                cls |= ORC_B_GAP;
+            if ((bt - tn) / bt <= MARGIN || (tf - bt) / bt <= MARGIN)
+                cls |= ORC_B_RANGE;
+            if (g < GRAZE)
+                cls |= ORC_B_GRAZE;
+        } else {
+            t_out[r] = -1.0;
+            tri_out[r] = -1;
+            u_out[r] = v_out[r] = 0.0;
+            hit_out[3 * r + 0] = hit_out[3 * r + 1] = hit_out[3 * r + 2] = NAN;
+            mb_out[r] = md_out[r] = g_out[r] = NAN;
+            if (c1.id >= 0)
+                cls |= ORC_B_NEARMISS;
+        }
+        cls_out[r] = cls;
+    }
+}

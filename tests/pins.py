@@ -1,0 +1,480 @@
+"""Pins of the CPU oracle: checks against facts that do not come from the oracle.
+
+Each ``pin_*`` function runs one family of checks against the oracle library
+currently loaded by ``oracle.oracle`` and returns a list of failure messages
+(empty = pinned).  The pin tests assert emptiness; the mutation test swaps in
+deliberately broken oracle builds and asserts that every one of them is caught
+by at least one pin.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import exact
+from oracle import oracle as O
+from paper_2503_01471_amd import scenes as S
+
+F32 = np.float32
+
+
+def _world_of(tris):
+    tris = np.ascontiguousarray(np.asarray(tris, np.float32).reshape(-1, 9))
+    n = len(tris)
+    return O.World(tris, np.array([0, n], np.int64), np.zeros(n, np.int32), np.zeros(n, np.int32))
+
+
+# --------------------------------------------------------------------------
+# 1. exact rational arithmetic on tiny adversarial scenes
+# --------------------------------------------------------------------------
+def tiny_scene(seed: int):
+    """1-4 triangles and 64 rays; the family rotates over random triangles,
+    shared edges, coplanar overlaps, axis-aligned faces and degenerate triangles."""
+    rng = np.random.default_rng(seed)
+    kind = seed % 5
+    if kind == 0:
+        tris = rng.uniform(-1, 1, (int(rng.integers(1, 5)), 9))
+    elif kind == 1:  # quad split along a diagonal + one random triangle
+        p = rng.uniform(-1, 1, (4, 3))
+        p[3] = p[0] + (p[2] - p[1])  # planar parallelogram
+        tris = [np.r_[p[0], p[1], p[2]], np.r_[p[0], p[2], p[3]], rng.uniform(-1, 1, 9)]
+    elif kind == 2:  # coplanar overlapping triangles in z = c
+        c = rng.uniform(-0.5, 0.5)
+        tris = []
+        for _ in range(3):
+            xy = rng.uniform(-1, 1, (3, 2))
+            tris.append(np.c_[xy, np.full(3, c)].reshape(9))
+    elif kind == 3:  # axis-aligned box faces with representable coordinates
+        lo = np.round(rng.uniform(-1, 0, 3) * 8) / 8
+        hi = lo + np.round(rng.uniform(0.25, 1, 3) * 8) / 8
+        v = np.array([[x, y, z] for z in (lo[2], hi[2]) for y in (lo[1], hi[1]) for x in (lo[0], hi[0])])
+        tris = [np.r_[v[0], v[2], v[3]], np.r_[v[0], v[3], v[1]], np.r_[v[1], v[3], v[7]],
+                np.r_[v[1], v[7], v[5]]]
+    else:  # degenerate: collinear and repeated vertices, plus a proper triangle
+        a, b = rng.uniform(-1, 1, (2, 3))
+        tris = [np.r_[a, b, 0.5 * (a + b)], np.r_[a, a, b], rng.uniform(-1, 1, 9)]
+    tris = np.asarray(tris, np.float64).reshape(-1, 9).astype(np.float32)
+    o = rng.uniform(-3, 3, 3)
+    o[2] = 2.5 + rng.uniform(0, 1)
+    # aim at an 8x8 grid over the triangles' bounding box, plus edge points
+    lo, hi = tris.reshape(-1, 3).min(0), tris.reshape(-1, 3).max(0)
+    g = np.linspace(0, 1, 8)
+    targets = [lo + (hi - lo) * np.array([a, b, rng.random()]) for a in g for b in g]
+    for k in range(min(len(tris), 4)):
+        t = tris[k].reshape(3, 3).astype(np.float64)
+        targets[k] = 0.5 * (t[0] + t[1])
+        targets[8 + k] = 0.5 * (t[1] + t[2])
+        targets[16 + k] = t[0]
+    d = (np.array(targets) - o).astype(np.float32)
+    o = np.tile(o.astype(np.float32), (len(d), 1))
+    return tris, o, d
+
+
+def _t_tol(tri, o, d, t):
+    """FP64 error bound for t of a Moller-Trumbore solve: a few ulps times the
+    conditioning |e1||e2||d| / |det| of the 3x3 system (large for slivers and
+    grazing rays), scaled by how far the origin is from the triangle."""
+    a, b, c = (np.asarray(tri[3 * i:3 * i + 3], float) for i in range(3))
+    d = np.asarray(d, float)
+    e1, e2 = b - a, c - a
+    det = abs(np.dot(e1, np.cross(d, e2)))
+    kappa = np.linalg.norm(e1) * np.linalg.norm(e2) * np.linalg.norm(d) / det
+    reach = max(1.0, np.linalg.norm(np.asarray(o, float) - a) / (abs(t) * np.linalg.norm(d)))
+    return 1e-14 * abs(t) * max(1.0, kappa) * reach
+
+
+def pin_exact(seeds=range(200), near=0.05, far=50.0, margin_tol=1e-12):
+    fails = []
+    for seed in seeds:
+        tris, o, d = tiny_scene(seed)
+        r = O.cast(_world_of(tris), np.zeros(len(o), np.int32), o, d, near, far, nthreads=1)
+        for i in range(len(o)):
+            k, t, u, v, m = exact.nearest(list(tris), o[i], d[i], near, far)
+            if m <= margin_tol:
+                continue
+            if r["tri"][i] != k:
+                fails.append(f"exact seed {seed} ray {i}: oracle tri {r['tri'][i]} exact {k}")
+                continue
+            if k >= 0 and abs(r["t"][i] - float(t)) > _t_tol(tris[k], o[i], d[i], float(t)):
+                fails.append(f"exact seed {seed} ray {i}: t {r['t'][i]} exact {float(t)}")
+    return fails
+
+
+def pin_duplicate_tie():
+    """Identical triangles tie exactly; the lower triangle id must win."""
+    tri = np.array([0, 0, 1, 1, 0, 1, 0, 1, 1], np.float32)
+    rng = np.random.default_rng(7)
+    tgt = np.c_[rng.uniform(0.05, 0.45, (64, 2)), np.ones(64)]
+    o = np.zeros((64, 3), np.float32)
+    d = tgt.astype(np.float32)
+    r = O.cast(_world_of([tri, tri]), np.zeros(64, np.int32), o, d, 0.1, 10.0, nthreads=1)
+    bad = np.nonzero(r["tri"] != 0)[0]
+    return [f"tie ray {i}: tri {r['tri'][i]}" for i in bad]
+
+
+# --------------------------------------------------------------------------
+# 2. closed forms
+# --------------------------------------------------------------------------
+def _ground_scene(sensor, pose):
+    inst = [(0, 0, S.affine(np.diag([200.0, 200.0, 1.0]), (-100.0, -100.0, 0.0)), 0, (0, 0, 0))]
+    return S.custom_scene([S.quad_mesh()], [(inst, [(0, pose)])], [sensor])
+
+
+def pin_ray_plane():
+    """Level sensors above an infinite-looking ground plane: depth / range
+    follow from the pixel or beam geometry alone."""
+    fails = []
+    h = 1.5
+    # pinhole: depth of row v = h / ((v + 1/2 - H/2) s),  s = tan(hfov/2)/(W/2)
+    W, H = 64, 48
+    cam = S.pinhole(W, H, 87.0, near=0.2, far=80.0)
+    for yaw in (0.0, 0.7, 2.9):
+        sc = _ground_scene(cam, S.sensor_pose(S.rot_zyx(yaw), (1.25, -2.5, h)))
+        r = O.render(sc, nthreads=1)
+        s = math.tan(float(F32(cam.hfov)) / 2) / (W / 2)
+        for v in range(H):
+            k = (v + 0.5 - H / 2) * s
+            row = slice(v * W, (v + 1) * W)
+            if k <= 0:
+                if np.any(r.tri[row] != -1):
+                    fails.append(f"plane: row {v} above horizon hits")
+                continue
+            depth = h / k
+            if depth > 80.0:
+                continue
+            got = r.t[row]
+            if np.any(np.abs(got - depth) > 1e-6 * depth):
+                fails.append(f"plane: yaw {yaw} row {v} depth {got.min()}..{got.max()} want {depth}")
+            # exact plane intersection of the FP32 rays: t = -o_z / d_z
+            o, d = O.sensor_rays(sc, 0, np.arange(v * W, (v + 1) * W))
+            tz = -o[:, 2].astype(np.float64) / d[:, 2].astype(np.float64)
+            if np.any(np.abs(got - tz) > 1e-12 * tz):
+                fails.append(f"plane: row {v} not on z=0")
+    # LiDAR: range of channel c = h / sin(-el_c) for every azimuth
+    lid = S.lidar(64, 16, 90.0, near=0.1, far=80.0)
+    sc = _ground_scene(lid, S.sensor_pose(S.rot_zyx(0.3), (0.5, 0.25, h)))
+    r = O.render(sc, nthreads=1)
+    for c in range(16):
+        el = float(F32(lid.vmax)) - c * (float(F32(lid.vmax)) - float(F32(lid.vmin))) / 15
+        row = slice(c * 64, (c + 1) * 64)
+        if el >= 0:
+            if np.any(r.tri[row] != -1):
+                fails.append(f"lidar: channel {c} above horizon hits")
+            continue
+        rng_ = h / math.sin(-el)
+        if np.any(np.abs(r.t[row] - rng_) > 1e-6 * rng_):
+            fails.append(f"lidar: channel {c} range {r.t[row].min()} want {rng_}")
+    return fails
+
+
+def _slab(lo, hi, o, d):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = (lo - o) / d
+        t2 = (hi - o) / d
+    tmin = np.nanmax(np.minimum(t1, t2), axis=-1)
+    tmax = np.nanmin(np.maximum(t1, t2), axis=-1)
+    return tmin, tmax
+
+
+def pin_boxes(seed=0):
+    """cfg1 (ground + axis-aligned boxes): the 12-triangle box is exactly the box
+    surface, so on rays away from edges the nearest hit equals the nearest slab
+    entry/exit over all boxes and the ground plane, computed in FP64."""
+    fails = []
+    sc = S.make_cfg1(seed)
+    w = O.world(sc)
+    r = O.render(sc, w, nthreads=1)
+    o, d = O.sensor_rays(sc, 0)
+    o64, d64 = o.astype(np.float64), d.astype(np.float64)
+    desc = sc.sensors[0]
+    n = len(o)
+    best_t = np.full(n, np.inf)
+    best_seg = np.full(n, -1)
+    for j in range(sc.n_inst):
+        rows = np.nonzero(w.tri_inst == j)[0]
+        pts = w.tris[rows].reshape(-1, 3).astype(np.float64)
+        lo, hi = pts.min(0), pts.max(0)
+        tmin, tmax = _slab(lo, hi, o64, d64)
+        ok = tmin <= tmax
+        cand = np.where(ok & (tmin >= desc.near), tmin, np.where(ok & (tmax >= desc.near), tmax, np.inf))
+        cand[cand > desc.far] = np.inf
+        better = cand < best_t
+        best_t[better] = cand[better]
+        best_seg[better] = sc.inst_seg[j]
+    robust = (r.cls & O.BORDER_MASK) == 0
+    hit_ref = np.isfinite(best_t)
+    bad = robust & ((r.tri >= 0) != hit_ref)
+    if bad.any():
+        fails.append(f"boxes: hit/miss differs on {bad.sum()} robust rays")
+    both = robust & hit_ref & (r.tri >= 0)
+    err = np.abs(r.t[both] - best_t[both]) / best_t[both]
+    if err.size and err.max() > 1e-12:
+        fails.append(f"boxes: max rel depth err {err.max()}")
+    if np.any(r.seg[both] != best_seg[both]):
+        fails.append(f"boxes: seg differs on {(r.seg[both] != best_seg[both]).sum()} rays")
+    if robust.sum() < 0.9 * n:
+        fails.append("boxes: too few robust rays")
+    return fails
+
+
+def _sphere_t(o, d, R):
+    """Entry parameter of ray o + t d into the ball |x| <= R (inf if none)."""
+    a = (d * d).sum(-1)
+    b = 2 * (o * d).sum(-1)
+    c = (o * o).sum(-1) - R * R
+    disc = b * b - 4 * a * c
+    with np.errstate(invalid="ignore"):
+        t = (-b - np.sqrt(disc)) / (2 * a)
+    return np.where(disc >= 0, t, np.inf)
+
+
+def pin_tessellated():
+    """Convex tessellations bracket the smooth surface: a level-5 icosphere P
+    with inradius r_in and circumradius R satisfies B(r_in) <= P <= B(R), so
+    t(B(R)) <= t_mesh <= t(B(r_in)); likewise an N-gon prism of radius r lies
+    between the cylinders of radius r cos(pi/N) and r."""
+    fails = []
+    v, t = S.icosphere_mesh(5)
+    tri = v[t].reshape(-1, 9)
+    a, b, c = tri[:, :3].astype(float), tri[:, 3:6].astype(float), tri[:, 6:].astype(float)
+    nrm = np.cross(b - a, c - a)
+    r_in = np.min(np.abs((nrm * a).sum(1)) / np.linalg.norm(nrm, axis=1))
+    R = np.max(np.linalg.norm(v.astype(float), axis=1))
+    rng = np.random.default_rng(3)
+    n = 512
+    o = rng.normal(size=(n, 3))
+    o = (3.0 * o / np.linalg.norm(o, axis=1, keepdims=True)).astype(np.float32)
+    tgt = rng.uniform(-0.9, 0.9, (n, 3)) * 0.6
+    d = (tgt - o).astype(np.float32)
+    r = O.cast(_world_of(tri), np.zeros(n, np.int32), o, d, 0.0, 100.0)
+    o64, d64 = o.astype(float), d.astype(float)
+    t_out, t_in = _sphere_t(o64, d64, R), _sphere_t(o64, d64, r_in)
+    sel = np.isfinite(t_in)
+    if np.any(r["tri"][sel] < 0):
+        fails.append("sphere: ray through inner ball missed")
+    lo_ok = r["t"][sel] >= t_out[sel] * (1 - 1e-12)
+    hi_ok = r["t"][sel] <= t_in[sel] * (1 + 1e-12)
+    if not (lo_ok.all() and hi_ok.all()):
+        fails.append(f"sphere: bracket violated on {(~lo_ok).sum() + (~hi_ok).sum()} rays")
+    miss_outer = ~np.isfinite(t_out)
+    if np.any(r["tri"][miss_outer] >= 0):
+        fails.append("sphere: ray outside the outer ball hit")
+    if (1 - r_in / R) > 2e-3:
+        fails.append("sphere: tessellation bound too loose")
+    # 16-gon prism side: horizontal rays at mid height, 2-D bracket
+    v, t = S.cylinder_mesh(16)
+    tri = v[t].reshape(-1, 9)
+    m = 256
+    ang = rng.uniform(0, 2 * np.pi, m)
+    o = np.c_[4 * np.cos(ang), 4 * np.sin(ang), np.full(m, 0.5)]
+    off = rng.uniform(-0.8, 0.8, m)
+    tgt = np.c_[-np.sin(ang) * off, np.cos(ang) * off, np.full(m, 0.5)]
+    o, d = o.astype(np.float32), (tgt - o).astype(np.float32)
+    r = O.cast(_world_of(tri), np.zeros(m, np.int32), o, d, 0.0, 100.0)
+    o2, d2 = o[:, :2].astype(float), d[:, :2].astype(float)
+
+    def circ(rad):
+        a_ = (d2 * d2).sum(1)
+        b_ = 2 * (o2 * d2).sum(1)
+        c_ = (o2 * o2).sum(1) - rad * rad
+        disc = b_ * b_ - 4 * a_ * c_
+        with np.errstate(invalid="ignore"):
+            return np.where(disc >= 0, (-b_ - np.sqrt(disc)) / (2 * a_), np.inf)
+
+    t_out, t_in = circ(1.0), circ(math.cos(math.pi / 16))
+    sel = np.isfinite(t_in)
+    if np.any(r["tri"][sel] < 0) or np.any(r["t"][sel] < t_out[sel] * (1 - 1e-12)) or \
+            np.any(r["t"][sel] > t_in[sel] * (1 + 1e-12)):
+        fails.append("prism: bracket violated")
+    return fails
+
+
+# --------------------------------------------------------------------------
+# 3. invariants
+# --------------------------------------------------------------------------
+def pin_invariants():
+    fails = []
+    sc = S.make_cfg2(n_envs=2, W=96, H=54)
+    w = O.world(sc)
+    r = O.render(sc, w)
+    desc = sc.sensors[0]
+    hit = r.tri >= 0
+    if np.any((r.t[hit] < desc.near) | (r.t[hit] > desc.far)):
+        fails.append("invariant: depth outside [near, far]")
+    # hit point lies on the winning triangle's plane
+    S_ = sc.rays_per_sensor_inst()
+    env = np.repeat(O.sensor_env(sc), S_)
+    g = w.env_off[env[hit]] + r.tri[hit]
+    T = w.tris[g].astype(np.float64)
+    a, b, c = T[:, :3], T[:, 3:6], T[:, 6:]
+    nrm = np.cross(b - a, c - a)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    p = r.raw["hit"][hit]
+    dist = np.abs(((p - a) * nrm).sum(1))
+    if dist.max() > 1e-9 * 20:
+        fails.append(f"invariant: hit off plane by {dist.max()}")
+    # segmentation = label of the instance owning the triangle (CSR definition)
+    counts = sc.proto_tri_counts()[sc.inst_mesh]
+    owner = np.repeat(np.arange(sc.n_inst), counts)
+    if np.any(r.seg[hit] != sc.inst_seg[owner[g]]):
+        fails.append("invariant: seg != owner label")
+    # closed room and far beyond its diagonal: no ray escapes
+    far_desc = S.pinhole(96, 54, 87.0, 0.2, 20.0)
+    sc2 = S.Scene(**{**sc.__dict__, "sensors": [far_desc]})
+    r2 = O.render(sc2, w)
+    if np.any(r2.tri < 0):
+        fails.append(f"invariant: {np.sum(r2.tri < 0)} misses inside a closed room")
+    # environment permutation permutes outputs; duplicates agree
+    rp = O.render(S.subset(sc, [1, 0, 1]))
+    n0 = desc.n_rays
+    if not (np.array_equal(rp.tri[:n0], r.tri[n0:]) and np.array_equal(rp.tri[n0:2 * n0], r.tri[:n0])
+            and np.array_equal(rp.tri[2 * n0:], r.tri[n0:])):
+        fails.append("invariant: permutation/duplicate mismatch")
+    # translating the whole scene (instances + sensors) moves nothing relative
+    shift = np.array([8.0, -4.0, 2.0], np.float32)
+    scs = S.Scene(**sc.__dict__)
+    scs.inst_T = sc.inst_T.copy()
+    scs.sensor_T = sc.sensor_T.copy()
+    for k, col in enumerate((3, 7, 11)):
+        scs.inst_T[:, col] += shift[k]
+        scs.sensor_T[:, col] += shift[k]
+    rs = O.render(scs)
+    rob = ((r.cls & O.BORDER_MASK) == 0) & ((rs.cls & O.BORDER_MASK) == 0)
+    if np.any(rs.tri[rob] != r.tri[rob]):
+        fails.append("invariant: translation changed robust winners")
+    hh = rob & hit
+    # vertices move by up to an FP32 rounding (|coord| <= 20 m), which shifts
+    # the hit along the ray by that amount over the grazing cosine
+    tol = 8 * 2.0 ** -24 * 20.0 / r.raw["g"][hh] + 1e-6 * r.t[hh]
+    if np.any(np.abs(rs.t[hh] - r.t[hh]) > tol):
+        fails.append("invariant: translation changed depth")
+    return fails
+
+
+def pin_transform():
+    """World vertices vs an FP64 evaluation of A[:, :3] v + A[:, 3]."""
+    fails = []
+    sc = S.make_cfg2(n_envs=2, W=16, H=9)
+    w = O.world(sc)
+    corners, tri_inst, _ = O.world_corners(sc)
+    A = sc.inst_T.astype(np.float64).reshape(-1, 3, 4)[tri_inst]
+    P = corners.astype(np.float64).reshape(-1, 3, 3)
+    ref = np.einsum("nij,nkj->nki", A[:, :, :3], P) + A[:, None, :, 3]
+    scale = np.einsum("nij,nkj->nki", np.abs(A[:, :, :3]), np.abs(P)) + np.abs(A[:, None, :, 3])
+    err = np.abs(w.tris.reshape(-1, 3, 3) - ref)
+    if np.any(err > 4 * 2.0 ** -24 * scale):
+        fails.append(f"transform: error {np.max(err / scale)} x scale")
+    # pure translations by representable values are exact
+    Tt = sc.inst_T.copy()
+    Tt[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]] = [1, 0, 0, 0, 1, 0, 0, 0, 1]
+    Tt[:, [3, 7, 11]] = np.round(Tt[:, [3, 7, 11]] * 4) / 4
+    wt = O.world(sc, Tt)
+    exp = corners.reshape(-1, 3, 3) + Tt[tri_inst][:, None, [3, 7, 11]]
+    if not np.array_equal(wt.tris.reshape(-1, 3, 3), exp.astype(np.float32)):
+        fails.append("transform: translation not exact")
+    return fails
+
+
+def pin_motion():
+    """Constant-velocity motion: translation after s steps is c0 + v s dt up to
+    FP32 rounding, and exactly c0 at s = 0."""
+    fails = []
+    sc = S.make_cfg4(n_envs=3, max_boxes=20)
+    for s in (0, 1, 50, 99):
+        T = O.moved_poses(sc, s)
+        dyn = sc.inst_dynamic.astype(bool)
+        ref = sc.inst_T[:, [3, 7, 11]].astype(float) + sc.inst_vel.astype(float) * (s * 0.01)
+        err = np.abs(T[:, [3, 7, 11]] - ref)
+        if np.any(err[dyn] > 1e-6 * (np.abs(ref[dyn]) + 1)):
+            fails.append(f"motion: step {s} error {err.max()}")
+        if not np.array_equal(T[~dyn], sc.inst_T[~dyn]):
+            fails.append("motion: static instance moved")
+        if not np.array_equal(T[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]], sc.inst_T[:, [0, 1, 2, 4, 5, 6, 8, 9, 10]]):
+            fails.append("motion: linear part changed")
+    if not np.array_equal(O.moved_poses(sc, 0), sc.inst_T):
+        fails.append("motion: step 0 differs")
+    return fails
+
+
+def pin_rays():
+    """Ray generation: pinhole forward component is 1 in the sensor frame and
+    the pixel grid is symmetric about the optical axis; LiDAR beams are unit
+    length with the stated elevation and azimuth grid."""
+    fails = []
+    W, H = 32, 24
+    cam = S.pinhole(W, H, 87.0)
+    R = S.rot_zyx(0.4, 0.1, -0.2)
+    sc = _ground_scene(cam, S.sensor_pose(R, (1.0, 2.0, 3.0)))
+    o, d = O.sensor_rays(sc, 0)
+    if not np.all(o == np.float32([1.0, 2.0, 3.0])):
+        fails.append("rays: origin is not the pose translation")
+    Rf = sc.sensor_T[0].reshape(3, 4)[:, :3].astype(float)
+    local = d.astype(float) @ Rf  # R^T d (R orthonormal up to FP32 rounding)
+    if np.any(np.abs(local[:, 0] - 1) > 1e-6):
+        fails.append("rays: pinhole forward component != 1")
+    f = (W / 2) / math.tan(float(F32(cam.hfov)) / 2)
+    cols = np.arange(W * H) % W
+    rows = np.arange(W * H) // W
+    if np.any(np.abs(local[:, 1] + (cols + 0.5 - W / 2) / f) > 1e-6) or \
+            np.any(np.abs(local[:, 2] + (rows + 0.5 - H / 2) / f) > 1e-6):
+        fails.append("rays: pinhole pixel grid wrong")
+    lid = S.lidar(16, 8, 90.0)
+    sc = _ground_scene(lid, S.sensor_pose(np.eye(3), (0.0, 0.0, 1.0)))
+    o, d = O.sensor_rays(sc, 0)
+    d = d.astype(float)
+    if np.any(np.abs(np.linalg.norm(d, axis=1) - 1) > 1e-6):
+        fails.append("rays: lidar not unit")
+    ch = np.arange(128) // 16
+    az = np.arange(128) % 16
+    el = np.arcsin(np.clip(d[:, 2], -1, 1))
+    want_el = math.pi / 4 - ch * (math.pi / 2) / 7
+    if np.any(np.abs(el - want_el) > 1e-5):
+        fails.append("rays: lidar elevations wrong")
+    a = np.arctan2(d[:, 1], d[:, 0])
+    want_a = -math.pi + az * (2 * math.pi / 16)
+    da = np.angle(np.exp(1j * (a - want_a)))
+    if np.any(np.abs(da) > 1e-5):
+        fails.append("rays: lidar azimuths wrong")
+    return fails
+
+
+# --------------------------------------------------------------------------
+# 4. classification
+# --------------------------------------------------------------------------
+def pin_classifier():
+    fails = []
+    tri = np.array([0, 0, 2, 2, 0, 2, 0, 2, 2], np.float32)  # in z = 2
+    cases = {
+        "robust": ([0.5, 0.5, 0], [0, 0, 1], O.HIT),
+        "edge": ([1.0, 0.0, 0], [0, 0, 1], O.HIT | O.B_BARY),
+        "nearmiss": ([1.0, -1e-6, 0], [0, 0, 1], O.B_NEARMISS),
+    }
+    for name, (o, d, want) in cases.items():
+        r = O.cast(_world_of([tri]), np.zeros(1, np.int32), np.float32([o]), np.float32([d]), 0.1, 10.0)
+        if r["cls"][0] != want:
+            fails.append(f"classifier {name}: {r['cls'][0]} want {want}")
+    # two parallel triangles 1e-6 apart
+    t2 = tri.copy()
+    t2[[2, 5, 8]] += 2e-6
+    r = O.cast(_world_of([tri, t2]), np.zeros(1, np.int32), np.float32([[0.5, 0.5, 0]]),
+               np.float32([[0, 0, 1]]), 0.1, 10.0)
+    if r["cls"][0] != O.HIT | O.B_GAP or r["tri"][0] != 0:
+        fails.append(f"classifier gap: {r['cls'][0]}")
+    # at the far limit
+    r = O.cast(_world_of([tri]), np.zeros(1, np.int32), np.float32([[0.5, 0.5, 0]]),
+               np.float32([[0, 0, 1]]), 0.1, 2.0000001)
+    if not r["cls"][0] & O.B_RANGE:
+        fails.append("classifier range")
+    # grazing incidence |cos| = 5e-4
+    c = 5e-4
+    d = np.float32([[math.sqrt(1 - c * c), 0, c]])
+    big = np.array([-50, -50, 2, 50, -50, 2, 0, 50, 2], np.float32)
+    r = O.cast(_world_of([big]), np.zeros(1, np.int32), np.float32([[0, 0, 1.99]]), d, 0.1, 100.0)
+    if not r["cls"][0] & O.B_GRAZE:
+        fails.append(f"classifier graze: {r['cls'][0]}")
+    return fails
+
+
+ALL_PINS = [pin_exact, pin_duplicate_tie, pin_ray_plane, pin_boxes, pin_tessellated,
+            pin_invariants, pin_transform, pin_motion, pin_rays, pin_classifier]
