@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched ray-cast renderer on one MI355X.
+
+One step = one pass of the rendering hot path over every environment of the
+workload: sensor poses uploaded, every instance transformed, one BVH built
+per environment, every ray generated, traversed and written (depth/range +
+segmentation).  Default workload: 4096 environments x one 64-channel x
+512-azimuth LiDAR in a 60-tree forest (4802 triangles per environment).
+
+Prints ONE JSON line: Mrays/s (whole job), env-steps/s, the render kernel's
+roofline position, the plain per-environment path on the same GPU, and the
+CPU oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s & env-steps/s (4096-env cam+LiDAR) vs plain; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    1: "1 env, 64x48 pinhole camera, ground + 8 boxes (98 tris)",
+    2: "1024 envs x 480x270 pinhole camera, room + 40 random box/cylinder/sphere obstacles (~5.3k tris/env)",
+    3: "4096 envs x 64ch x 512az rotating LiDAR (360 x 90 deg, 0.5-30 m), 60-tree forest (4802 tris/env)",
+    4: "2048 envs, 5-200 boxes (30% moving), mixed 480x270 / 240x135 cameras and 32x512 LiDAR",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def byte_model(stats, rays):
+    """Algorithmic bytes per ray: 32 B per ray-box test, 40 B per ray-triangle
+    test (36 B vertices + 4 B id), 8 B of output (depth + label)."""
+    box, tri = stats[0], stats[1]
+    return (32.0 * box + 40.0 * tri) / rays + 8.0
+
+
+def cpu_baseline(cfg, seconds):
+    """The oracle on a bounded sample of the same workload, all host cores."""
+    import numpy as np  # noqa: F401
+    from oracle import oracle as O
+    from paper_2503_01471_amd import scenes as S
+    cores = len(os.sched_getaffinity(0))
+    n_env = 1
+    sc = S.make(cfg, env_ids=[0]) if cfg != 1 else S.make_cfg1()
+    t0 = time.perf_counter()
+    O.render(sc, nthreads=cores)
+    dt = time.perf_counter() - t0
+    if cfg != 1:
+        n_env = max(1, min(64, int(seconds / max(dt, 1e-3))))
+        sc = S.make(cfg, env_ids=list(range(n_env)))
+        t0 = time.perf_counter()
+        O.render(sc, nthreads=cores)
+        dt = time.perf_counter() - t0
+    rays = sc.total_rays()
+    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_env} env(s) of cfg{cfg}, all {rays} rays, brute-force FP64, {dt:.1f} s",
+            "env_steps_per_s": n_env / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cfg", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--mode", default="batched", choices=["plain", "flat", "batched"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); environments shard across GPUs "
+              "with no exchange, so a multi-GPU run is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2503_01471_amd import rc, scenes
+    from paper_2503_01471_amd.renderer import Renderer
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    mode = {"plain": rc.RC_RENDER_PLAIN, "flat": rc.RC_RENDER_FLAT, "batched": rc.RC_RENDER_BATCHED}[args.mode]
+    log(f"generating cfg{args.cfg}")
+    scene = scenes.make(args.cfg)
+    n_envs = scene.n_envs
+    log(f"loading {n_envs} envs, {int(scene.env_tri_counts().sum())} tris, {scene.total_rays()} rays")
+    R = Renderer(scene, build=True)
+    out = R.alloc(depth=True, seg=True)
+    rays = R.total_rays
+    ctx = R.ctx
+    torch.cuda.synchronize()
+
+    def step():
+        rc.rc_set_sensor_poses(ctx, R.sensor_T)
+        rc.rc_build(ctx)
+        rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays)
+
+    def timed(fn, k):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(k):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / k
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    ms = timed(step, args.steps)
+    log(f"step {ms:.3f} ms")
+    # components on the same stream
+    ms_render = timed(lambda: rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays), args.steps)
+    ms_build = timed(lambda: rc.rc_build(ctx), max(2, args.steps // 2))
+    log(f"render {ms_render:.3f} ms, build {ms_build:.3f} ms")
+    plain = None
+    if not args.no_plain and mode != rc.RC_RENDER_PLAIN:
+        ms_plain = timed(lambda: rc.rc_render(ctx, out["depth"], out["seg"], None, None, rc.RC_RENDER_PLAIN, None,
+                                              rays), max(2, args.steps // 2))
+        plain = {"ms_render": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_vs_plain": ms_plain / ms_render}
+        log(f"plain render {ms_plain:.3f} ms")
+    stats = R.stats()
+    b_ray = byte_model(stats, rays)
+    achieved = b_ray * rays / (ms_render * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": rays / ms / 1e3,
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"cfg{args.cfg}: {WORKLOADS[args.cfg]}", "envs": n_envs, "rays_per_step": rays,
+                   "mode": args.mode, "outputs": "depth+seg",
+                   "step": "sensor poses + transform + SAH build + render"},
+        "env_steps_per_s": n_envs / (ms * 1e-3),
+        "render_ms": ms_render,
+        "render_Mrays_s": rays / ms_render / 1e3,
+        "build_ms": ms_build,
+        "plain": plain,
+        "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
+                      "fp64_per_ray": stats[2] / rays},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_ray": b_ray,
+                     "kernel": "k_render_batched" if mode == rc.RC_RENDER_BATCHED else "k_render_flat",
+                     "byte_model": "traversal counters of this BVH"},
+        "cpu_baseline": None,
+    }
+    R.close()
+    del out
+    torch.cuda.synchronize()
+    if not args.no_cpu:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(args.cfg, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

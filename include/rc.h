@@ -1,0 +1,215 @@
+/*
+ * rc.h -- C ABI of the MI355X batched ray-cast renderer.
+ *
+ * The library renders depth/range, segmentation, triangle-id and hit-point
+ * buffers for many independent environments at once, each with its own
+ * triangle meshes and its own sensors (pinhole cameras and rotating LiDARs).
+ *
+ * Problem statement it implements (paper, Sec. III-D "Exteroceptive
+ * Sensors"): environment i holds a base mesh made of n_i sub-meshes, one per
+ * object; each sub-mesh has its own transform at time t; the transformed mesh
+ * gets a bounding volume hierarchy, and one ray is cast per pixel or beam; the
+ * sensor-to-hit distance is reported as range (LiDAR, time of flight) and the
+ * distance from the image plane as depth (cameras); segmentation, face index
+ * and point outputs come from the same hit.
+ *
+ * Conventions (all calls):
+ *   - Every call returns an rc_status; no exception crosses the ABI.  Argument
+ *     errors are detected before any work is queued.  rc_last_error() gives a
+ *     human-readable detail for the calling thread.
+ *   - Host arrays passed in are copied before the call returns.
+ *   - Device pointers passed in must stay valid until the work queued on the
+ *     given stream has completed.  Output buffers are always caller-owned; the
+ *     library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the context's stream).
+ *   - Units are metres and radians; world z is up; the sensor frame is
+ *     x forward, y left, z up; images have u to the right and v downward with
+ *     row 0 at the top.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef RC_H
+#define RC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rc_status;
+#define RC_OK 0
+#define RC_E_INVALID (-1) /* bad argument */
+#define RC_E_OOM (-2)     /* device allocation failed or memory budget exceeded */
+#define RC_E_HIP (-3)     /* HIP runtime error */
+#define RC_E_STATE (-4)   /* call out of order (e.g. render before build) */
+#define RC_E_BUSY (-5)    /* resource in use */
+#define RC_E_DEVICE (-6)  /* device-side error flag raised */
+
+typedef struct rc_context rc_context;
+
+/* Status code as text (static string). */
+const char *rc_status_string(rc_status s);
+/* Detail of the last failing call on this thread (owned by the library). */
+const char *rc_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Context.                                                                  */
+/* device: HIP device ordinal; stream: default hipStream_t for the context's */
+/* work (NULL = the null stream); hbm_budget: cap in bytes on library-owned  */
+/* device memory (0 = no cap).  Allocation above the cap fails with          */
+/* RC_E_OOM and leaves the previous state intact.                            */
+/* ------------------------------------------------------------------------ */
+rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context **out);
+rc_status rc_destroy(rc_context *ctx);
+/* Library-owned device bytes currently allocated. */
+rc_status rc_memory_used(const rc_context *ctx, size_t *bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Prototype meshes (the sub-meshes M_j of Sec. III-D, shared by reference). */
+/* xyz: host float[n_verts][3]; tri3: host int32[n_tris][3] vertex indices.  */
+/* Copied; ids are dense from 0 in call order.  Must precede rc_scene_load.  */
+/* ------------------------------------------------------------------------ */
+rc_status rc_mesh_add(rc_context *ctx, const float *xyz, int32_t n_verts, const int32_t *tri3,
+                      int32_t n_tris, int32_t *mesh_id);
+
+/* ------------------------------------------------------------------------ */
+/* Scene: instances of prototype meshes per environment (Sec. III-D base     */
+/* mesh of environment i = its n_i sub-meshes).  CSR over environments:      */
+/*   inst_offsets: host int64[n_envs+1], non-decreasing, inst_offsets[0]=0;  */
+/*   inst_mesh:    host int32[n_inst] prototype id;                          */
+/*   inst_seg:     host int32[n_inst] segmentation label reported on hits;   */
+/*   inst_dynamic: host uint8[n_inst] (nullable = all static): instances     */
+/*                 re-transformed by rc_refit.                               */
+/* Environment-local triangle numbering: instances in CSR order, then the    */
+/* prototype's triangle order.  Replaces any previous scene atomically: on   */
+/* error the previous scene (and its BVH) is untouched.  Sensors must be     */
+/* attached again after a new scene.                                         */
+/* ------------------------------------------------------------------------ */
+rc_status rc_scene_load(rc_context *ctx, int32_t n_envs, const int64_t *inst_offsets,
+                        const int32_t *inst_mesh, const int32_t *inst_seg, const uint8_t *inst_dynamic);
+
+/* ------------------------------------------------------------------------ */
+/* Sensor models.                                                            */
+/*  RC_PINHOLE: width x height pixels, horizontal field of view hfov, square */
+/*    pixels (focal length (W/2)/tan(hfov/2)), pixel centres at +1/2; the    */
+/*    local direction has forward component exactly 1, so t is depth.       */
+/*  RC_LIDAR: width azimuths x height channels; channel c has elevation      */
+/*    vmax - c (vmax-vmin)/(H-1) (channel 0 on top), azimuth a is            */
+/*    hmin + a (hmax-hmin)/W counter-clockwise from +x; unit directions, so  */
+/*    t is range.  The scan is instantaneous (one pose per scan).            */
+/*  RC_TABLE: width*height local unit directions in dir_table (host          */
+/*    float[W*H][3], copied): user-defined projection models.                */
+/* Rays are indexed r = row*width + col (pinhole row = image row, LiDAR row  */
+/* = channel).  near_/far_ bound the ray parameter t: a triangle counts only */
+/* if near_ <= t <= far_ (0 <= near_ <= far_).                               */
+/* ------------------------------------------------------------------------ */
+#define RC_PINHOLE 0
+#define RC_LIDAR 1
+#define RC_TABLE 2
+typedef struct {
+    int32_t kind;
+    int32_t width, height;
+    float hfov;
+    float vmin, vmax, hmin, hmax;
+    float near_, far_;
+    const float *dir_table;
+} rc_sensor_desc;
+
+rc_status rc_sensor_add(rc_context *ctx, const rc_sensor_desc *desc, int32_t *sensor_id);
+
+/* Sensor instances per environment, CSR: sens_offsets host int64[n_envs+1], */
+/* sensor_ids host int32[n_sensor_inst].  Requires a loaded scene.           */
+rc_status rc_sensors_attach(rc_context *ctx, const int64_t *sens_offsets, const int32_t *sensor_ids);
+
+/* Output layout: ray-major per sensor instance; sensor instance s owns      */
+/* output rays [ray_offsets[s], ray_offsets[s+1]).  ray_offsets: host        */
+/* int64[n_sensor_inst+1] (nullable); total_rays: host int64 (nullable).     */
+rc_status rc_ray_layout(const rc_context *ctx, int64_t *ray_offsets, int64_t *total_rays);
+
+/* Environment triangle offsets: host int64[n_envs+1]; environment e owns    */
+/* global triangles [off[e], off[e+1]).                                      */
+rc_status rc_env_tri_offsets(const rc_context *ctx, int64_t *off);
+
+/* ------------------------------------------------------------------------ */
+/* Poses (Sec. III-D transforms T_{j,t} and sensor poses).  Caller-owned     */
+/* DEVICE pointers, FP32 row-major 3x4 [R | p] per instance / per sensor     */
+/* instance, copied on `stream`.  world vertex = R v + p (per coordinate     */
+/* fma(R0,x, fma(R1,y, fma(R2,z, p)))); ray origin = p, world direction      */
+/* component i = fma(Ri0,dx, fma(Ri1,dy, Ri2*dz)).                           */
+/* ------------------------------------------------------------------------ */
+rc_status rc_set_instance_poses(rc_context *ctx, const float *d_inst_T, void *stream);
+rc_status rc_set_sensor_poses(rc_context *ctx, const float *d_sensor_T, void *stream);
+
+/* Constant-velocity motion of dynamic instances: translation at `step` is   */
+/* fma(v, float(step)*dt, p0) with p0 the translation of the last            */
+/* rc_set_instance_poses; d_vel: caller device float[n_inst][3].             */
+rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, float dt, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Acceleration structure (Sec. III-D: a BVH over the transformed mesh of    */
+/* each environment).  rc_build transforms every instance and builds one     */
+/* BVH per environment (builder RC_BUILD_SAH: binned surface-area           */
+/* heuristic, one wavefront per environment).  rc_refit re-transforms the    */
+/* dynamic instances and recomputes the bounds bottom-up on the fixed        */
+/* topology.  Both are asynchronous on `stream`.                             */
+/* ------------------------------------------------------------------------ */
+#define RC_BUILD_SAH 0
+rc_status rc_build(rc_context *ctx, int32_t builder, void *stream);
+rc_status rc_refit(rc_context *ctx, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Render (Sec. III-D: one ray per pixel or beam, nearest hit over the       */
+/* environment's transformed mesh).  Outputs are caller-owned device         */
+/* buffers in the rc_ray_layout order, each nullable (skipped):              */
+/*   depth  float[total]: t of the nearest hit (depth for pinholes, range    */
+/*          for LiDARs), -1.0f on a miss;                                    */
+/*   seg    int32[total]: label of the instance owning the hit triangle, -1; */
+/*   tri    int32[total]: environment-local triangle id, -1;                 */
+/*   hit_xyz float[total][3]: world hit point o + t d, NaN on a miss.        */
+/* The nearest hit is the smallest t in [near_, far_] over every triangle of */
+/* the ray's environment (two-sided; equal t resolved by the lower triangle  */
+/* id).  Every mode computes bit-identical outputs:                          */
+/*   RC_RENDER_PLAIN   one launch per sensor instance (per-env path);        */
+/*   RC_RENDER_FLAT    one launch over every ray tile;                       */
+/*   RC_RENDER_BATCHED one persistent launch popping tiles from a device     */
+/*                     work queue (largest estimated cost first);            */
+/*   RC_RENDER_BRUTE   no BVH: every triangle tested (reference path).       */
+/* ------------------------------------------------------------------------ */
+#define RC_RENDER_PLAIN 0
+#define RC_RENDER_FLAT 1
+#define RC_RENDER_BATCHED 2
+#define RC_RENDER_BRUTE 3
+typedef struct {
+    float *depth;
+    int32_t *seg;
+    int32_t *tri;
+    float *hit_xyz;
+} rc_outputs;
+
+rc_status rc_render(rc_context *ctx, const rc_outputs *out, int32_t mode, void *stream);
+
+/* Traversal statistics of one FLAT render (same arithmetic, counters added): */
+/* counters host int64[4] = box tests, triangle tests, FP64 re-evaluations,  */
+/* rays.  Synchronous.                                                       */
+rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
+
+/* ------------------------------------------------------------------------ */
+/* Inspection (synchronous, host outputs; for validation).                   */
+/* ------------------------------------------------------------------------ */
+/* World triangles in global original order: host float[total_tris][9].      */
+rc_status rc_debug_world(rc_context *ctx, float *tris9);
+/* World rays of sensor instance s for the given ray indices (host arrays).  */
+rc_status rc_debug_rays(rc_context *ctx, int32_t s, int64_t n, const int64_t *ray_idx, float *o, float *d);
+/* BVH of environment e: n_nodes; per node child boxes float[n][2][6]        */
+/* (lo xyz, hi xyz), child refs int32[n][2] (>= 0 internal node, < 0 leaf    */
+/* ~(first<<3 | (count-1)) over leaf positions), parent int32[n]; leaf_ids   */
+/* int32[n_tris] env-local triangle id at each leaf position; root ref.      */
+/* Buffers must hold n_tris entries (n_nodes <= n_tris).                     */
+rc_status rc_debug_bvh(rc_context *ctx, int32_t e, int32_t *n_nodes, float *boxes, int32_t *children,
+                       int32_t *parent, int32_t *leaf_ids, int32_t *root);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RC_H */

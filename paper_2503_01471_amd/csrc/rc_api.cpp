@@ -1,0 +1,743 @@
+// rc_api.cpp -- host runtime behind the C ABI in include/rc.h.
+//
+// Owns the device copies of meshes, scenes, BVHs and sensors of one context,
+// enforces the memory budget, validates arguments before queueing work, and
+// dispatches the kernels of rc_build.hip / rc_render.hip on HIP streams.
+#include "rc.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "rc_common.hpp"
+
+using namespace rc;
+
+namespace {
+
+thread_local std::string g_err;
+
+rc_status fail(rc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+rc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(RC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define RC_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess)                         \
+            return hip_fail(e_, #call);               \
+    } while (0)
+
+// Budgeted device allocation owned by a context.
+struct Pool;
+
+struct DBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    Pool *pool = nullptr;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf();
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct Pool {
+    size_t budget = 0;
+    size_t used = 0;
+    rc_status alloc(DBuf &b, size_t bytes)
+    {
+        if (bytes == 0)
+            bytes = 16;
+        if (budget && used + bytes > budget)
+            return fail(RC_E_OOM, "memory budget exceeded: %zu used + %zu requested > %zu", used, bytes, budget);
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RC_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        b.p = p;
+        b.n = bytes;
+        b.pool = this;
+        used += bytes;
+        return RC_OK;
+    }
+};
+
+DBuf::~DBuf()
+{
+    if (p) {
+        (void)hipFree(p);
+        if (pool)
+            pool->used -= n;
+    }
+}
+
+struct Mesh {
+    int64_t vert_off, n_verts, tri_off, n_tris;
+};
+
+struct Scene {
+    int32_t n_envs = 0;
+    int64_t n_inst = 0, n_tris = 0, n_dyn = 0;
+    std::vector<int64_t> env_tri_off;  // host copy
+    std::vector<int64_t> inst_offsets;
+    DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
+    DBuf world, box_lo, box_hi, cen, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, refit_cnt;
+    bool poses_set = false;
+    bool built = false;
+
+    BuildView view() const
+    {
+        BuildView v;
+        v.n_envs = n_envs;
+        v.n_tris = n_tris;
+        v.env_tri_off = d_env_tri_off.as<int64_t>();
+        v.tri_env = tri_env.as<int32_t>();
+        v.tri_src = tri_src.as<int2>();
+        v.proto_xyz = proto_xyz.as<float>();
+        v.proto_tri = proto_tri.as<int32_t>();
+        v.inst_T = inst_T.as<float>();
+        v.world = world.as<float>();
+        v.box_lo = box_lo.as<float4>();
+        v.box_hi = box_hi.as<float4>();
+        v.cen = cen.as<float4>();
+        v.prim = prim.as<int32_t>();
+        v.tmp = tmp.as<int32_t>();
+        v.nodes = nodes.as<Node>();
+        v.recs = recs.as<TriRec>();
+        v.pos_of = pos_of.as<int32_t>();
+        v.env_root = env_root.as<int32_t>();
+        v.env_nodes = env_nodes.as<int32_t>();
+        v.refit_cnt = refit_cnt.as<int32_t>();
+        return v;
+    }
+    SceneView sview() const
+    {
+        SceneView s;
+        s.env_tri_off = d_env_tri_off.as<int64_t>();
+        s.env_root = env_root.as<int32_t>();
+        s.nodes = nodes.as<Node>();
+        s.recs = recs.as<TriRec>();
+        s.tri_seg = tri_seg.as<int32_t>();
+        s.world = world.as<float>();
+        s.n_envs = n_envs;
+        return s;
+    }
+};
+
+struct ModelHost {
+    SensorModel m;
+    std::vector<float> table;  // lidar / table directions (FP32)
+};
+
+struct Sensors {
+    int64_t n_si = 0, n_items = 0, total_rays = 0;
+    std::vector<int64_t> ray_off, item_off;
+    DBuf models, tables, si_env, si_model, d_ray_off, pose, items, lpt_items, head, counters;
+    bool poses_set = false;
+
+    SensorView view() const
+    {
+        SensorView v;
+        v.models = models.as<SensorModel>();
+        v.tables = tables.as<float>();
+        v.si_env = si_env.as<int32_t>();
+        v.si_model = si_model.as<int32_t>();
+        v.ray_off = d_ray_off.as<int64_t>();
+        v.pose = pose.as<float>();
+        v.items = items.as<int2>();
+        return v;
+    }
+};
+
+}  // namespace
+
+struct rc_context {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    Pool pool;
+    std::vector<float> mesh_xyz;
+    std::vector<int32_t> mesh_tri;  // global vertex indices
+    std::vector<Mesh> meshes;
+    std::vector<ModelHost> models;
+    std::unique_ptr<Scene> scene;
+    std::unique_ptr<Sensors> sensors;
+    int batched_grid = 0;
+};
+
+namespace {
+
+hipStream_t pick(const rc_context *c, void *stream) { return stream ? (hipStream_t)stream : c->stream; }
+
+template <class T>
+rc_status upload(rc_context *c, DBuf &b, const T *src, size_t count, hipStream_t st)
+{
+    rc_status s = c->pool.alloc(b, count * sizeof(T));
+    if (s != RC_OK)
+        return s;
+    if (count)
+        RC_HIP(hipMemcpyAsync(b.p, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+    return RC_OK;
+}
+
+rc_status set_device(const rc_context *c)
+{
+    RC_HIP(hipSetDevice(c->device));
+    return RC_OK;
+}
+
+#define RC_CHECK(cond, ...)                            \
+    do {                                               \
+        if (!(cond))                                   \
+            return fail(RC_E_INVALID, __VA_ARGS__);    \
+    } while (0)
+#define RC_TRY(expr)                                   \
+    do {                                               \
+        rc_status s_ = (expr);                         \
+        if (s_ != RC_OK)                               \
+            return s_;                                 \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *rc_status_string(rc_status s)
+{
+    switch (s) {
+    case RC_OK: return "ok";
+    case RC_E_INVALID: return "invalid argument";
+    case RC_E_OOM: return "out of memory";
+    case RC_E_HIP: return "HIP error";
+    case RC_E_STATE: return "invalid state";
+    case RC_E_BUSY: return "busy";
+    case RC_E_DEVICE: return "device error";
+    default: return "unknown status";
+    }
+}
+
+const char *rc_last_error(void) { return g_err.c_str(); }
+
+rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context **out)
+{
+    RC_CHECK(out, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    RC_HIP(hipGetDeviceCount(&n));
+    RC_CHECK(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
+    RC_HIP(hipSetDevice(device));
+    auto *c = new rc_context;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    c->pool.budget = hbm_budget;
+    c->batched_grid = batched_grid_size(device);
+    *out = c;
+    return RC_OK;
+}
+
+rc_status rc_destroy(rc_context *c)
+{
+    if (!c)
+        return RC_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    c->sensors.reset();
+    c->scene.reset();
+    delete c;
+    return RC_OK;
+}
+
+rc_status rc_memory_used(const rc_context *c, size_t *bytes)
+{
+    RC_CHECK(c && bytes, "NULL argument");
+    *bytes = c->pool.used;
+    return RC_OK;
+}
+
+rc_status rc_mesh_add(rc_context *c, const float *xyz, int32_t n_verts, const int32_t *tri3, int32_t n_tris,
+                      int32_t *mesh_id)
+{
+    RC_CHECK(c && mesh_id, "NULL argument");
+    RC_CHECK(n_verts >= 0 && n_tris >= 0, "negative sizes");
+    RC_CHECK((n_verts == 0 || xyz) && (n_tris == 0 || tri3), "NULL mesh arrays");
+    for (int64_t i = 0; i < 3 * (int64_t)n_verts; ++i)
+        RC_CHECK(isfinite(xyz[i]), "vertex coordinate %lld is not finite", (long long)i);
+    for (int64_t i = 0; i < 3 * (int64_t)n_tris; ++i)
+        RC_CHECK(tri3[i] >= 0 && tri3[i] < n_verts, "triangle index %lld out of range", (long long)i);
+    Mesh m{(int64_t)c->mesh_xyz.size() / 3, n_verts, (int64_t)c->mesh_tri.size() / 3, n_tris};
+    c->mesh_xyz.insert(c->mesh_xyz.end(), xyz, xyz + 3 * (int64_t)n_verts);
+    for (int64_t i = 0; i < 3 * (int64_t)n_tris; ++i)
+        c->mesh_tri.push_back((int32_t)(tri3[i] + m.vert_off));
+    *mesh_id = (int32_t)c->meshes.size();
+    c->meshes.push_back(m);
+    return RC_OK;
+}
+
+rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offsets, const int32_t *inst_mesh,
+                        const int32_t *inst_seg, const uint8_t *inst_dynamic)
+{
+    RC_CHECK(c, "NULL context");
+    RC_CHECK(n_envs >= 0, "n_envs < 0");
+    RC_CHECK(inst_offsets, "inst_offsets is NULL");
+    RC_CHECK(inst_offsets[0] == 0, "inst_offsets[0] != 0");
+    for (int32_t e = 0; e < n_envs; ++e)
+        RC_CHECK(inst_offsets[e + 1] >= inst_offsets[e], "inst_offsets not non-decreasing at %d", e);
+    const int64_t n_inst = inst_offsets[n_envs];
+    RC_CHECK(n_inst == 0 || (inst_mesh && inst_seg), "NULL instance arrays");
+    const int64_t n_meshes = (int64_t)c->meshes.size();
+    for (int64_t i = 0; i < n_inst; ++i)
+        RC_CHECK(inst_mesh[i] >= 0 && inst_mesh[i] < n_meshes, "inst_mesh[%lld] = %d is not a mesh id",
+                 (long long)i, inst_mesh[i]);
+    RC_TRY(set_device(c));
+    hipStream_t st = c->stream;
+
+    auto sc = std::make_unique<Scene>();
+    sc->n_envs = n_envs;
+    sc->n_inst = n_inst;
+    sc->inst_offsets.assign(inst_offsets, inst_offsets + n_envs + 1);
+    sc->env_tri_off.assign(n_envs + 1, 0);
+    for (int32_t e = 0; e < n_envs; ++e) {
+        int64_t t = 0;
+        for (int64_t i = inst_offsets[e]; i < inst_offsets[e + 1]; ++i)
+            t += c->meshes[inst_mesh[i]].n_tris;
+        RC_CHECK(t < (1 << 27), "environment %d has %lld triangles (limit 2^27)", e, (long long)t);
+        sc->env_tri_off[e + 1] = sc->env_tri_off[e] + t;
+    }
+    const int64_t N = sc->env_tri_off[n_envs];
+    sc->n_tris = N;
+    std::vector<int32_t> tri_env(N), tri_seg(N), dyn;
+    std::vector<int2> tri_src(N);
+    std::vector<uint8_t> dynf(n_inst, 0);
+    int64_t g = 0;
+    for (int32_t e = 0; e < n_envs; ++e) {
+        for (int64_t i = inst_offsets[e]; i < inst_offsets[e + 1]; ++i) {
+            const Mesh &m = c->meshes[inst_mesh[i]];
+            const bool d = inst_dynamic && inst_dynamic[i];
+            dynf[i] = d;
+            for (int64_t k = 0; k < m.n_tris; ++k, ++g) {
+                tri_env[g] = e;
+                tri_seg[g] = inst_seg[i];
+                tri_src[g] = make_int2((int)i, (int)(m.tri_off + k));
+                if (d)
+                    dyn.push_back((int32_t)g);
+            }
+        }
+    }
+    RC_CHECK(N < INT32_MAX, "too many triangles");
+    sc->n_dyn = (int64_t)dyn.size();
+    RC_TRY(upload(c, sc->proto_xyz, c->mesh_xyz.data(), c->mesh_xyz.size(), st));
+    RC_TRY(upload(c, sc->proto_tri, c->mesh_tri.data(), c->mesh_tri.size(), st));
+    RC_TRY(upload(c, sc->d_env_tri_off, sc->env_tri_off.data(), sc->env_tri_off.size(), st));
+    RC_TRY(upload(c, sc->tri_env, tri_env.data(), N, st));
+    RC_TRY(upload(c, sc->tri_seg, tri_seg.data(), N, st));
+    RC_TRY(upload(c, sc->tri_src, tri_src.data(), N, st));
+    RC_TRY(upload(c, sc->inst_dyn, dynf.data(), n_inst, st));
+    RC_TRY(upload(c, sc->dyn_tris, dyn.data(), dyn.size(), st));
+    RC_TRY(c->pool.alloc(sc->inst_T, 48 * n_inst));
+    RC_TRY(c->pool.alloc(sc->inst_T0, 48 * n_inst));
+    RC_TRY(c->pool.alloc(sc->world, 36 * N));
+    RC_TRY(c->pool.alloc(sc->box_lo, 16 * N));
+    RC_TRY(c->pool.alloc(sc->box_hi, 16 * N));
+    RC_TRY(c->pool.alloc(sc->cen, 16 * N));
+    RC_TRY(c->pool.alloc(sc->prim, 4 * N));
+    RC_TRY(c->pool.alloc(sc->tmp, 4 * N));
+    RC_TRY(c->pool.alloc(sc->nodes, sizeof(Node) * N));
+    RC_TRY(c->pool.alloc(sc->recs, sizeof(TriRec) * N));
+    RC_TRY(c->pool.alloc(sc->pos_of, 4 * N));
+    RC_TRY(c->pool.alloc(sc->env_root, 4 * (size_t)n_envs));
+    RC_TRY(c->pool.alloc(sc->env_nodes, 4 * (size_t)n_envs));
+    RC_TRY(c->pool.alloc(sc->refit_cnt, 4 * N));
+    RC_HIP(hipMemsetAsync(sc->refit_cnt.p, 0, 4 * N, st));
+    RC_HIP(hipStreamSynchronize(st));
+    c->sensors.reset();
+    c->scene = std::move(sc);
+    return RC_OK;
+}
+
+rc_status rc_sensor_add(rc_context *c, const rc_sensor_desc *d, int32_t *sensor_id)
+{
+    RC_CHECK(c && d && sensor_id, "NULL argument");
+    RC_CHECK(d->kind == RC_PINHOLE || d->kind == RC_LIDAR || d->kind == RC_TABLE, "unknown sensor kind %d", d->kind);
+    RC_CHECK(d->width > 0 && d->height > 0, "sensor size must be positive");
+    RC_CHECK((int64_t)d->width * d->height < (1ll << 31), "sensor too large");
+    RC_CHECK(isfinite(d->near_) && isfinite(d->far_) && d->near_ >= 0.f && d->near_ <= d->far_,
+             "need 0 <= near <= far (finite)");
+    ModelHost h{};
+    SensorModel &m = h.m;
+    m.kind = d->kind;
+    m.W = d->width;
+    m.H = d->height;
+    m.tiles_x = (d->width + 7) / 8;
+    m.tiles = m.tiles_x * ((d->height + 7) / 8);
+    m.hw = (float)d->width * 0.5f;
+    m.hh = (float)d->height * 0.5f;
+    m.tn = d->near_;
+    m.tf = d->far_;
+    m.s = 0.f;
+    m.table_off = 0;
+    if (d->kind == RC_PINHOLE) {
+        RC_CHECK(d->hfov > 0.f && d->hfov < 3.14159f, "pinhole hfov must be in (0, pi)");
+        m.s = (float)(tan((double)d->hfov * 0.5) / ((double)d->width * 0.5));
+    } else if (d->kind == RC_LIDAR) {
+        RC_CHECK(isfinite(d->vmin) && isfinite(d->vmax) && isfinite(d->hmin) && isfinite(d->hmax),
+                 "lidar angles must be finite");
+        const int W = d->width, H = d->height;
+        h.table.resize(3 * (size_t)W * H);
+        for (int ch = 0; ch < H; ++ch) {
+            const double el = H > 1 ? (double)d->vmax - (double)ch * ((double)d->vmax - (double)d->vmin) / (double)(H - 1)
+                                    : (double)d->vmax;
+            const double ce = cos(el), se = sin(el);
+            for (int a = 0; a < W; ++a) {
+                const double az = (double)d->hmin + (double)a * ((double)d->hmax - (double)d->hmin) / (double)W;
+                float *t = &h.table[3 * ((size_t)ch * W + a)];
+                t[0] = (float)(ce * cos(az));
+                t[1] = (float)(ce * sin(az));
+                t[2] = (float)se;
+            }
+        }
+    } else {
+        RC_CHECK(d->dir_table, "table sensor needs dir_table");
+        const size_t n = 3 * (size_t)d->width * d->height;
+        for (size_t i = 0; i < n; ++i)
+            RC_CHECK(isfinite(d->dir_table[i]), "dir_table entry %zu not finite", i);
+        h.table.assign(d->dir_table, d->dir_table + n);
+    }
+    *sensor_id = (int32_t)c->models.size();
+    c->models.push_back(std::move(h));
+    return RC_OK;
+}
+
+rc_status rc_sensors_attach(rc_context *c, const int64_t *sens_offsets, const int32_t *sensor_ids)
+{
+    RC_CHECK(c && sens_offsets, "NULL argument");
+    if (!c->scene)
+        return fail(RC_E_STATE, "rc_sensors_attach before rc_scene_load");
+    const Scene &sc = *c->scene;
+    const int32_t E = sc.n_envs;
+    RC_CHECK(sens_offsets[0] == 0, "sens_offsets[0] != 0");
+    for (int32_t e = 0; e < E; ++e)
+        RC_CHECK(sens_offsets[e + 1] >= sens_offsets[e], "sens_offsets not non-decreasing at %d", e);
+    const int64_t S = sens_offsets[E];
+    RC_CHECK(S == 0 || sensor_ids, "sensor_ids is NULL");
+    for (int64_t s = 0; s < S; ++s)
+        RC_CHECK(sensor_ids[s] >= 0 && sensor_ids[s] < (int32_t)c->models.size(), "sensor_ids[%lld] invalid",
+                 (long long)s);
+    RC_TRY(set_device(c));
+    hipStream_t st = c->stream;
+    auto se = std::make_unique<Sensors>();
+    se->n_si = S;
+    // models + concatenated tables
+    std::vector<SensorModel> models;
+    std::vector<float> tables;
+    for (const ModelHost &h : c->models) {
+        SensorModel m = h.m;
+        m.table_off = (int64_t)tables.size() / 3;
+        tables.insert(tables.end(), h.table.begin(), h.table.end());
+        models.push_back(m);
+    }
+    std::vector<int32_t> si_env(S), si_model(S);
+    se->ray_off.assign(S + 1, 0);
+    se->item_off.assign(S + 1, 0);
+    for (int32_t e = 0; e < E; ++e)
+        for (int64_t s = sens_offsets[e]; s < sens_offsets[e + 1]; ++s)
+            si_env[s] = e;
+    for (int64_t s = 0; s < S; ++s) {
+        si_model[s] = sensor_ids[s];
+        const SensorModel &m = models[sensor_ids[s]];
+        se->ray_off[s + 1] = se->ray_off[s] + (int64_t)m.W * m.H;
+        se->item_off[s + 1] = se->item_off[s] + m.tiles;
+    }
+    se->total_rays = se->ray_off[S];
+    se->n_items = se->item_off[S];
+    RC_CHECK(se->n_items < INT32_MAX, "too many tiles");
+    std::vector<int2> items(se->n_items);
+    for (int64_t s = 0; s < S; ++s)
+        for (int64_t k = se->item_off[s]; k < se->item_off[s + 1]; ++k)
+            items[k] = make_int2((int)s, (int)(k - se->item_off[s]));
+    // queue order for the persistent form: sensor instances by estimated cost
+    // (rays x log2 of the environment's triangle count), largest first; the
+    // tiles of one instance stay together
+    std::vector<int64_t> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(S);
+    for (int64_t s = 0; s < S; ++s) {
+        const int e = si_env[s];
+        const double ntri = (double)(sc.env_tri_off[e + 1] - sc.env_tri_off[e]);
+        cost[s] = (double)(se->ray_off[s + 1] - se->ray_off[s]) * log2(ntri + 2.0);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    std::vector<int2> lpt;
+    lpt.reserve(se->n_items);
+    for (int64_t s : order)
+        for (int64_t k = se->item_off[s]; k < se->item_off[s + 1]; ++k)
+            lpt.push_back(items[k]);
+    RC_TRY(upload(c, se->models, models.data(), models.size(), st));
+    RC_TRY(upload(c, se->tables, tables.data(), tables.size(), st));
+    RC_TRY(upload(c, se->si_env, si_env.data(), S, st));
+    RC_TRY(upload(c, se->si_model, si_model.data(), S, st));
+    RC_TRY(upload(c, se->d_ray_off, se->ray_off.data(), S + 1, st));
+    RC_TRY(upload(c, se->items, items.data(), items.size(), st));
+    RC_TRY(upload(c, se->lpt_items, lpt.data(), lpt.size(), st));
+    RC_TRY(c->pool.alloc(se->pose, 48 * (size_t)S));
+    RC_TRY(c->pool.alloc(se->head, 256));
+    RC_TRY(c->pool.alloc(se->counters, 256));
+    RC_HIP(hipStreamSynchronize(st));
+    c->sensors = std::move(se);
+    return RC_OK;
+}
+
+rc_status rc_ray_layout(const rc_context *c, int64_t *ray_offsets, int64_t *total_rays)
+{
+    RC_CHECK(c, "NULL context");
+    if (!c->sensors)
+        return fail(RC_E_STATE, "no sensors attached");
+    if (ray_offsets)
+        memcpy(ray_offsets, c->sensors->ray_off.data(), sizeof(int64_t) * c->sensors->ray_off.size());
+    if (total_rays)
+        *total_rays = c->sensors->total_rays;
+    return RC_OK;
+}
+
+rc_status rc_env_tri_offsets(const rc_context *c, int64_t *off)
+{
+    RC_CHECK(c && off, "NULL argument");
+    if (!c->scene)
+        return fail(RC_E_STATE, "no scene loaded");
+    memcpy(off, c->scene->env_tri_off.data(), sizeof(int64_t) * c->scene->env_tri_off.size());
+    return RC_OK;
+}
+
+rc_status rc_set_instance_poses(rc_context *c, const float *d_inst_T, void *stream)
+{
+    RC_CHECK(c, "NULL context");
+    if (!c->scene)
+        return fail(RC_E_STATE, "no scene loaded");
+    Scene &sc = *c->scene;
+    RC_CHECK(sc.n_inst == 0 || d_inst_T, "d_inst_T is NULL");
+    RC_TRY(set_device(c));
+    hipStream_t st = pick(c, stream);
+    if (sc.n_inst) {
+        RC_HIP(hipMemcpyAsync(sc.inst_T.p, d_inst_T, 48 * sc.n_inst, hipMemcpyDeviceToDevice, st));
+        RC_HIP(hipMemcpyAsync(sc.inst_T0.p, d_inst_T, 48 * sc.n_inst, hipMemcpyDeviceToDevice, st));
+    }
+    sc.poses_set = true;
+    return RC_OK;
+}
+
+rc_status rc_set_sensor_poses(rc_context *c, const float *d_sensor_T, void *stream)
+{
+    RC_CHECK(c, "NULL context");
+    if (!c->sensors)
+        return fail(RC_E_STATE, "no sensors attached");
+    Sensors &se = *c->sensors;
+    RC_CHECK(se.n_si == 0 || d_sensor_T, "d_sensor_T is NULL");
+    RC_TRY(set_device(c));
+    if (se.n_si)
+        RC_HIP(hipMemcpyAsync(se.pose.p, d_sensor_T, 48 * se.n_si, hipMemcpyDeviceToDevice, pick(c, stream)));
+    se.poses_set = true;
+    return RC_OK;
+}
+
+rc_status rc_move_instances(rc_context *c, const float *d_vel, int32_t step, float dt, void *stream)
+{
+    RC_CHECK(c, "NULL context");
+    if (!c->scene || !c->scene->poses_set)
+        return fail(RC_E_STATE, "instance poses not set");
+    Scene &sc = *c->scene;
+    RC_CHECK(sc.n_inst == 0 || d_vel, "d_vel is NULL");
+    RC_CHECK(isfinite(dt), "dt not finite");
+    RC_TRY(set_device(c));
+    RC_HIP(launch_move(sc.n_inst, sc.inst_T0.as<float>(), d_vel, sc.inst_dyn.as<uint8_t>(), step, dt,
+                       sc.inst_T.as<float>(), pick(c, stream)));
+    return RC_OK;
+}
+
+rc_status rc_build(rc_context *c, int32_t builder, void *stream)
+{
+    RC_CHECK(c, "NULL context");
+    RC_CHECK(builder == RC_BUILD_SAH, "unknown builder %d", builder);
+    if (!c->scene || !c->scene->poses_set)
+        return fail(RC_E_STATE, "rc_build needs a scene and instance poses");
+    Scene &sc = *c->scene;
+    RC_TRY(set_device(c));
+    hipStream_t st = pick(c, stream);
+    const BuildView v = sc.view();
+    RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
+    RC_HIP(launch_build_sah(v, st));
+    sc.built = true;
+    return RC_OK;
+}
+
+rc_status rc_refit(rc_context *c, void *stream)
+{
+    RC_CHECK(c, "NULL context");
+    if (!c->scene || !c->scene->built)
+        return fail(RC_E_STATE, "rc_refit before rc_build");
+    Scene &sc = *c->scene;
+    RC_TRY(set_device(c));
+    hipStream_t st = pick(c, stream);
+    const BuildView v = sc.view();
+    RC_HIP(launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, st));
+    RC_HIP(launch_refit(v, st));
+    return RC_OK;
+}
+
+static rc_status render_ready(const rc_context *c)
+{
+    if (!c->scene || !c->scene->built)
+        return fail(RC_E_STATE, "render before rc_build");
+    if (!c->sensors)
+        return fail(RC_E_STATE, "render before rc_sensors_attach");
+    if (!c->sensors->poses_set)
+        return fail(RC_E_STATE, "render before rc_set_sensor_poses");
+    return RC_OK;
+}
+
+rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *stream)
+{
+    RC_CHECK(c && out, "NULL argument");
+    RC_TRY(render_ready(c));
+    RC_CHECK(mode >= RC_RENDER_PLAIN && mode <= RC_RENDER_BRUTE, "unknown render mode %d", mode);
+    RC_TRY(set_device(c));
+    hipStream_t st = pick(c, stream);
+    const Scene &sc = *c->scene;
+    Sensors &se = *c->sensors;
+    const SceneView sv = sc.sview();
+    const SensorView ev = se.view();
+    const OutView ov{out->depth, out->seg, out->tri, out->hit_xyz};
+    switch (mode) {
+    case RC_RENDER_PLAIN:
+        for (int64_t s = 0; s < se.n_si; ++s)
+            RC_HIP(launch_render_flat(sv, ev, ov, se.item_off[s], se.item_off[s + 1] - se.item_off[s], st));
+        break;
+    case RC_RENDER_FLAT:
+        RC_HIP(launch_render_flat(sv, ev, ov, 0, se.n_items, st));
+        break;
+    case RC_RENDER_BATCHED:
+        RC_HIP(launch_render_batched(sv, ev, ov, se.lpt_items.as<int2>(), se.n_items, se.head.as<unsigned int>(),
+                                     c->batched_grid, st));
+        break;
+    case RC_RENDER_BRUTE:
+        RC_HIP(launch_render_brute(sv, ev, ov, se.n_items, st));
+        break;
+    }
+    return RC_OK;
+}
+
+rc_status rc_render_stats(rc_context *c, void *stream, int64_t *counters)
+{
+    RC_CHECK(c && counters, "NULL argument");
+    RC_TRY(render_ready(c));
+    RC_TRY(set_device(c));
+    hipStream_t st = pick(c, stream);
+    Sensors &se = *c->sensors;
+    const OutView ov{nullptr, nullptr, nullptr, nullptr};
+    RC_HIP(launch_fill_u32(se.counters.as<unsigned int>(), 8, 0u, st));
+    RC_HIP(launch_render_stats(c->scene->sview(), se.view(), ov, se.n_items, se.counters.as<unsigned long long>(),
+                               st));
+    unsigned long long h[3];
+    RC_HIP(hipMemcpyAsync(h, se.counters.p, sizeof h, hipMemcpyDeviceToHost, st));
+    RC_HIP(hipStreamSynchronize(st));
+    counters[0] = (int64_t)h[0];
+    counters[1] = (int64_t)h[1];
+    counters[2] = (int64_t)h[2];
+    counters[3] = se.total_rays;
+    return RC_OK;
+}
+
+rc_status rc_debug_world(rc_context *c, float *tris9)
+{
+    RC_CHECK(c && tris9, "NULL argument");
+    if (!c->scene || !c->scene->built)
+        return fail(RC_E_STATE, "no built scene");
+    RC_TRY(set_device(c));
+    RC_HIP(hipStreamSynchronize(c->stream));
+    RC_HIP(hipMemcpy(tris9, c->scene->world.p, 36 * c->scene->n_tris, hipMemcpyDeviceToHost));
+    return RC_OK;
+}
+
+rc_status rc_debug_rays(rc_context *c, int32_t s, int64_t n, const int64_t *ray_idx, float *o, float *d)
+{
+    RC_CHECK(c && (n == 0 || (ray_idx && o && d)), "NULL argument");
+    if (!c->sensors || !c->sensors->poses_set)
+        return fail(RC_E_STATE, "sensors or sensor poses missing");
+    Sensors &se = *c->sensors;
+    RC_CHECK(s >= 0 && s < se.n_si, "sensor instance %d out of range", s);
+    const int64_t nr = se.ray_off[s + 1] - se.ray_off[s];
+    for (int64_t i = 0; i < n; ++i)
+        RC_CHECK(ray_idx[i] >= 0 && ray_idx[i] < nr, "ray index %lld out of range", (long long)ray_idx[i]);
+    RC_TRY(set_device(c));
+    hipStream_t st = c->stream;
+    DBuf di, dout;
+    RC_TRY(c->pool.alloc(di, 8 * n));
+    RC_TRY(c->pool.alloc(dout, 24 * n));
+    RC_HIP(hipMemcpyAsync(di.p, ray_idx, 8 * n, hipMemcpyHostToDevice, st));
+    float *od = dout.as<float>();
+    RC_HIP(launch_debug_rays(se.view(), s, n, di.as<int64_t>(), od, od + 3 * n, st));
+    RC_HIP(hipMemcpyAsync(o, od, 12 * n, hipMemcpyDeviceToHost, st));
+    RC_HIP(hipMemcpyAsync(d, od + 3 * n, 12 * n, hipMemcpyDeviceToHost, st));
+    RC_HIP(hipStreamSynchronize(st));
+    return RC_OK;
+}
+
+rc_status rc_debug_bvh(rc_context *c, int32_t e, int32_t *n_nodes, float *boxes, int32_t *children, int32_t *parent,
+                       int32_t *leaf_ids, int32_t *root)
+{
+    RC_CHECK(c && n_nodes && boxes && children && parent && leaf_ids && root, "NULL argument");
+    if (!c->scene || !c->scene->built)
+        return fail(RC_E_STATE, "no built scene");
+    const Scene &sc = *c->scene;
+    RC_CHECK(e >= 0 && e < sc.n_envs, "environment %d out of range", e);
+    RC_TRY(set_device(c));
+    RC_HIP(hipStreamSynchronize(c->stream));
+    const int64_t base = sc.env_tri_off[e], n = sc.env_tri_off[e + 1] - base;
+    int32_t nn = 0;
+    RC_HIP(hipMemcpy(&nn, sc.env_nodes.as<int32_t>() + e, 4, hipMemcpyDeviceToHost));
+    RC_HIP(hipMemcpy(root, sc.env_root.as<int32_t>() + e, 4, hipMemcpyDeviceToHost));
+    std::vector<Node> nodes(nn);
+    std::vector<TriRec> recs(n);
+    if (nn)
+        RC_HIP(hipMemcpy(nodes.data(), sc.nodes.as<Node>() + base, sizeof(Node) * nn, hipMemcpyDeviceToHost));
+    if (n)
+        RC_HIP(hipMemcpy(recs.data(), sc.recs.as<TriRec>() + base, sizeof(TriRec) * n, hipMemcpyDeviceToHost));
+    *n_nodes = nn;
+    for (int32_t i = 0; i < nn; ++i) {
+        const Node &d = nodes[i];
+        const float b[12] = {d.xy0.x, d.xy0.z, d.z01.x, d.xy0.y, d.xy0.w, d.z01.y,
+                             d.xy1.x, d.xy1.z, d.z01.z, d.xy1.y, d.xy1.w, d.z01.w};
+        memcpy(boxes + 12 * (int64_t)i, b, sizeof b);
+        children[2 * i] = d.ch.x;
+        children[2 * i + 1] = d.ch.y;
+        parent[i] = d.ch.z;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t id;
+        memcpy(&id, &recs[i].c.y, 4);
+        leaf_ids[i] = id;
+    }
+    return RC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// rc_common.hpp -- data layouts shared by the renderer's host runtime and its
+// gfx950 kernels (internal to the library; the public ABI is include/rc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rc {
+
+// ---------------------------------------------------------------------------
+// BVH layout.  Binary BVH with both child boxes stored in the parent (one
+// 64-byte node fetch tests two children).  Child refs: >= 0 internal node
+// index (environment-local, node array of environment e starts at
+// env_tri_off[e]); < 0 leaf ~(first << 3 | (count - 1)) over the
+// environment's leaf-ordered triangle records.
+// ---------------------------------------------------------------------------
+constexpr int kLeafMax = 4;        // triangles per leaf (<= 8 by the encoding)
+constexpr int kMaxNodeDepth = 30;  // internal-node depth bound enforced by the builder
+constexpr int kStack = 32;         // traversal stack entries (> kMaxNodeDepth)
+constexpr int kBins = 16;          // SAH bins per axis
+constexpr int kEmptyRoot = INT32_MIN;
+
+struct alignas(16) Node {
+    float4 xy0;  // child 0: lo.x hi.x lo.y hi.y
+    float4 xy1;  // child 1: lo.x hi.x lo.y hi.y
+    float4 z01;  // lo0.z hi0.z lo1.z hi1.z
+    int4 ch;     // child0, child1, parent (-1 at the root), unused
+};
+static_assert(sizeof(Node) == 64, "node is one 64-byte fetch");
+
+// Leaf-ordered triangle record: 3 vertices + environment-local triangle id.
+struct alignas(16) TriRec {
+    float4 a;  // v0.x v0.y v0.z v1.x
+    float4 b;  // v1.y v1.z v2.x v2.y
+    float4 c;  // v2.z, id (bits), 0, 0
+};
+static_assert(sizeof(TriRec) == 48, "record is three 16-byte fetches");
+
+__host__ __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
+
+// ---------------------------------------------------------------------------
+// Sensors.
+// ---------------------------------------------------------------------------
+struct SensorModel {
+    int32_t kind;     // 0 pinhole, 1 lidar, 2 table
+    int32_t W, H;     // pinhole W x H; lidar azimuths x channels
+    int32_t tiles_x;  // 8x8 ray tiles per row of tiles
+    int32_t tiles;    // tiles per sensor instance
+    float s;          // pinhole: tan(hfov/2)/(W/2)
+    float hw, hh;     // W/2, H/2
+    float tn, tf;     // near, far
+    int64_t table_off;  // float3 entries into the direction table (lidar/table)
+};
+
+// ---------------------------------------------------------------------------
+// Kernel argument views.
+// ---------------------------------------------------------------------------
+struct SceneView {
+    const int64_t *env_tri_off;  // [E+1]
+    const int32_t *env_root;     // [E]
+    const Node *nodes;           // [N] (env base = env_tri_off[e])
+    const TriRec *recs;          // [N] leaf order
+    const int32_t *tri_seg;      // [N] global original order
+    const float *world;          // [N][9] original order (reference path)
+    int32_t n_envs;
+};
+
+struct SensorView {
+    const SensorModel *models;
+    const float *tables;     // float3 directions
+    const int32_t *si_env;   // [S]
+    const int32_t *si_model; // [S]
+    const int64_t *ray_off;  // [S+1]
+    const float *pose;       // [S][12]
+    const int2 *items;       // (sensor instance, tile)
+};
+
+struct OutView {
+    float *depth;
+    int32_t *seg;
+    int32_t *tri;
+    float *hit;
+};
+
+struct BuildView {
+    int32_t n_envs;
+    int64_t n_tris;
+    const int64_t *env_tri_off;  // [E+1]
+    const int32_t *tri_env;      // [N]
+    const int2 *tri_src;         // [N] (instance, global prototype triangle)
+    const float *proto_xyz;      // prototype vertices
+    const int32_t *proto_tri;    // prototype triangles (global vertex indices)
+    const float *inst_T;         // [I][12]
+    float *world;                // [N][9] original order
+    float4 *box_lo, *box_hi, *cen;  // [N] build scratch
+    int32_t *prim, *tmp;         // [N] build scratch
+    Node *nodes;                 // [N]
+    TriRec *recs;                // [N]
+    int32_t *pos_of;             // [N] leaf position of env-local id
+    int32_t *env_root;           // [E]
+    int32_t *env_nodes;          // [E] internal nodes per environment
+    int32_t *refit_cnt;          // [N] refit arrival counters (kept at zero)
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (rc_build.hip / rc_render.hip).
+// ---------------------------------------------------------------------------
+hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t n, bool to_recs,
+                            hipStream_t st);
+hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step,
+                       float dt, float *T, hipStream_t st);
+hipError_t launch_build_sah(const BuildView &v, hipStream_t st);
+hipError_t launch_refit(const BuildView &v, hipStream_t st);
+
+hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const OutView &o, int64_t item_begin,
+                              int64_t n_items, hipStream_t st);
+hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const int2 *lpt_items,
+                                 int64_t n_items, unsigned int *head, int grid, hipStream_t st);
+int batched_grid_size(int device);
+hipError_t launch_render_brute(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                               hipStream_t st);
+hipError_t launch_render_stats(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                               unsigned long long *counters, hipStream_t st);
+hipError_t launch_debug_rays(const SensorView &se, int32_t s, int64_t n, const int64_t *ray_idx, float *o,
+                             float *d, hipStream_t st);
+hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int value, hipStream_t st);
+
+}  // namespace rc

@@ -1,0 +1,617 @@
+// rc_render.hip -- ray generation, BVH traversal and output kernels (gfx950).
+//
+// Paper, Sec. III-D: one ray per pixel (pinhole) or beam (LiDAR) is cast
+// against the environment's transformed mesh; the sensor-to-hit distance is
+// range, the distance from the image plane is depth, and segmentation, face
+// index and hit point come from the same nearest hit.
+//
+// Arithmetic.  Traversal and triangle tests run in FP32.  Every FP32 test
+// carries a forward error bound, so each decision is either certain (equal to
+// the exact-arithmetic decision) or flagged uncertain; uncertain decisions,
+// and the reported t of the final winner, are evaluated in FP64 on the same
+// FP32 inputs (an adaptive-precision predicate).  Hence every render mode and
+// every BVH returns the exact nearest hit up to FP64 rounding, with the
+// lowest-id tie break, and all modes are bit-identical.
+//
+// Layout.  A wavefront (64 lanes) takes one tile of 8 x 8 rays of one sensor
+// instance; a 256-lane workgroup holds four such tiles.  The traversal stack
+// lives in LDS (kStack entries per lane, lane-interleaved).
+#include "rc_common.hpp"
+
+namespace rc {
+
+namespace {
+
+constexpr float kU = 0x1p-24f;              // unit roundoff
+constexpr float kErr = 0x1p-17f;            // triple-product error factor (>= 48 u)
+constexpr float kBoxGrow = 1.0f + 0x1p-20f;  // >= 1 + 4 gamma_3 (robust slab test)
+constexpr int kBlock = 256;
+
+struct Ray {
+    float ox, oy, oz;
+    float dx, dy, dz;
+    float ix, iy, iz;
+    float knd;  // kErr * max|d_i|
+    float tn, tf;
+};
+
+// Unified wave-uniform view of one work item.
+struct Tile {
+    int s, env, W, H, kind, tiles_x;
+    float hw, hh, scale, tn, tf;
+    int64_t table_off, ray_base;
+};
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Ray of (row, col) of sensor instance s.  Local direction: pinhole
+// (1, -(col+1/2-W/2) s, -(row+1/2-H/2) s); lidar / table from the FP32
+// direction table.  World direction i = fma(P_i0, dx, fma(P_i1, dy, P_i2 dz)).
+__device__ __forceinline__ void gen_ray(const SensorView &se, const Tile &t, int row, int col, Ray &r)
+{
+    float lx, ly, lz;
+    if (t.kind == 0) {
+        lx = 1.0f;
+        ly = -((((float)col + 0.5f) - t.hw) * t.scale);
+        lz = -((((float)row + 0.5f) - t.hh) * t.scale);
+    } else {
+        const float *d = se.tables + 3 * (t.table_off + (int64_t)row * t.W + col);
+        lx = d[0];
+        ly = d[1];
+        lz = d[2];
+    }
+    const float *P = se.pose + 12 * (int64_t)t.s;
+    r.ox = P[3];
+    r.oy = P[7];
+    r.oz = P[11];
+    r.dx = fmaf(P[0], lx, fmaf(P[1], ly, P[2] * lz));
+    r.dy = fmaf(P[4], lx, fmaf(P[5], ly, P[6] * lz));
+    r.dz = fmaf(P[8], lx, fmaf(P[9], ly, P[10] * lz));
+    r.ix = 1.0f / r.dx;
+    r.iy = 1.0f / r.dy;
+    r.iz = 1.0f / r.dz;
+    r.knd = kErr * fmaxf(fmaxf(fabsf(r.dx), fabsf(r.dy)), fabsf(r.dz));
+    r.tn = t.tn;
+    r.tf = t.tf;
+}
+
+__device__ __forceinline__ Tile load_tile(const SensorView &se, int2 item)
+{
+    Tile t;
+    t.s = item.x;
+    const int m = se.si_model[t.s];
+    const SensorModel &M = se.models[m];
+    t.env = se.si_env[t.s];
+    t.W = M.W;
+    t.H = M.H;
+    t.kind = M.kind;
+    t.tiles_x = M.tiles_x;
+    t.hw = M.hw;
+    t.hh = M.hh;
+    t.scale = M.s;
+    t.tn = M.tn;
+    t.tf = M.tf;
+    t.table_off = M.table_off;
+    t.ray_base = se.ray_off[t.s];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Robust slab test (boxes are stored expanded outward by one float step).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool slab(const Ray &r, float lx, float hx, float ly, float hy, float lz, float hz,
+                                     float tcap, float &tenter)
+{
+    const float t0x = (lx - r.ox) * r.ix, t1x = (hx - r.ox) * r.ix;
+    const float t0y = (ly - r.oy) * r.iy, t1y = (hy - r.oy) * r.iy;
+    const float t0z = (lz - r.oz) * r.iz, t1z = (hz - r.oz) * r.iz;
+    const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), r.tn));
+    const float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tcap));
+    tenter = tmin;
+    return tmin <= tmax * kBoxGrow;
+}
+
+// ---------------------------------------------------------------------------
+// Moller-Trumbore with certified FP32 decisions.
+//   e1 = v1 - v0, e2 = v2 - v0, T = o - v0, p = d x e2, q = T x e1,
+//   det = e1.p, U = T.p, V = d.q, W = e2.q;  hit iff det != 0, U/det >= 0,
+//   V/det >= 0, (U+V)/det <= 1 and near <= W/det <= far.
+// Each triple product is within kErr * (product of the operands' max-norms)
+// of its exact value.  Returns kReject / kAccept when certain, else kUnsure;
+// on kAccept, [t - et, t + et] contains the exact t.
+// ---------------------------------------------------------------------------
+enum { kReject = 0, kAccept = 1, kUnsure = 2 };
+
+__device__ __forceinline__ int mt32(const Ray &r, const float4 A, const float4 B, const float4 C, float tcap,
+                                    float &t, float &et)
+{
+    const float e1x = A.w - A.x, e1y = B.x - A.y, e1z = B.y - A.z;
+    const float e2x = B.z - A.x, e2y = B.w - A.y, e2z = C.x - A.z;
+    const float Tx = r.ox - A.x, Ty = r.oy - A.y, Tz = r.oz - A.z;
+    const float px = fmaf(r.dy, e2z, -(r.dz * e2y));
+    const float py = fmaf(r.dz, e2x, -(r.dx * e2z));
+    const float pz = fmaf(r.dx, e2y, -(r.dy * e2x));
+    const float det = fmaf(e1x, px, fmaf(e1y, py, e1z * pz));
+    const float qx = fmaf(Ty, e1z, -(Tz * e1y));
+    const float qy = fmaf(Tz, e1x, -(Tx * e1z));
+    const float qz = fmaf(Tx, e1y, -(Ty * e1x));
+    const float U = fmaf(Tx, px, fmaf(Ty, py, Tz * pz));
+    const float V = fmaf(r.dx, qx, fmaf(r.dy, qy, r.dz * qz));
+    const float W = fmaf(e2x, qx, fmaf(e2y, qy, e2z * qz));
+    const float n1 = fmaxf(fmaxf(fabsf(e1x), fabsf(e1y)), fabsf(e1z));
+    const float n2 = fmaxf(fmaxf(fabsf(e2x), fabsf(e2y)), fabsf(e2z));
+    const float nT = fmaxf(fmaxf(fabsf(Tx), fabsf(Ty)), fabsf(Tz));
+    const float kT = r.knd * nT;
+    const float eD = r.knd * n1 * n2;
+    const float eU = kT * n2;
+    const float eV = kT * n1;
+    const float eW = kErr * nT * n1 * n2;
+    const float ad = fabsf(det);
+    if (!(ad > 2.0f * eD))
+        return kUnsure;
+    const bool neg = det < 0.0f;
+    const float sU = neg ? -U : U, sV = neg ? -V : V, sW = neg ? -W : W;
+    if (sU < -eU || sV < -eV)
+        return kReject;
+    const float S = sU + sV;
+    const float eS = eU + eV + eD + 4.0f * kU * (fabsf(sU) + fabsf(sV) + ad);
+    if (S > ad + eS)
+        return kReject;
+    const float rcp = __builtin_amdgcn_rcpf(ad);
+    t = sW * rcp;
+    const float at = fabsf(t);
+    et = 2.0f * fmaf(at, eD, eW) * rcp + 4.0f * kU * at;
+    if (t + et < r.tn || t - et > tcap)
+        return kReject;
+    const bool sure = sU >= eU && sV >= eV && S <= ad - eS && t - et >= r.tn && t + et <= r.tf;
+    return sure ? kAccept : kUnsure;
+}
+
+// FP64 evaluation of the same test on the same FP32 inputs.  Kept out of
+// line (it runs only for uncertain tests and winners) and called by value so
+// the ray stays in registers.
+struct T64 {
+    double t;
+    int ok;
+};
+
+__device__ __noinline__ T64 mt64v(float ox, float oy, float oz, float dxf, float dyf, float dzf, float tn, float tf,
+                                 float4 A, float4 B, float4 C)
+{
+    T64 res{0.0, 0};
+    const double ax = A.x, ay = A.y, az = A.z;
+    const double e1x = (double)A.w - ax, e1y = (double)B.x - ay, e1z = (double)B.y - az;
+    const double e2x = (double)B.z - ax, e2y = (double)B.w - ay, e2z = (double)C.x - az;
+    const double dx = dxf, dy = dyf, dz = dzf;
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    double det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0)
+        return res;
+    const double Tx = (double)ox - ax, Ty = (double)oy - ay, Tz = (double)oz - az;
+    const double qx = Ty * e1z - Tz * e1y, qy = Tz * e1x - Tx * e1z, qz = Tx * e1y - Ty * e1x;
+    double U = Tx * px + Ty * py + Tz * pz;
+    double V = dx * qx + dy * qy + dz * qz;
+    double W = e2x * qx + e2y * qy + e2z * qz;
+    if (det < 0.0) {
+        det = -det;
+        U = -U;
+        V = -V;
+        W = -W;
+    }
+    if (U < 0.0 || V < 0.0 || U + V > det)
+        return res;
+    res.t = W / det;
+    res.ok = res.t >= (double)tn && res.t <= (double)tf;
+    return res;
+}
+
+__device__ __forceinline__ bool mt64(const Ray &r, const float4 A, const float4 B, const float4 C, double &t)
+{
+    const T64 q = mt64v(r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tn, r.tf, A, B, C);
+    t = q.t;
+    return q.ok != 0;
+}
+
+struct Best {
+    float lo, hi;  // bracket of the exact t of the current winner
+    int pos;       // record index (-1: none)
+    int id;        // environment-local triangle id
+    bool have64;
+    double t64;
+};
+
+struct Stats {
+    unsigned box, tri, fp64;
+};
+
+// Offer triangle record (A, B, C) at index pos to the running winner.
+template <bool STATS>
+__device__ __forceinline__ void offer(const Ray &r, const TriRec *__restrict__ recs, int pos, const float4 A,
+                                     const float4 B, const float4 C, Best &b, Stats &st)
+{
+    float t, et;
+    const int code = mt32(r, A, B, C, b.hi, t, et);
+    if (code == kReject)
+        return;
+    if (code == kAccept && t + et < b.lo) {
+        b.lo = t - et;
+        b.hi = t + et;
+        b.pos = pos;
+        b.id = __float_as_int(C.y);
+        b.have64 = false;
+        return;
+    }
+    if (STATS)
+        ++st.fp64;
+    double tc;
+    if (!mt64(r, A, B, C, tc))
+        return;
+    const int idc = __float_as_int(C.y);
+    if (b.pos >= 0 && !b.have64) {
+        const TriRec w = recs[b.pos];
+        double tw;
+        if (mt64(r, w.a, w.b, w.c, tw)) {
+            b.t64 = tw;
+            b.have64 = true;
+        } else {
+            b.pos = -1;  // cannot happen for a certain accept; drop it defensively
+        }
+    }
+    if (b.pos < 0 || tc < b.t64 || (tc == b.t64 && idc < b.id)) {
+        b.pos = pos;
+        b.id = idc;
+        b.t64 = tc;
+        b.have64 = true;
+        const float tf = (float)tc;
+        b.lo = tf * (1.0f - 0x1p-23f);
+        b.hi = tf * (1.0f + 0x1p-23f);
+    }
+}
+
+// Stack-based traversal of one ray (nearest child first).
+template <bool STATS>
+__device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ nodes,
+                                         const TriRec *__restrict__ recs, int root, int *stk, Best &b, Stats &st)
+{
+    int sp = 0;
+    int ref = root;
+    while (true) {
+        if (ref >= 0) {
+            const Node *n = nodes + ref;
+            const float4 a = n->xy0, c = n->xy1, z = n->z01;
+            const int4 ch = n->ch;
+            float t0, t1;
+            const bool h0 = slab(r, a.x, a.y, a.z, a.w, z.x, z.y, b.hi, t0);
+            const bool h1 = slab(r, c.x, c.y, c.z, c.w, z.z, z.w, b.hi, t1);
+            if (STATS)
+                st.box += 2;
+            if (h0 && h1) {
+                const bool first0 = t0 <= t1;
+                stk[sp * kBlock] = first0 ? ch.y : ch.x;
+                ++sp;
+                ref = first0 ? ch.x : ch.y;
+                continue;
+            }
+            if (h0 || h1) {
+                ref = h0 ? ch.x : ch.y;
+                continue;
+            }
+        } else {
+            const int code = ~ref;
+            const int first = code >> 3, cnt = (code & 7) + 1;
+            for (int k = 0; k < cnt; ++k) {
+                const TriRec T = recs[first + k];
+                if (STATS)
+                    ++st.tri;
+                offer<STATS>(r, recs, first + k, T.a, T.b, T.c, b, st);
+            }
+        }
+        if (sp == 0)
+            break;
+        --sp;
+        ref = stk[sp * kBlock];
+    }
+}
+
+// Final outputs of one ray from the winner (FP64 t, hit = o + t d).
+__device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc, const Ray &r, int env,
+                                          const TriRec *__restrict__ recs, Best &b, int64_t idx)
+{
+    float depth = -1.0f, hx = __builtin_nanf(""), hy = hx, hz = hx;
+    int seg = -1, tri = -1;
+    if (b.pos >= 0) {
+        double t = b.t64;
+        if (!b.have64) {
+            t = 0.5 * ((double)b.lo + (double)b.hi);
+            if (recs) {
+                const TriRec w = recs[b.pos];
+                double tw;
+                if (mt64(r, w.a, w.b, w.c, tw))
+                    t = tw;
+            }
+        }
+        depth = (float)t;
+        hx = (float)((double)r.ox + t * (double)r.dx);
+        hy = (float)((double)r.oy + t * (double)r.dy);
+        hz = (float)((double)r.oz + t * (double)r.dz);
+        tri = b.id;
+        seg = sc.tri_seg[sc.env_tri_off[env] + b.id];
+    }
+    if (o.depth)
+        o.depth[idx] = depth;
+    if (o.seg)
+        o.seg[idx] = seg;
+    if (o.tri)
+        o.tri[idx] = tri;
+    if (o.hit) {
+        o.hit[3 * idx + 0] = hx;
+        o.hit[3 * idx + 1] = hy;
+        o.hit[3 * idx + 2] = hz;
+    }
+}
+
+// One 8x8 tile per wavefront.
+template <bool STATS>
+__device__ __forceinline__ void render_tile(const SceneView &sc, const SensorView &se, const OutView &o, int2 item,
+                                            int *stk, Stats &st)
+{
+    const Tile t = load_tile(se, item);
+    const int lane = threadIdx.x & 63;
+    const int tile = item.y;
+    const int ty = tile / t.tiles_x, tx = tile - ty * t.tiles_x;
+    const int row = ty * 8 + (lane >> 3), col = tx * 8 + (lane & 7);
+    if (row >= t.H || col >= t.W)
+        return;
+    Ray r;
+    gen_ray(se, t, row, col, r);
+    Best b{r.tf, r.tf, -1, -1, false, 0.0};
+    const int64_t base = sc.env_tri_off[t.env];
+    const Node *nodes = sc.nodes + base;
+    const TriRec *recs = sc.recs + base;
+    const int root = sc.env_root[t.env];
+    if (root != kEmptyRoot)
+        traverse<STATS>(r, nodes, recs, root, stk, b, st);
+    write_out(o, sc, r, t.env, recs, b, t.ray_base + (int64_t)row * t.W + col);
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; map them so that each XCD walks
+// a contiguous range of work (neighbouring tiles share an environment's BVH
+// in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t q = nb >> 3, rem = nb & 7, x = b & 7;
+    return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
+__global__ __launch_bounds__(kBlock) void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
+                                                        int64_t n_items)
+{
+    __shared__ int s_stack[kStack * kBlock];
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t k = lb * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    if (k >= n_items)
+        return;
+    Stats st{0, 0, 0};
+    render_tile<false>(sc, se, o, se.items[item_begin + k], s_stack + threadIdx.x, st);
+}
+
+__global__ __launch_bounds__(kBlock) void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
+                                                         unsigned long long *counters)
+{
+    __shared__ int s_stack[kStack * kBlock];
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t k = lb * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    if (k >= n_items)
+        return;
+    Stats st{0, 0, 0};
+    render_tile<true>(sc, se, o, se.items[k], s_stack + threadIdx.x, st);
+    unsigned box = st.box, tri = st.tri, f64 = st.fp64;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        box += __shfl_xor(box, off, 64);
+        tri += __shfl_xor(tri, off, 64);
+        f64 += __shfl_xor(f64, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&counters[0], (unsigned long long)box);
+        atomicAdd(&counters[1], (unsigned long long)tri);
+        atomicAdd(&counters[2], (unsigned long long)f64);
+    }
+}
+
+// Persistent form: every wavefront pops tiles from a device queue.
+__global__ __launch_bounds__(kBlock) void k_render_batched(SceneView sc, SensorView se, OutView o,
+                                                           const int2 *__restrict__ items, int64_t n_items,
+                                                           unsigned int *head)
+{
+    __shared__ int s_stack[kStack * kBlock];
+    const int lane = threadIdx.x & 63;
+    Stats st{0, 0, 0};
+    while (true) {
+        unsigned int k = 0;
+        if (lane == 0)
+            k = atomicAdd(head, 1u);
+        k = (unsigned)uniform((int)k);
+        if ((int64_t)k >= n_items)
+            break;
+        render_tile<false>(sc, se, o, items[k], s_stack + threadIdx.x, st);
+    }
+}
+
+// Reference path: every triangle of the environment, original order.
+__global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorView se, OutView o, int64_t n_items)
+{
+    const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    if (k >= n_items)
+        return;
+    const int2 item = se.items[k];
+    const Tile t = load_tile(se, item);
+    const int lane = threadIdx.x & 63;
+    const int ty = item.y / t.tiles_x, tx = item.y - ty * t.tiles_x;
+    const int row = ty * 8 + (lane >> 3), col = tx * 8 + (lane & 7);
+    if (row >= t.H || col >= t.W)
+        return;
+    Ray r;
+    gen_ray(se, t, row, col, r);
+    Best b{r.tf, r.tf, -1, -1, false, 0.0};
+    Stats st{0, 0, 0};
+    const int64_t base = sc.env_tri_off[t.env];
+    const int n = (int)(sc.env_tri_off[t.env + 1] - base);
+    // records in original order are built on the fly from the world array;
+    // the winner is re-read through the same path, so pos indexes world tris
+    const float *w = sc.world + 9 * base;
+    for (int i = 0; i < n; ++i) {
+        const float *q = w + 9 * i;
+        const float4 A = make_float4(q[0], q[1], q[2], q[3]);
+        const float4 B = make_float4(q[4], q[5], q[6], q[7]);
+        const float4 C = make_float4(q[8], __int_as_float(i), 0.f, 0.f);
+        float tt, et;
+        const int code = mt32(r, A, B, C, b.hi, tt, et);
+        if (code == kReject)
+            continue;
+        if (code == kAccept && tt + et < b.lo) {
+            b.lo = tt - et;
+            b.hi = tt + et;
+            b.pos = i;
+            b.id = i;
+            b.have64 = false;
+            continue;
+        }
+        double tc;
+        if (!mt64(r, A, B, C, tc))
+            continue;
+        if (b.pos >= 0 && !b.have64) {
+            const float *p = w + 9 * b.pos;
+            double tw;
+            if (mt64(r, make_float4(p[0], p[1], p[2], p[3]), make_float4(p[4], p[5], p[6], p[7]),
+                     make_float4(p[8], 0.f, 0.f, 0.f), tw)) {
+                b.t64 = tw;
+                b.have64 = true;
+            } else {
+                b.pos = -1;
+            }
+        }
+        if (b.pos < 0 || tc < b.t64 || (tc == b.t64 && i < b.id)) {
+            b.pos = i;
+            b.id = i;
+            b.t64 = tc;
+            b.have64 = true;
+            const float tf = (float)tc;
+            b.lo = tf * (1.0f - 0x1p-23f);
+            b.hi = tf * (1.0f + 0x1p-23f);
+        }
+    }
+    if (b.pos >= 0 && !b.have64) {
+        const float *p = w + 9 * b.pos;
+        double tw;
+        if (mt64(r, make_float4(p[0], p[1], p[2], p[3]), make_float4(p[4], p[5], p[6], p[7]),
+                 make_float4(p[8], 0.f, 0.f, 0.f), tw)) {
+            b.t64 = tw;
+            b.have64 = true;
+        }
+    }
+    (void)st;
+    write_out(o, sc, r, t.env, nullptr, b, t.ray_base + (int64_t)row * t.W + col);
+}
+
+__global__ __launch_bounds__(256) void k_debug_rays(SensorView se, int32_t s, int64_t n,
+                                                    const int64_t *__restrict__ ray_idx, float *o, float *d)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const Tile t = load_tile(se, make_int2(s, 0));
+    const int64_t ri = ray_idx[i];
+    const int row = (int)(ri / t.W), col = (int)(ri % t.W);
+    Ray r;
+    gen_ray(se, t, row, col, r);
+    o[3 * i] = r.ox;
+    o[3 * i + 1] = r.oy;
+    o[3 * i + 2] = r.oz;
+    d[3 * i] = r.dx;
+    d[3 * i + 1] = r.dy;
+    d[3 * i + 2] = r.dz;
+}
+
+__global__ void k_fill_u32(unsigned int *p, int64_t n, unsigned int value)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = value;
+}
+
+inline unsigned blocks_for(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const OutView &o, int64_t item_begin,
+                              int64_t n_items, hipStream_t st)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_render_flat, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se, o,
+                       item_begin, n_items);
+    return hipGetLastError();
+}
+
+int batched_grid_size(int device)
+{
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess)
+        return 1024;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return p.multiProcessorCount * per_cu;
+}
+
+hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const int2 *lpt_items,
+                                 int64_t n_items, unsigned int *head, int grid, hipStream_t st)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    hipError_t err = launch_fill_u32(head, 1, 0u, st);
+    if (err != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(k_render_batched, dim3(grid), dim3(kBlock), 0, st, sc, se, o, lpt_items, n_items, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_brute(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                               hipStream_t st)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_render_brute, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se, o,
+                       n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_stats(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                               unsigned long long *counters, hipStream_t st)
+{
+    if (n_items == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_render_stats, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se, o,
+                       n_items, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_rays(const SensorView &se, int32_t s, int64_t n, const int64_t *ray_idx, float *o, float *d,
+                             hipStream_t st)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_debug_rays, dim3(blocks_for(n, 256)), dim3(256), 0, st, se, s, n, ray_idx, o, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int *p, int64_t n, unsigned int value, hipStream_t st)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
+}  // namespace rc

@@ -1,0 +1,251 @@
+"""Python binding of the renderer's C ABI (``include/rc.h``).
+
+Argument marshalling only: every function forwards to the ``rc_*`` entry point
+of the same name in ``librc.so``; every step of the rendering path runs in the
+library's HIP kernels.  Device buffers are torch tensors on a HIP device
+(their ``data_ptr()`` is passed), host arrays are numpy arrays.  Loading fails
+loudly if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librc.so")
+
+RC_PINHOLE, RC_LIDAR, RC_TABLE = 0, 1, 2
+RC_BUILD_SAH = 0
+RC_RENDER_PLAIN, RC_RENDER_FLAT, RC_RENDER_BATCHED, RC_RENDER_BRUTE = 0, 1, 2, 3
+
+# Every function declared in include/rc.h.
+ABI = [
+    "rc_status_string", "rc_last_error", "rc_create", "rc_destroy", "rc_memory_used", "rc_mesh_add",
+    "rc_scene_load", "rc_sensor_add", "rc_sensors_attach", "rc_ray_layout", "rc_env_tri_offsets",
+    "rc_set_instance_poses", "rc_set_sensor_poses", "rc_move_instances", "rc_build", "rc_refit", "rc_render",
+    "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh",
+]
+
+
+class RCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class rc_sensor_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("hfov", C.c_float),
+                ("vmin", C.c_float), ("vmax", C.c_float), ("hmin", C.c_float), ("hmax", C.c_float),
+                ("near_", C.c_float), ("far_", C.c_float), ("dir_table", C.c_void_p)]
+
+
+class rc_outputs(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("seg", C.c_void_p), ("tri", C.c_void_p), ("hit_xyz", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``librc.so`` (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_01471_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "rc_status_string": (C.c_char_p, [I32]),
+            "rc_last_error": (C.c_char_p, []),
+            "rc_create": (I32, [I32, P, SZ, C.POINTER(P)]),
+            "rc_destroy": (I32, [P]),
+            "rc_memory_used": (I32, [P, C.POINTER(SZ)]),
+            "rc_mesh_add": (I32, [P, P, I32, P, I32, C.POINTER(I32)]),
+            "rc_scene_load": (I32, [P, I32, P, P, P, P]),
+            "rc_sensor_add": (I32, [P, C.POINTER(rc_sensor_desc), C.POINTER(I32)]),
+            "rc_sensors_attach": (I32, [P, P, P]),
+            "rc_ray_layout": (I32, [P, P, C.POINTER(I64)]),
+            "rc_env_tri_offsets": (I32, [P, P]),
+            "rc_set_instance_poses": (I32, [P, P, P]),
+            "rc_set_sensor_poses": (I32, [P, P, P]),
+            "rc_move_instances": (I32, [P, P, I32, C.c_float, P]),
+            "rc_build": (I32, [P, I32, P]),
+            "rc_refit": (I32, [P, P]),
+            "rc_render": (I32, [P, C.POINTER(rc_outputs), I32, P]),
+            "rc_render_stats": (I32, [P, P, P]),
+            "rc_debug_world": (I32, [P, P]),
+            "rc_debug_rays": (I32, [P, I32, I64, P, P, P]),
+            "rc_debug_bvh": (I32, [P, I32, C.POINTER(I32), P, P, P, P, C.POINTER(I32)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        L = lib()
+        raise RCError(status, f"{L.rc_status_string(status).decode()}: {L.rc_last_error().decode()}")
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array or torch tensor (None passes NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _dev(t, dtype_name: str, numel: int, what: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a torch tensor on a HIP device")
+    if str(t.dtype) != "torch." + dtype_name or not t.is_contiguous() or t.numel() < numel:
+        raise TypeError(f"{what} must be a contiguous torch.{dtype_name} tensor with >= {numel} elements")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream or None
+    return getattr(stream, "cuda_stream", stream) or None
+
+
+# --------------------------------------------------------------------------
+# one wrapper per entry point
+# --------------------------------------------------------------------------
+def rc_create(device: int = 0, stream=None, hbm_budget: int = 0):
+    out = C.c_void_p()
+    _check(lib().rc_create(device, _stream(stream) if stream is not None else None, hbm_budget, C.byref(out)))
+    return out.value
+
+
+def rc_destroy(ctx) -> None:
+    _check(lib().rc_destroy(ctx))
+
+
+def rc_memory_used(ctx) -> int:
+    n = C.c_size_t()
+    _check(lib().rc_memory_used(ctx, C.byref(n)))
+    return n.value
+
+
+def rc_mesh_add(ctx, xyz, tris) -> int:
+    xyz = _host(xyz, np.float32).reshape(-1, 3)
+    tris = _host(tris, np.int32).reshape(-1, 3)
+    mid = C.c_int32()
+    _check(lib().rc_mesh_add(ctx, _ptr(xyz), len(xyz), _ptr(tris), len(tris), C.byref(mid)))
+    return mid.value
+
+
+def rc_scene_load(ctx, inst_offsets, inst_mesh, inst_seg, inst_dynamic=None) -> None:
+    io = _host(inst_offsets, np.int64)
+    im = _host(inst_mesh, np.int32)
+    iseg = _host(inst_seg, np.int32)
+    idyn = None if inst_dynamic is None else _host(inst_dynamic, np.uint8)
+    _check(lib().rc_scene_load(ctx, len(io) - 1, _ptr(io), _ptr(im), _ptr(iseg), _ptr(idyn)))
+
+
+def rc_sensor_add(ctx, kind, width, height, hfov=0.0, vmin=0.0, vmax=0.0, hmin=0.0, hmax=0.0, near=0.0,
+                  far=0.0, dir_table=None) -> int:
+    tab = None if dir_table is None else _host(dir_table, np.float32)
+    d = rc_sensor_desc(kind, width, height, hfov, vmin, vmax, hmin, hmax, near, far,
+                       None if tab is None else tab.ctypes.data)
+    sid = C.c_int32()
+    _check(lib().rc_sensor_add(ctx, C.byref(d), C.byref(sid)))
+    return sid.value
+
+
+def rc_sensors_attach(ctx, sens_offsets, sensor_ids) -> None:
+    so = _host(sens_offsets, np.int64)
+    ids = _host(sensor_ids, np.int32)
+    _check(lib().rc_sensors_attach(ctx, _ptr(so), _ptr(ids)))
+
+
+def rc_ray_layout(ctx, n_sensor_inst: int):
+    off = np.zeros(n_sensor_inst + 1, np.int64)
+    tot = C.c_int64()
+    _check(lib().rc_ray_layout(ctx, _ptr(off), C.byref(tot)))
+    return off, tot.value
+
+
+def rc_env_tri_offsets(ctx, n_envs: int) -> np.ndarray:
+    off = np.zeros(n_envs + 1, np.int64)
+    _check(lib().rc_env_tri_offsets(ctx, _ptr(off)))
+    return off
+
+
+def rc_set_instance_poses(ctx, d_inst_T, stream=None) -> None:
+    _check(lib().rc_set_instance_poses(ctx, _dev(d_inst_T, "float32", 0, "d_inst_T"), _stream(stream)))
+
+
+def rc_set_sensor_poses(ctx, d_sensor_T, stream=None) -> None:
+    _check(lib().rc_set_sensor_poses(ctx, _dev(d_sensor_T, "float32", 0, "d_sensor_T"), _stream(stream)))
+
+
+def rc_move_instances(ctx, d_vel, step: int, dt: float, stream=None) -> None:
+    _check(lib().rc_move_instances(ctx, _dev(d_vel, "float32", 0, "d_vel"), step, dt, _stream(stream)))
+
+
+def rc_build(ctx, builder: int = RC_BUILD_SAH, stream=None) -> None:
+    _check(lib().rc_build(ctx, builder, _stream(stream)))
+
+
+def rc_refit(ctx, stream=None) -> None:
+    _check(lib().rc_refit(ctx, _stream(stream)))
+
+
+def rc_render(ctx, depth=None, seg=None, tri=None, hit_xyz=None, mode: int = RC_RENDER_FLAT, stream=None,
+              total_rays: int = 0) -> None:
+    out = rc_outputs(
+        None if depth is None else _dev(depth, "float32", total_rays, "depth"),
+        None if seg is None else _dev(seg, "int32", total_rays, "seg"),
+        None if tri is None else _dev(tri, "int32", total_rays, "tri"),
+        None if hit_xyz is None else _dev(hit_xyz, "float32", 3 * total_rays, "hit_xyz"))
+    _check(lib().rc_render(ctx, C.byref(out), mode, _stream(stream)))
+
+
+def rc_render_stats(ctx, stream=None) -> np.ndarray:
+    c = np.zeros(4, np.int64)
+    _check(lib().rc_render_stats(ctx, _stream(stream), _ptr(c)))
+    return c
+
+
+def rc_debug_world(ctx, n_tris: int) -> np.ndarray:
+    w = np.zeros((n_tris, 9), np.float32)
+    _check(lib().rc_debug_world(ctx, _ptr(w)))
+    return w
+
+
+def rc_debug_rays(ctx, s: int, ray_idx):
+    idx = _host(ray_idx, np.int64)
+    o = np.zeros((len(idx), 3), np.float32)
+    d = np.zeros((len(idx), 3), np.float32)
+    _check(lib().rc_debug_rays(ctx, s, len(idx), _ptr(idx), _ptr(o), _ptr(d)))
+    return o, d
+
+
+def rc_debug_bvh(ctx, e: int, n_tris: int) -> dict:
+    cap = max(n_tris, 1)
+    boxes = np.zeros((cap, 2, 6), np.float32)
+    ch = np.zeros((cap, 2), np.int32)
+    par = np.zeros(cap, np.int32)
+    ids = np.zeros(cap, np.int32)
+    nn = C.c_int32()
+    root = C.c_int32()
+    _check(lib().rc_debug_bvh(ctx, e, C.byref(nn), _ptr(boxes), _ptr(ch), _ptr(par), _ptr(ids), C.byref(root)))
+    n = nn.value
+    return dict(n_nodes=n, boxes=boxes[:n], children=ch[:n], parent=par[:n], leaf_ids=ids[:n_tris],
+                root=root.value)

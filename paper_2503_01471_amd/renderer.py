@@ -1,0 +1,89 @@
+"""Load a generated scene into the HIP renderer (marshalling only).
+
+``Renderer(scene)`` registers the scene's prototype meshes, instances and
+sensors through the C ABI, keeps the pose tensors on the device and exposes
+build / refit / render with torch output tensors.  No rendering arithmetic
+happens here.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rc
+
+
+class Renderer:
+    def __init__(self, scene, device: int = 0, hbm_budget: int = 0, build: bool = True):
+        self.scene = scene
+        self.device = torch.device("cuda", device)
+        self.ctx = rc.rc_create(device, None, hbm_budget)
+        for v, t in scene.protos:
+            rc.rc_mesh_add(self.ctx, v, t)
+        rc.rc_scene_load(self.ctx, scene.inst_offsets, scene.inst_mesh, scene.inst_seg, scene.inst_dynamic)
+        for desc in scene.sensors:
+            rc.rc_sensor_add(self.ctx, desc.kind, desc.width, desc.height, desc.hfov, desc.vmin, desc.vmax,
+                             desc.hmin, desc.hmax, desc.near, desc.far, desc.dir_table)
+        rc.rc_sensors_attach(self.ctx, scene.sens_offsets, scene.sensor_ids)
+        self.n_si = len(scene.sensor_ids)
+        self.ray_offsets, self.total_rays = rc.rc_ray_layout(self.ctx, self.n_si)
+        self.env_tri_off = rc.rc_env_tri_offsets(self.ctx, scene.n_envs)
+        self.n_tris = int(self.env_tri_off[-1])
+        self.inst_T = torch.from_numpy(np.ascontiguousarray(scene.inst_T, np.float32)).to(self.device)
+        self.sensor_T = torch.from_numpy(np.ascontiguousarray(scene.sensor_T, np.float32)).to(self.device)
+        self.inst_vel = torch.from_numpy(np.ascontiguousarray(scene.inst_vel, np.float32)).to(self.device)
+        if scene.n_inst:
+            rc.rc_set_instance_poses(self.ctx, self.inst_T)
+        else:
+            rc.rc_set_instance_poses(self.ctx, torch.zeros(12, device=self.device))
+        if self.n_si:
+            rc.rc_set_sensor_poses(self.ctx, self.sensor_T)
+        else:
+            rc.rc_set_sensor_poses(self.ctx, torch.zeros(12, device=self.device))
+        if build:
+            self.build()
+
+    # -- acceleration structure --------------------------------------------
+    def build(self, stream=None):
+        rc.rc_build(self.ctx, rc.RC_BUILD_SAH, stream)
+
+    def refit(self, stream=None):
+        rc.rc_refit(self.ctx, stream)
+
+    def move(self, step: int, stream=None):
+        rc.rc_move_instances(self.ctx, self.inst_vel, step, float(self.scene.dt), stream)
+
+    def set_sensor_poses(self, T: torch.Tensor, stream=None):
+        rc.rc_set_sensor_poses(self.ctx, T, stream)
+
+    # -- outputs -------------------------------------------------------------
+    def alloc(self, depth=True, seg=True, tri=False, hit=False):
+        n = self.total_rays
+        d = self.device
+        return dict(
+            depth=torch.empty(n, dtype=torch.float32, device=d) if depth else None,
+            seg=torch.empty(n, dtype=torch.int32, device=d) if seg else None,
+            tri=torch.empty(n, dtype=torch.int32, device=d) if tri else None,
+            hit_xyz=torch.empty(n, 3, dtype=torch.float32, device=d) if hit else None,
+        )
+
+    def render(self, out=None, mode: int = rc.RC_RENDER_FLAT, stream=None, **which):
+        if out is None:
+            out = self.alloc(**which) if which else self.alloc(depth=True, seg=True, tri=True, hit=True)
+        rc.rc_render(self.ctx, out.get("depth"), out.get("seg"), out.get("tri"), out.get("hit_xyz"), mode, stream,
+                     self.total_rays)
+        return out
+
+    def stats(self):
+        return rc.rc_render_stats(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            rc.rc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

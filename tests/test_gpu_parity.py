@@ -1,0 +1,249 @@
+"""GPU parity: the HIP renderer (through the C ABI) against the CPU oracle.
+
+Small configurations are checked on every ray; the full-size workloads are
+rendered in the launch configuration the benchmark times and checked on a
+seeded sample of rays.  All render modes and the brute-force path must agree
+bit for bit."""
+import numpy as np
+import pytest
+
+import bvh_check
+import parity
+from oracle import oracle as O
+from paper_2503_01471_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _renderer(scene, **kw):
+    from paper_2503_01471_amd.renderer import Renderer
+    return Renderer(scene, **kw)
+
+
+def _host(out):
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+
+
+def _all_modes_equal(R, ref):
+    from paper_2503_01471_amd import rc
+    for mode in (rc.RC_RENDER_PLAIN, rc.RC_RENDER_BATCHED, rc.RC_RENDER_BRUTE):
+        _say(f"mode {mode}")
+        o = _host(R.render(mode=mode))
+        torch.cuda.synchronize()
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(o[k], ref[k]), (mode, k)
+        assert np.array_equal(np.isnan(o["hit_xyz"]), np.isnan(ref["hit_xyz"]))
+        assert np.array_equal(np.nan_to_num(o["hit_xyz"]), np.nan_to_num(ref["hit_xyz"])), mode
+
+
+def _check_scene(scene, modes=True, bvh_envs=(0,)):
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    _say(f"{scene.name}: envs={scene.n_envs} rays={scene.total_rays()}")
+    R = _renderer(scene)
+    out = _host(R.render(mode=rc.RC_RENDER_FLAT))
+    torch.cuda.synchronize()
+    w = O.world(scene)
+    # the transform is FP32 with a fixed fma order on both sides: bit-exact
+    gw = rc.rc_debug_world(R.ctx, R.n_tris)
+    assert np.array_equal(gw, w.tris)
+    assert np.array_equal(R.env_tri_off, w.env_off)
+    ora = O.render(scene, w)
+    rep = parity.compare(out, ora)
+    print(rep, flush=True)
+    parity.assert_contract(rep)
+    for e in bvh_envs:
+        bvh = rc.rc_debug_bvh(R.ctx, e, int(w.env_off[e + 1] - w.env_off[e]))
+        errs = bvh_check.validate(bvh, w.tris[w.env_off[e]:w.env_off[e + 1]])
+        assert not errs, errs[:5]
+    if modes:
+        _all_modes_equal(R, out)
+    return R, out, ora, rep
+
+
+def test_cfg1_all_rays_all_modes():
+    R, out, ora, rep = _check_scene(S.make_cfg1())
+    # cfg1 is small enough that every ray (borderline included) matches
+    assert rep["all_tri_agree"] == rep["n"], rep
+    R.close()
+
+
+def test_rays_bit_exact():
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    for scene in (S.make_cfg1(), S.make_cfg3(n_envs=1), S.make_cfg4(n_envs=3)):
+        _say(f"rays {scene.name}")
+        R = _renderer(scene, build=False)
+        for s in range(len(scene.sensor_ids)):
+            n = scene.sensors[int(scene.sensor_ids[s])].n_rays
+            idx = np.unique(np.r_[0, n - 1, np.random.default_rng(s).integers(0, n, 500)])
+            go, gd = rc.rc_debug_rays(R.ctx, s, idx)
+            oo, od = O.sensor_rays(scene, s, idx)
+            assert np.array_equal(go, oo) and np.array_equal(gd, od), (scene.name, s)
+        R.close()
+
+
+def test_cfg2_small_full_res():
+    R, *_ = _check_scene(S.make_cfg2(n_envs=3), bvh_envs=(0, 1, 2))
+    R.close()
+
+
+def test_cfg3_small_full_res():
+    R, *_ = _check_scene(S.make_cfg3(n_envs=3), bvh_envs=(0, 2))
+    R.close()
+
+
+def test_cfg4_small_mixed_sensors():
+    R, *_ = _check_scene(S.make_cfg4(n_envs=6), bvh_envs=(0, 3))
+    R.close()
+
+
+def test_cfg4_motion_refit_equals_rebuild():
+    """Move dynamic boxes, refit, render; compare with the oracle at the moved
+    poses, and with a from-scratch build at the same poses (bit-exact)."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=6, env_ids=None)
+    R = _renderer(scene)
+    for step in (1, 50, 99):
+        _say(f"cfg4 motion step {step}")
+        R.move(step)
+        R.refit()
+        refit = _host(R.render(mode=rc.RC_RENDER_FLAT))
+        T = O.moved_poses(scene, step)
+        w = O.world(scene, T)
+        gw = rc.rc_debug_world(R.ctx, R.n_tris)
+        assert np.array_equal(gw, w.tris), step
+        ora = O.render(scene, w)
+        rep = parity.compare(refit, ora)
+        print(rep, flush=True)
+        parity.assert_contract(rep)
+        for e in (0, 5):
+            bvh = rc.rc_debug_bvh(R.ctx, e, int(w.env_off[e + 1] - w.env_off[e]))
+            assert not bvh_check.validate(bvh, w.tris[w.env_off[e]:w.env_off[e + 1]])
+    # rebuild from scratch at the last poses: same outputs bit for bit
+    Tt = torch.from_numpy(O.moved_poses(scene, 99)).cuda()
+    rc.rc_set_instance_poses(R.ctx, Tt)
+    R.build()
+    rebuilt = _host(R.render(mode=rc.RC_RENDER_FLAT))
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(rebuilt[k], refit[k]), k
+    R.close()
+
+
+def test_deterministic():
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    scene = S.make_cfg2(n_envs=4, W=160, H=90)
+    R = _renderer(scene)
+    a = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    R.build()
+    b = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(a[k], b[k])
+    R.close()
+
+
+def test_edge_cases():
+    """Empty environment, single-triangle environment (root is a leaf),
+    exactly one full leaf, ragged tiles (7x5, 1x1 sensors), near = far,
+    no sensors in some envs, a direction-table sensor."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    quad, box = S.quad_mesh(), S.box_mesh()
+    one = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.int32))
+    rng = np.random.default_rng(5)
+    dirs = rng.normal(size=(6 * 4, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    sensors = [S.pinhole(7, 5, 60.0, 0.1, 50.0), S.pinhole(1, 1, 30.0, 0.1, 50.0),
+               S.table_sensor(dirs, 6, 4, 0.0, 50.0), S.pinhole(16, 16, 90.0, 2.0, 2.0)]
+    look_down = S.sensor_pose(S.rot_zyx(0.3, 80 * S.DEG), (0.3, 0.2, 2.0))
+    T = lambda s, t: S.affine(np.diag(s), t)
+    z3 = (0.0, 0.0, 0.0)
+    envs = [
+        ([], [(0, look_down)]),  # empty environment
+        ([(2, 3, T([1, 1, 1], z3), 0, z3)], [(0, look_down), (1, look_down)]),  # 1 triangle
+        ([(0, 1, T([4, 4, 1], (-2, -2, 0)), 0, z3), (0, 2, T([1, 1, 1], (0, 0, 1)), 0, z3)],
+         [(2, look_down), (3, look_down)]),  # 4 triangles = one full leaf
+        ([(1, 7, T([1, 1, 1], (0.3, 0.2, 0.0)), 0, z3)], []),  # sensor-less env
+        ([(1, k, T([0.5, 0.5, 0.5], (k * 0.25, 0, 0)), 0, z3) for k in range(12)] +
+         [(0, 0, T([10, 10, 1], (-5, -5, 0)), 0, z3)], [(0, look_down), (2, look_down)]),
+    ]
+    scene = S.custom_scene([quad, box, one], envs, sensors)
+    _check_scene(scene, bvh_envs=(1, 2, 4))
+
+
+def test_api_errors():
+    """Argument and state errors are reported as status codes before any work."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    ctx = rc.rc_create(0)
+    with pytest.raises(rc.RCError) as ei:
+        rc.rc_scene_load(ctx, [0, 1], [5], [0])  # no such mesh
+    assert ei.value.status == -1
+    with pytest.raises(rc.RCError) as ei:
+        rc.rc_build(ctx)  # no scene
+    assert ei.value.status == -4
+    mid = rc.rc_mesh_add(ctx, *S.box_mesh())
+    rc.rc_scene_load(ctx, [0, 1], [mid], [1])
+    with pytest.raises(rc.RCError) as ei:
+        rc.rc_render(ctx, torch.empty(1, device="cuda"))  # not built
+    assert ei.value.status == -4
+    with pytest.raises(rc.RCError):
+        rc.rc_sensor_add(ctx, rc.RC_PINHOLE, 8, 8, hfov=1.0, near=2.0, far=1.0)
+    rc.rc_destroy(ctx)
+    # budget: a scene that does not fit fails with RC_E_OOM and keeps the old one
+    ctx = rc.rc_create(0, None, 1 << 20)
+    mid = rc.rc_mesh_add(ctx, *S.icosphere_mesh(2))
+    rc.rc_scene_load(ctx, [0, 1], [mid], [1])
+    used = rc.rc_memory_used(ctx)
+    with pytest.raises(rc.RCError) as ei:
+        rc.rc_scene_load(ctx, [0, 64], [mid] * 64, [1] * 64)
+    assert ei.value.status == -2
+    assert rc.rc_memory_used(ctx) == used
+    rc.rc_destroy(ctx)
+
+
+# --------------------------------------------------------------------------
+# full-size workloads, sampled rays, benchmark launch configuration
+# --------------------------------------------------------------------------
+def _sampled(scene, mode, n_sample=12000, seed=0):
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    _say(f"full {scene.name}: envs={scene.n_envs} rays={scene.total_rays()} mode={mode}")
+    R = _renderer(scene)
+    out = R.render(mode=mode, depth=True, seg=True, tri=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed)
+    g = np.sort(rng.choice(R.total_rays, n_sample, replace=False))
+    gi = torch.from_numpy(g).cuda()
+    got = {k: out[k][gi].cpu().numpy() for k in ("depth", "seg", "tri")}
+    s = np.searchsorted(R.ray_offsets, g, side="right") - 1
+    ridx = g - R.ray_offsets[s]
+    ora = O.render(scene, O.world(scene), sensor_inst=s, ray_idx=ridx)
+    rep = parity.compare(got, ora)
+    print(rep, flush=True)
+    parity.assert_contract(rep)
+    # whole-image properties: every hit depth within [near, far], misses sentinel
+    d = out["depth"]
+    seg = out["seg"]
+    assert bool(torch.all((d == -1) == (seg == -1)))
+    R.close()
+    return rep
+
+
+@pytest.mark.parametrize("cfg,mode", [(3, 2), (2, 2), (4, 2)])
+def test_full_size_sampled(cfg, mode):
+    scene = S.make(cfg)
+    _sampled(scene, mode)
