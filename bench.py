@@ -37,11 +37,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def byte_model(stats, rays):
-    """Algorithmic bytes per ray: 32 B per ray-box test, 40 B per ray-triangle
-    test (36 B vertices + 4 B id), 8 B of output (depth + label)."""
-    box, tri = stats[0], stats[1]
-    return (32.0 * box + 40.0 * tri) / rays + 8.0
+def traffic_record(kernel, cfg):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cfg{cfg}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as g:
+            h.update(g.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec
+
+
+def calibration_copy(nbytes=1 << 28):
+    """A plain device copy of known size: the profiler's FETCH_SIZE / WRITE_SIZE
+    for it give the scale factor from counter units to bytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def cpu_baseline(cfg, seconds):
@@ -77,6 +100,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); environments shard across GPUs "
@@ -126,7 +150,15 @@ def main():
     # components on the same stream
     ms_render = timed(lambda: rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays), args.steps)
     ms_build = timed(lambda: rc.rc_build(ctx), max(2, args.steps // 2))
-    log(f"render {ms_render:.3f} ms, build {ms_build:.3f} ms")
+
+    def refit_step():
+        rc.rc_set_sensor_poses(ctx, R.sensor_T)
+        rc.rc_set_instance_poses(ctx, R.inst_T)
+        rc.rc_refit(ctx)
+        rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays)
+
+    ms_refit_step = timed(refit_step, max(2, args.steps // 2))
+    log(f"render {ms_render:.3f} ms, build {ms_build:.3f} ms, refit step {ms_refit_step:.3f} ms")
     plain = None
     if not args.no_plain and mode != rc.RC_RENDER_PLAIN:
         ms_plain = timed(lambda: rc.rc_render(ctx, out["depth"], out["seg"], None, None, rc.RC_RENDER_PLAIN, None,
@@ -134,8 +166,14 @@ def main():
         plain = {"ms_render": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_vs_plain": ms_plain / ms_render}
         log(f"plain render {ms_plain:.3f} ms")
     stats = R.stats()
-    b_ray = byte_model(stats, rays)
+    from bytemodel import bytemodel
+    bm = bytemodel.load()[f"cfg{args.cfg}"]
+    b_ray = bm["bytes_per_ray"]
     achieved = b_ray * rays / (ms_render * 1e-3) / 1e9
+    kernel = "k_render_batched" if mode == rc.RC_RENDER_BATCHED else "k_render_flat"
+    traffic = traffic_record(kernel, args.cfg)
+    if args.calib:
+        calibration_copy()
     result = {
         "metric": METRIC,
         "value": rays / ms / 1e3,
@@ -151,18 +189,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cfg{args.cfg}: {WORKLOADS[args.cfg]}", "envs": n_envs, "rays_per_step": rays,
                    "mode": args.mode, "outputs": "depth+seg",
-                   "step": "sensor poses + transform + SAH build + render"},
+                   "step": "sensor poses + transform of every instance + SAH build of every env + render"},
         "env_steps_per_s": n_envs / (ms * 1e-3),
         "render_ms": ms_render,
         "render_Mrays_s": rays / ms_render / 1e3,
         "build_ms": ms_build,
+        "refit_step_ms": ms_refit_step,
+        "refit_step_Mrays_s": rays / ms_refit_step / 1e3,
         "plain": plain,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
-                      "fp64_per_ray": stats[2] / rays},
+                      "fp64_evals_per_ray": stats[2] / rays},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_ray": b_ray,
-                     "kernel": "k_render_batched" if mode == rc.RC_RENDER_BATCHED else "k_render_flat",
-                     "byte_model": "traversal counters of this BVH"},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "kernel": kernel, "bytes_per_ray": b_ray, "units_per_launch": rays,
+                     "byte_model": "canonical full-sweep SAH traversal: 32 B/box test + 40 B/tri test + 8 B out",
+                     "l2_hit_rate": None if traffic is None else traffic.get("l2_hit_rate")},
         "cpu_baseline": None,
     }
     R.close()

@@ -104,7 +104,7 @@ struct Scene {
     std::vector<int64_t> env_tri_off;  // host copy
     std::vector<int64_t> inst_offsets;
     DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
-    DBuf world, box_lo, box_hi, cen, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, refit_cnt;
+    DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes;
     bool poses_set = false;
     bool built = false;
 
@@ -122,7 +122,6 @@ struct Scene {
         v.world = world.as<float>();
         v.box_lo = box_lo.as<float4>();
         v.box_hi = box_hi.as<float4>();
-        v.cen = cen.as<float4>();
         v.prim = prim.as<int32_t>();
         v.tmp = tmp.as<int32_t>();
         v.nodes = nodes.as<Node>();
@@ -130,7 +129,6 @@ struct Scene {
         v.pos_of = pos_of.as<int32_t>();
         v.env_root = env_root.as<int32_t>();
         v.env_nodes = env_nodes.as<int32_t>();
-        v.refit_cnt = refit_cnt.as<int32_t>();
         return v;
     }
     SceneView sview() const
@@ -360,7 +358,6 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->world, 36 * N));
     RC_TRY(c->pool.alloc(sc->box_lo, 16 * N));
     RC_TRY(c->pool.alloc(sc->box_hi, 16 * N));
-    RC_TRY(c->pool.alloc(sc->cen, 16 * N));
     RC_TRY(c->pool.alloc(sc->prim, 4 * N));
     RC_TRY(c->pool.alloc(sc->tmp, 4 * N));
     RC_TRY(c->pool.alloc(sc->nodes, sizeof(Node) * N));
@@ -368,8 +365,6 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->pos_of, 4 * N));
     RC_TRY(c->pool.alloc(sc->env_root, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->env_nodes, 4 * (size_t)n_envs));
-    RC_TRY(c->pool.alloc(sc->refit_cnt, 4 * N));
-    RC_HIP(hipMemsetAsync(sc->refit_cnt.p, 0, 4 * N, st));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);

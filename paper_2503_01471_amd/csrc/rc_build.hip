@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_move(int64_t n, const float *__restrict
         T[12 * i + k] = a[k];
 }
 
-// K2: per-triangle bounds and centroid (build scratch).
+// K2: per-triangle bounds (build scratch).
 __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -129,7 +129,6 @@ __global__ __launch_bounds__(256) void k_bounds(BuildView v)
     const float lz = fminf(fminf(w[2], w[5]), w[8]), hz = fmaxf(fmaxf(w[2], w[5]), w[8]);
     v.box_lo[g] = make_float4(lx, ly, lz, 0.f);
     v.box_hi[g] = make_float4(hx, hy, hz, 0.f);
-    v.cen[g] = make_float4(0.5f * (lx + hx), 0.5f * (ly + hy), 0.5f * (lz + hz), 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -139,29 +138,16 @@ __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 // stable partitions of the primitive list, so the build is deterministic.
 // A node whose subtree could exceed kMaxNodeDepth is split at the index median
 // (balanced), which bounds the traversal stack.
+// Once a task holds at most kSmall primitives its whole subtree is built from
+// LDS: depth-first order guarantees that every task popped after it, until the
+// stack is back at its height, is one of its descendants.
 // ---------------------------------------------------------------------------
 constexpr int kTaskCap = kMaxNodeDepth + 4;
+constexpr int kSmall = 128;
 
 struct WaveBox {
     float lx, ly, lz, hx, hy, hz;
 };
-
-__device__ __forceinline__ WaveBox reduce_boxes(const BuildView &v, const int32_t *prim, int64_t base, int b, int e,
-                                                int lane)
-{
-    float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-    for (int i = b + lane; i < e; i += 64) {
-        const int p = prim[i];
-        const float4 lo = v.box_lo[base + p], hi = v.box_hi[base + p];
-        lx = fminf(lx, lo.x);
-        ly = fminf(ly, lo.y);
-        lz = fminf(lz, lo.z);
-        hx = fmaxf(hx, hi.x);
-        hy = fmaxf(hy, hi.y);
-        hz = fmaxf(hz, hi.z);
-    }
-    return WaveBox{wave_min(lx), wave_min(ly), wave_min(lz), wave_max(hx), wave_max(hy), wave_max(hz)};
-}
 
 __device__ __forceinline__ int levels_needed(int n)
 {
@@ -181,6 +167,17 @@ __device__ __forceinline__ int bin_of(float c, float cmin, float scale)
     return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
 }
 
+struct BuildShared {
+    int cnt[3 * kBins];
+    int lo[3 * kBins * 3];
+    int hi[3 * kBins * 3];
+    int tp[kTaskCap], ts[kTaskCap], tb[kTaskCap], te[kTaskCap], td[kTaskCap];
+    float box[6][kSmall];  // local mode: primitive bounds by slot
+    int id[kSmall];        // local mode: environment-local id by slot
+    int perm[kSmall];      // local mode: slot at each position
+    int perm2[kSmall];
+};
+
 __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 {
     const int e = blockIdx.x;
@@ -190,11 +187,9 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
     int32_t *prim = v.prim + base;
     int32_t *tmp = v.tmp + base;
     Node *nodes = v.nodes + base;
-
-    __shared__ int s_cnt[3 * kBins];
-    __shared__ int s_lo[3 * kBins * 3];
-    __shared__ int s_hi[3 * kBins * 3];
-    __shared__ int s_tp[kTaskCap], s_ts[kTaskCap], s_tb[kTaskCap], s_te[kTaskCap], s_td[kTaskCap];
+    const float4 *blo = v.box_lo + base;
+    const float4 *bhi = v.box_hi + base;
+    __shared__ BuildShared S;
 
     for (int i = lane; i < n; i += 64)
         prim[i] = i;
@@ -207,22 +202,82 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
         return;
     }
     __syncthreads();
+    bool local = false;
+    int b0 = 0, cnt0 = 0, h0 = 0;
+
+    // bounds of the primitive at list position i (global list or LDS copy)
+    auto box_at = [&](int i, float &lx, float &ly, float &lz, float &hx, float &hy, float &hz) {
+        if (local) {
+            const int slot = S.perm[i - b0];
+            lx = S.box[0][slot];
+            ly = S.box[1][slot];
+            lz = S.box[2][slot];
+            hx = S.box[3][slot];
+            hy = S.box[4][slot];
+            hz = S.box[5][slot];
+        } else {
+            const int p = prim[i];
+            const float4 lo = blo[p], hi = bhi[p];
+            lx = lo.x;
+            ly = lo.y;
+            lz = lo.z;
+            hx = hi.x;
+            hy = hi.y;
+            hz = hi.z;
+        }
+    };
+    auto reduce_range = [&](int b, int en) {
+        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+        for (int i = b + lane; i < en; i += 64) {
+            float a0, a1, a2, c0, c1, c2;
+            box_at(i, a0, a1, a2, c0, c1, c2);
+            lx = fminf(lx, a0);
+            ly = fminf(ly, a1);
+            lz = fminf(lz, a2);
+            hx = fmaxf(hx, c0);
+            hy = fmaxf(hy, c1);
+            hz = fmaxf(hz, c2);
+        }
+        return WaveBox{wave_min(lx), wave_min(ly), wave_min(lz), wave_max(hx), wave_max(hy), wave_max(hz)};
+    };
+
     if (n <= kLeafMax) {
         if (lane == 0)
             v.env_root[e] = leaf_ref(0, n);
     } else {
         int sp = 0;
-        s_tp[0] = -1;
-        s_ts[0] = 0;
-        s_tb[0] = 0;
-        s_te[0] = n;
-        s_td[0] = 0;
+        S.tp[0] = -1;
+        S.ts[0] = 0;
+        S.tb[0] = 0;
+        S.te[0] = n;
+        S.td[0] = 0;
         sp = 1;
         __syncthreads();
         while (sp > 0) {
             --sp;
-            const int parent = s_tp[sp], side = s_ts[sp], b = s_tb[sp], en = s_te[sp], depth = s_td[sp];
+            const int parent = S.tp[sp], side = S.ts[sp], b = S.tb[sp], en = S.te[sp], depth = S.td[sp];
             const int cnt = en - b;
+            __syncthreads();
+            if (!local && cnt <= kSmall) {
+                // enter local mode: copy the task's primitives into LDS
+                b0 = b;
+                cnt0 = cnt;
+                h0 = sp;
+                for (int i = lane; i < cnt; i += 64) {
+                    const int p = prim[b + i];
+                    const float4 lo = blo[p], hi = bhi[p];
+                    S.id[i] = p;
+                    S.perm[i] = i;
+                    S.box[0][i] = lo.x;
+                    S.box[1][i] = lo.y;
+                    S.box[2][i] = lo.z;
+                    S.box[3][i] = hi.x;
+                    S.box[4][i] = hi.y;
+                    S.box[5][i] = hi.z;
+                }
+                local = true;
+                __syncthreads();
+            }
             const int id = n_nodes++;
             if (lane == 0) {
                 if (parent < 0)
@@ -232,18 +287,21 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                 else
                     nodes[parent].ch.y = id;
                 nodes[id].ch.z = parent;
-                nodes[id].ch.w = 0;
+                nodes[id].ch.w = depth;
             }
-            // centroid bounds
+            // centroid bounds (centroid = midpoint of the primitive's box)
             float cl0 = INFINITY, cl1 = INFINITY, cl2 = INFINITY, ch0 = -INFINITY, ch1 = -INFINITY, ch2 = -INFINITY;
+#pragma unroll 4
             for (int i = b + lane; i < en; i += 64) {
-                const float4 c = v.cen[base + prim[i]];
-                cl0 = fminf(cl0, c.x);
-                cl1 = fminf(cl1, c.y);
-                cl2 = fminf(cl2, c.z);
-                ch0 = fmaxf(ch0, c.x);
-                ch1 = fmaxf(ch1, c.y);
-                ch2 = fmaxf(ch2, c.z);
+                float a0, a1, a2, c0, c1, c2;
+                box_at(i, a0, a1, a2, c0, c1, c2);
+                const float x = 0.5f * (a0 + c0), y = 0.5f * (a1 + c1), z = 0.5f * (a2 + c2);
+                cl0 = fminf(cl0, x);
+                cl1 = fminf(cl1, y);
+                cl2 = fminf(cl2, z);
+                ch0 = fmaxf(ch0, x);
+                ch1 = fmaxf(ch1, y);
+                ch2 = fmaxf(ch2, z);
             }
             const float cmin[3] = {wave_min(cl0), wave_min(cl1), wave_min(cl2)};
             const float cmax[3] = {wave_max(ch0), wave_max(ch1), wave_max(ch2)};
@@ -261,27 +319,28 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
             WaveBox L{}, R{};
             if (usable && !forced) {
                 for (int j = lane; j < 3 * kBins; j += 64) {
-                    s_cnt[j] = 0;
-                    s_lo[3 * j] = s_lo[3 * j + 1] = s_lo[3 * j + 2] = f2o(INFINITY);
-                    s_hi[3 * j] = s_hi[3 * j + 1] = s_hi[3 * j + 2] = f2o(-INFINITY);
+                    S.cnt[j] = 0;
+                    S.lo[3 * j] = S.lo[3 * j + 1] = S.lo[3 * j + 2] = f2o(INFINITY);
+                    S.hi[3 * j] = S.hi[3 * j + 1] = S.hi[3 * j + 2] = f2o(-INFINITY);
                 }
                 __syncthreads();
+#pragma unroll 4
                 for (int i = b + lane; i < en; i += 64) {
-                    const int p = prim[i];
-                    const float4 c = v.cen[base + p], lo = v.box_lo[base + p], hi = v.box_hi[base + p];
-                    const float cc[3] = {c.x, c.y, c.z};
+                    float a0, a1, a2, c0, c1, c2;
+                    box_at(i, a0, a1, a2, c0, c1, c2);
+                    const float cc[3] = {0.5f * (a0 + c0), 0.5f * (a1 + c1), 0.5f * (a2 + c2)};
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         if (scale[a] == 0.f)
                             continue;
                         const int j = a * kBins + bin_of(cc[a], cmin[a], scale[a]);
-                        atomicAdd(&s_cnt[j], 1);
-                        atomicMin(&s_lo[3 * j + 0], f2o(lo.x));
-                        atomicMin(&s_lo[3 * j + 1], f2o(lo.y));
-                        atomicMin(&s_lo[3 * j + 2], f2o(lo.z));
-                        atomicMax(&s_hi[3 * j + 0], f2o(hi.x));
-                        atomicMax(&s_hi[3 * j + 1], f2o(hi.y));
-                        atomicMax(&s_hi[3 * j + 2], f2o(hi.z));
+                        atomicAdd(&S.cnt[j], 1);
+                        atomicMin(&S.lo[3 * j + 0], f2o(a0));
+                        atomicMin(&S.lo[3 * j + 1], f2o(a1));
+                        atomicMin(&S.lo[3 * j + 2], f2o(a2));
+                        atomicMax(&S.hi[3 * j + 0], f2o(c0));
+                        atomicMax(&S.hi[3 * j + 1], f2o(c1));
+                        atomicMax(&S.hi[3 * j + 2], f2o(c2));
                     }
                 }
                 __syncthreads();
@@ -296,16 +355,16 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                         int nr = 0;
                         for (int j = 0; j < kBins; ++j) {
                             const int q = a * kBins + j;
-                            const int c = s_cnt[q];
+                            const int c = S.cnt[q];
                             if (c == 0)
                                 continue;
                             WaveBox &B = j <= k ? bl : br;
-                            B.lx = fminf(B.lx, o2f(s_lo[3 * q]));
-                            B.ly = fminf(B.ly, o2f(s_lo[3 * q + 1]));
-                            B.lz = fminf(B.lz, o2f(s_lo[3 * q + 2]));
-                            B.hx = fmaxf(B.hx, o2f(s_hi[3 * q]));
-                            B.hy = fmaxf(B.hy, o2f(s_hi[3 * q + 1]));
-                            B.hz = fmaxf(B.hz, o2f(s_hi[3 * q + 2]));
+                            B.lx = fminf(B.lx, o2f(S.lo[3 * q]));
+                            B.ly = fminf(B.ly, o2f(S.lo[3 * q + 1]));
+                            B.lz = fminf(B.lz, o2f(S.lo[3 * q + 2]));
+                            B.hx = fmaxf(B.hx, o2f(S.hi[3 * q]));
+                            B.hy = fmaxf(B.hy, o2f(S.hi[3 * q + 1]));
+                            B.hz = fmaxf(B.hz, o2f(S.hi[3 * q + 2]));
                             if (j <= k)
                                 nl += c;
                             else
@@ -337,73 +396,88 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                     R = WaveBox{__shfl(br.lx, bw, 64), __shfl(br.ly, bw, 64), __shfl(br.lz, bw, 64),
                                 __shfl(br.hx, bw, 64), __shfl(br.hy, bw, 64), __shfl(br.hz, bw, 64)};
                     mid = b + nL;
-                    // stable partition into tmp, then copy back
+                    // stable partition, then copy back
                     int lc = 0, rc = 0;
                     const float cm = cmin[best_axis], sc = scale[best_axis];
                     for (int c0 = b; c0 < en; c0 += 64) {
                         const int i = c0 + lane;
                         const bool valid = i < en;
-                        const int p = valid ? prim[i] : 0;
                         float cc = 0.f;
+                        int item = 0;
                         if (valid) {
-                            const float4 c = v.cen[base + p];
-                            cc = best_axis == 0 ? c.x : (best_axis == 1 ? c.y : c.z);
+                            float a0, a1, a2, d0, d1, d2;
+                            box_at(i, a0, a1, a2, d0, d1, d2);
+                            cc = best_axis == 0 ? 0.5f * (a0 + d0) : (best_axis == 1 ? 0.5f * (a1 + d1) : 0.5f * (a2 + d2));
+                            item = local ? S.perm[i - b0] : prim[i];
                         }
                         const bool left = valid && bin_of(cc, cm, sc) <= best_k;
                         const uint64_t m = __ballot(left);
                         const uint64_t below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
                         const int rank = __popcll(below);
                         const int nvalid = min(64, en - c0);
-                        if (left)
-                            tmp[b + lc + rank] = p;
-                        else if (valid)
-                            tmp[mid + rc + (lane - rank)] = p;
+                        const int dst = left ? b + lc + rank : mid + rc + (lane - rank);
+                        if (valid) {
+                            if (local)
+                                S.perm2[dst - b0] = item;
+                            else
+                                tmp[dst] = item;
+                        }
                         const int cl = __popcll(m);
                         lc += cl;
                         rc += nvalid - cl;
                     }
                     __syncthreads();
-                    for (int i = b + lane; i < en; i += 64)
-                        prim[i] = tmp[i];
+                    for (int i = b + lane; i < en; i += 64) {
+                        if (local)
+                            S.perm[i - b0] = S.perm2[i - b0];
+                        else
+                            prim[i] = tmp[i];
+                    }
                     __syncthreads();
                 }
             }
             if (mid < 0) {  // index-median split (forced depth bound or no usable plane)
                 mid = b + cnt / 2;
-                L = reduce_boxes(v, prim, base, b, mid, lane);
-                R = reduce_boxes(v, prim, base, mid, en, lane);
+                L = reduce_range(b, mid);
+                R = reduce_range(mid, en);
             }
             // write the node's child boxes (expanded outward by one step)
+            const int nl = mid - b, nr = en - mid;
             if (lane == 0) {
                 Node &nd = nodes[id];
                 nd.xy0 = make_float4(expand_lo(L.lx), expand_hi(L.hx), expand_lo(L.ly), expand_hi(L.hy));
                 nd.xy1 = make_float4(expand_lo(R.lx), expand_hi(R.hx), expand_lo(R.ly), expand_hi(R.hy));
                 nd.z01 = make_float4(expand_lo(L.lz), expand_hi(L.hz), expand_lo(R.lz), expand_hi(R.hz));
-                const int nl = mid - b, nr = en - mid;
                 if (nl <= kLeafMax)
                     nd.ch.x = leaf_ref(b, nl);
                 if (nr <= kLeafMax)
                     nd.ch.y = leaf_ref(mid, nr);
             }
-            const int nl = mid - b, nr = en - mid;
             // push right then left so that the left child is popped next
             if (nr > kLeafMax) {
-                s_tp[sp] = id;
-                s_ts[sp] = 1;
-                s_tb[sp] = mid;
-                s_te[sp] = en;
-                s_td[sp] = depth + 1;
+                S.tp[sp] = id;
+                S.ts[sp] = 1;
+                S.tb[sp] = mid;
+                S.te[sp] = en;
+                S.td[sp] = depth + 1;
                 ++sp;
             }
             if (nl > kLeafMax) {
-                s_tp[sp] = id;
-                s_ts[sp] = 0;
-                s_tb[sp] = b;
-                s_te[sp] = mid;
-                s_td[sp] = depth + 1;
+                S.tp[sp] = id;
+                S.ts[sp] = 0;
+                S.tb[sp] = b;
+                S.te[sp] = mid;
+                S.td[sp] = depth + 1;
                 ++sp;
             }
             __syncthreads();
+            if (local && sp == h0) {
+                // subtree finished: write its primitive order back
+                for (int i = lane; i < cnt0; i += 64)
+                    prim[b0 + i] = S.id[S.perm[i]];
+                local = false;
+                __syncthreads();
+            }
         }
     }
     if (lane == 0)
@@ -423,19 +497,14 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 }
 
 // ---------------------------------------------------------------------------
-// K7: refit.  One thread per internal node: it writes the boxes of its leaf
-// children, then arrives at its own counter; every completed node writes its
-// box (union of its two child boxes) into its parent and arrives there.  The
-// last arrival (internal children + the node's own thread) completes a node
-// and carries on upward.  min/max are exact, so the result does not depend on
-// the arrival order and equals the from-scratch bounds bit for bit.  Counters
-// are returned to zero by the thread that completes the node.
+// K7: refit.  One workgroup per environment walks its nodes level by level,
+// deepest first (a node's depth is stored in ch.w by the builder): each node
+// takes the bounds of its leaf children from the records and of its internal
+// children from their (already refitted) two child boxes.  All traffic stays
+// inside one workgroup, so a barrier between levels is the only
+// synchronisation.  min/max are exact, so the result equals the from-scratch
+// bounds bit for bit.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float ld_f(const float *p)
-{
-    return __int_as_float(__hip_atomic_load((const int *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
 __device__ __forceinline__ void leaf_box(const TriRec *recs, int ref, float b[6])
 {
     const int code = ~ref;
@@ -458,68 +527,47 @@ __device__ __forceinline__ void leaf_box(const TriRec *recs, int ref, float b[6]
     b[5] = expand_hi(hz);
 }
 
-__device__ __forceinline__ void store_child_box(Node *nd, int side, const float b[6])
+// Box of internal child c = union of its two (stored, already expanded) child
+// boxes; expansion commutes with min/max, so this equals the expanded union.
+__device__ __forceinline__ void node_box(const Node &c, float b[6])
 {
-    float *xy = side == 0 ? &nd->xy0.x : &nd->xy1.x;
-    xy[0] = b[0];
-    xy[1] = b[1];
-    xy[2] = b[2];
-    xy[3] = b[3];
-    float *z = &nd->z01.x + 2 * side;
-    z[0] = b[4];
-    z[1] = b[5];
+    b[0] = fminf(c.xy0.x, c.xy1.x);
+    b[1] = fmaxf(c.xy0.y, c.xy1.y);
+    b[2] = fminf(c.xy0.z, c.xy1.z);
+    b[3] = fmaxf(c.xy0.w, c.xy1.w);
+    b[4] = fminf(c.z01.x, c.z01.z);
+    b[5] = fmaxf(c.z01.y, c.z01.w);
 }
 
-__global__ __launch_bounds__(256) void k_refit(BuildView v)
+constexpr int kRefitBlock = 256;
+
+__global__ __launch_bounds__(kRefitBlock) void k_refit(BuildView v)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= v.n_tris)
-        return;
-    const int e = v.tri_env[g];
+    const int e = blockIdx.x;
     const int64_t base = v.env_tri_off[e];
-    const int m = (int)(g - base);
-    if (m >= v.env_nodes[e])
-        return;
+    const int nn = v.env_nodes[e];
     Node *nodes = v.nodes + base;
     const TriRec *recs = v.recs + base;
-    int32_t *cnt = v.refit_cnt + base;
-
-    const int4 ch = nodes[m].ch;
-    float b[6];
-    if (ch.x < 0) {
-        leaf_box(recs, ch.x, b);
-        store_child_box(&nodes[m], 0, b);
-    }
-    if (ch.y < 0) {
-        leaf_box(recs, ch.y, b);
-        store_child_box(&nodes[m], 1, b);
-    }
-    __threadfence();
-    int cur = m;
-    int pending = (ch.x >= 0) + (ch.y >= 0);
-    if (atomicAdd(&cnt[cur], 1) != pending)
-        return;
-    while (true) {
-        __threadfence();
-        cnt[cur] = 0;
-        const int parent = nodes[cur].ch.z;
-        if (parent < 0)
-            break;
-        const float *xy0 = &nodes[cur].xy0.x, *xy1 = &nodes[cur].xy1.x, *z01 = &nodes[cur].z01.x;
-        float u[6];
-        u[0] = fminf(ld_f(xy0 + 0), ld_f(xy1 + 0));
-        u[1] = fmaxf(ld_f(xy0 + 1), ld_f(xy1 + 1));
-        u[2] = fminf(ld_f(xy0 + 2), ld_f(xy1 + 2));
-        u[3] = fmaxf(ld_f(xy0 + 3), ld_f(xy1 + 3));
-        u[4] = fminf(ld_f(z01 + 0), ld_f(z01 + 2));
-        u[5] = fmaxf(ld_f(z01 + 1), ld_f(z01 + 3));
-        const int4 pch = nodes[parent].ch;
-        store_child_box(&nodes[parent], pch.x == cur ? 0 : 1, u);
-        __threadfence();
-        pending = (pch.x >= 0) + (pch.y >= 0);
-        if (atomicAdd(&cnt[parent], 1) != pending)
-            break;
-        cur = parent;
+    for (int level = kMaxNodeDepth; level >= 0; --level) {
+        for (int m = threadIdx.x; m < nn; m += kRefitBlock) {
+            const int4 ch = nodes[m].ch;
+            if (ch.w != level)
+                continue;
+            float b0[6], b1[6];
+            if (ch.x < 0)
+                leaf_box(recs, ch.x, b0);
+            else
+                node_box(nodes[ch.x], b0);
+            if (ch.y < 0)
+                leaf_box(recs, ch.y, b1);
+            else
+                node_box(nodes[ch.y], b1);
+            Node &nd = nodes[m];
+            nd.xy0 = make_float4(b0[0], b0[1], b0[2], b0[3]);
+            nd.xy1 = make_float4(b1[0], b1[1], b1[2], b1[3]);
+            nd.z01 = make_float4(b0[4], b0[5], b1[4], b1[5]);
+        }
+        __syncthreads();
     }
 }
 
@@ -560,9 +608,9 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
 
 hipError_t launch_refit(const BuildView &v, hipStream_t st)
 {
-    if (v.n_tris == 0)
+    if (v.n_envs == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_refit, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
+    hipLaunchKernelGGL(k_refit, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
     return hipGetLastError();
 }
 

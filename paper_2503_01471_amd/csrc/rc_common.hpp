@@ -24,7 +24,7 @@ struct alignas(16) Node {
     float4 xy0;  // child 0: lo.x hi.x lo.y hi.y
     float4 xy1;  // child 1: lo.x hi.x lo.y hi.y
     float4 z01;  // lo0.z hi0.z lo1.z hi1.z
-    int4 ch;     // child0, child1, parent (-1 at the root), unused
+    int4 ch;     // child0, child1, parent (-1 at the root), depth (root 0)
 };
 static_assert(sizeof(Node) == 64, "node is one 64-byte fetch");
 
@@ -92,14 +92,13 @@ struct BuildView {
     const int32_t *proto_tri;    // prototype triangles (global vertex indices)
     const float *inst_T;         // [I][12]
     float *world;                // [N][9] original order
-    float4 *box_lo, *box_hi, *cen;  // [N] build scratch
+    float4 *box_lo, *box_hi;     // [N] build scratch
     int32_t *prim, *tmp;         // [N] build scratch
     Node *nodes;                 // [N]
     TriRec *recs;                // [N]
     int32_t *pos_of;             // [N] leaf position of env-local id
     int32_t *env_root;           // [E]
     int32_t *env_nodes;          // [E] internal nodes per environment
-    int32_t *refit_cnt;          // [N] refit arrival counters (kept at zero)
 };
 
 // ---------------------------------------------------------------------------
