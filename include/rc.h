@@ -205,7 +205,8 @@ rc_status rc_debug_rays(rc_context *ctx, int32_t s, int64_t n, const int64_t *ra
 /* (lo xyz, hi xyz), child refs int32[n][2] (>= 0 internal node, < 0 leaf    */
 /* ~(first<<3 | (count-1)) over leaf positions), parent int32[n]; leaf_ids   */
 /* int32[n_tris] env-local triangle id at each leaf position; root ref.      */
-/* Buffers must hold n_tris entries (n_nodes <= n_tris).                     */
+/* Node buffers must hold n_tris + n_tris/4 + 2 entries (the node slots of   */
+/* the environment; slots not reachable from the root carry parent -1).      */
 rc_status rc_debug_bvh(rc_context *ctx, int32_t e, int32_t *n_nodes, float *boxes, int32_t *children,
                        int32_t *parent, int32_t *leaf_ids, int32_t *root);
 

@@ -104,7 +104,7 @@ struct Scene {
     std::vector<int64_t> env_tri_off;  // host copy
     std::vector<int64_t> inst_offsets;
     DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
-    DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes;
+    DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, env_micro, micro;
     bool poses_set = false;
     bool built = false;
 
@@ -129,6 +129,8 @@ struct Scene {
         v.pos_of = pos_of.as<int32_t>();
         v.env_root = env_root.as<int32_t>();
         v.env_nodes = env_nodes.as<int32_t>();
+        v.env_micro = env_micro.as<int32_t>();
+        v.micro = micro.as<int4>();
         return v;
     }
     SceneView sview() const
@@ -360,11 +362,13 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->box_hi, 16 * N));
     RC_TRY(c->pool.alloc(sc->prim, 4 * N));
     RC_TRY(c->pool.alloc(sc->tmp, 4 * N));
-    RC_TRY(c->pool.alloc(sc->nodes, sizeof(Node) * N));
+    RC_TRY(c->pool.alloc(sc->nodes, sizeof(Node) * (size_t)(node_base(N, n_envs) + 16)));
     RC_TRY(c->pool.alloc(sc->recs, sizeof(TriRec) * N));
     RC_TRY(c->pool.alloc(sc->pos_of, 4 * N));
     RC_TRY(c->pool.alloc(sc->env_root, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->env_nodes, 4 * (size_t)n_envs));
+    RC_TRY(c->pool.alloc(sc->env_micro, 4 * (size_t)n_envs));
+    RC_TRY(c->pool.alloc(sc->micro, 16 * N));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);
@@ -714,7 +718,8 @@ rc_status rc_debug_bvh(rc_context *c, int32_t e, int32_t *n_nodes, float *boxes,
     std::vector<Node> nodes(nn);
     std::vector<TriRec> recs(n);
     if (nn)
-        RC_HIP(hipMemcpy(nodes.data(), sc.nodes.as<Node>() + base, sizeof(Node) * nn, hipMemcpyDeviceToHost));
+        RC_HIP(hipMemcpy(nodes.data(), sc.nodes.as<Node>() + node_base(base, e), sizeof(Node) * nn,
+                         hipMemcpyDeviceToHost));
     if (n)
         RC_HIP(hipMemcpy(recs.data(), sc.recs.as<TriRec>() + base, sizeof(TriRec) * n, hipMemcpyDeviceToHost));
     *n_nodes = nn;

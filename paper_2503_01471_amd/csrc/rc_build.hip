@@ -143,7 +143,8 @@ __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 // stack is back at its height, is one of its descendants.
 // ---------------------------------------------------------------------------
 constexpr int kTaskCap = kMaxNodeDepth + 4;
-constexpr int kSmall = 128;
+constexpr int kSmall = 128;   // subtrees up to this size are built from LDS
+constexpr int kMicro = 16;    // ranges of 5..16 go to the per-thread builder
 
 struct WaveBox {
     float lx, ly, lz, hx, hy, hz;
@@ -178,6 +179,13 @@ struct BuildShared {
     int perm2[kSmall];
 };
 
+__device__ __forceinline__ void write_boxes(Node &nd, const WaveBox &L, const WaveBox &R)
+{
+    nd.xy0 = make_float4(expand_lo(L.lx), expand_hi(L.hx), expand_lo(L.ly), expand_hi(L.hy));
+    nd.xy1 = make_float4(expand_lo(R.lx), expand_hi(R.hx), expand_lo(R.ly), expand_hi(R.hy));
+    nd.z01 = make_float4(expand_lo(L.lz), expand_hi(L.hz), expand_lo(R.lz), expand_hi(R.hz));
+}
+
 __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 {
     const int e = blockIdx.x;
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
     const int n = (int)(v.env_tri_off[e + 1] - base);
     int32_t *prim = v.prim + base;
     int32_t *tmp = v.tmp + base;
-    Node *nodes = v.nodes + base;
+    Node *nodes = v.nodes + node_base(base, e);
     const float4 *blo = v.box_lo + base;
     const float4 *bhi = v.box_hi + base;
     __shared__ BuildShared S;
@@ -198,12 +206,15 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
         if (lane == 0) {
             v.env_root[e] = kEmptyRoot;
             v.env_nodes[e] = 0;
+            v.env_micro[e] = 0;
         }
         return;
     }
     __syncthreads();
     bool local = false;
     int b0 = 0, cnt0 = 0, h0 = 0;
+    int nm = 0;  // deferred small ranges of this environment
+    int4 *micro = v.micro + base;
 
     // bounds of the primitive at list position i (global list or LDS copy)
     auto box_at = [&](int i, float &lx, float &ly, float &lz, float &hx, float &hy, float &hz) {
@@ -445,30 +456,42 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
             const int nl = mid - b, nr = en - mid;
             if (lane == 0) {
                 Node &nd = nodes[id];
-                nd.xy0 = make_float4(expand_lo(L.lx), expand_hi(L.hx), expand_lo(L.ly), expand_hi(L.hy));
-                nd.xy1 = make_float4(expand_lo(R.lx), expand_hi(R.hx), expand_lo(R.ly), expand_hi(R.hy));
-                nd.z01 = make_float4(expand_lo(L.lz), expand_hi(L.hz), expand_lo(R.lz), expand_hi(R.hz));
+                write_boxes(nd, L, R);
                 if (nl <= kLeafMax)
                     nd.ch.x = leaf_ref(b, nl);
                 if (nr <= kLeafMax)
                     nd.ch.y = leaf_ref(mid, nr);
             }
-            // push right then left so that the left child is popped next
-            if (nr > kLeafMax) {
-                S.tp[sp] = id;
-                S.ts[sp] = 1;
-                S.tb[sp] = mid;
-                S.te[sp] = en;
-                S.td[sp] = depth + 1;
-                ++sp;
-            }
-            if (nl > kLeafMax) {
-                S.tp[sp] = id;
-                S.ts[sp] = 0;
-                S.tb[sp] = b;
-                S.te[sp] = mid;
-                S.td[sp] = depth + 1;
-                ++sp;
+            // Children of 5..kMicro primitives are deferred to k_build_micro
+            // (their node id is assigned now, plus two reserved ids for the
+            // second level of a range above 8); larger ones are pushed, right
+            // first so that the left child is popped next.
+            const int cb[2] = {b, mid}, ce[2] = {mid, en};
+            for (int sd = 1; sd >= 0; --sd) {
+                const int c = ce[sd] - cb[sd];
+                if (c <= kLeafMax)
+                    continue;
+                if (c <= kMicro) {
+                    const int cid = n_nodes;
+                    n_nodes += c > 2 * kLeafMax ? 3 : 1;
+                    if (lane == 0) {
+                        if (sd == 0)
+                            nodes[id].ch.x = cid;
+                        else
+                            nodes[id].ch.y = cid;
+                        nodes[cid].ch.z = id;
+                        nodes[cid].ch.w = depth + 1;
+                        micro[nm] = make_int4(cid, cb[sd], ce[sd], depth + 1);
+                    }
+                    ++nm;
+                } else {
+                    S.tp[sp] = id;
+                    S.ts[sp] = sd;
+                    S.tb[sp] = cb[sd];
+                    S.te[sp] = ce[sd];
+                    S.td[sp] = depth + 1;
+                    ++sp;
+                }
             }
             __syncthreads();
             if (local && sp == h0) {
@@ -480,20 +503,205 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
             }
         }
     }
-    if (lane == 0)
+    if (lane == 0) {
         v.env_nodes[e] = n_nodes;
-    __syncthreads();
-    // leaf-ordered records and the inverse permutation
-    for (int i = lane; i < n; i += 64) {
-        const int id = prim[i];
-        const float *w = v.world + 9 * (base + id);
-        TriRec rec;
-        rec.a = make_float4(w[0], w[1], w[2], w[3]);
-        rec.b = make_float4(w[4], w[5], w[6], w[7]);
-        rec.c = make_float4(w[8], __int_as_float(id), 0.f, 0.f);
-        v.recs[base + i] = rec;
-        v.pos_of[base + id] = i;
+        v.env_micro[e] = nm;
     }
+}
+
+// ---------------------------------------------------------------------------
+// K5b: ranges of 5..16 primitives deferred by k_build_sah, one per thread.
+// Full-sweep SAH over the three centroid axes with both sides limited to
+// `cap` primitives (8 for the top split, so each side is a leaf or one more
+// node with two leaves; 4 below).  Sorting is an odd-even transposition
+// network on (centroid, position), so the result is deterministic.  The
+// range's bounds live in this thread's LDS slice.
+// ---------------------------------------------------------------------------
+constexpr int kMicroBlock = 64;
+
+struct MicroShared {
+    float box[6][kMicro][kMicroBlock];
+    int pid[kMicro][kMicroBlock];
+};
+
+template <int N>
+__device__ __forceinline__ int micro_split(const MicroShared &M, int t, int *slot_out, int first, int cnt, int cap,
+                                           WaveBox &L, WaveBox &R)
+{
+    float key[N];
+    int os[N];  // (original position << 8) | slot
+    float best_cost = INFINITY;
+    int best_axis = 0, best_k = cnt / 2;
+    const int kmin = cnt - cap > 1 ? cnt - cap : 1;
+    const int kmax = cap < cnt - 1 ? cap : cnt - 1;
+#pragma unroll 1
+    for (int axis = 0; axis <= 3; ++axis) {
+        const int a = axis < 3 ? axis : best_axis;  // pass 3 re-sorts along the chosen axis
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (k < cnt) {
+                const int q = slot_out[first + k];
+                key[k] = 0.5f * (M.box[a][q][t] + M.box[a + 3][q][t]);
+                os[k] = (k << 8) | q;
+            } else {
+                key[k] = INFINITY;
+                os[k] = ((N + k) << 8);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+#pragma unroll
+            for (int i = (r & 1); i + 1 < N; i += 2) {
+                const bool sw = key[i] > key[i + 1] || (key[i] == key[i + 1] && os[i] > os[i + 1]);
+                const float tk = sw ? key[i + 1] : key[i], uk = sw ? key[i] : key[i + 1];
+                const int to = sw ? os[i + 1] : os[i], uo = sw ? os[i] : os[i + 1];
+                key[i] = tk;
+                key[i + 1] = uk;
+                os[i] = to;
+                os[i + 1] = uo;
+            }
+        }
+        if (axis == 3)
+            break;
+        float ra[N];  // half area of the suffix [k, cnt)
+        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+#pragma unroll
+        for (int k = N - 1; k >= 1; --k) {
+            if (k < cnt) {
+                const int q = os[k] & 255;
+                lx = fminf(lx, M.box[0][q][t]);
+                ly = fminf(ly, M.box[1][q][t]);
+                lz = fminf(lz, M.box[2][q][t]);
+                hx = fmaxf(hx, M.box[3][q][t]);
+                hy = fmaxf(hy, M.box[4][q][t]);
+                hz = fmaxf(hz, M.box[5][q][t]);
+            }
+            ra[k] = half_area(lx, ly, lz, hx, hy, hz);
+        }
+        lx = ly = lz = INFINITY;
+        hx = hy = hz = -INFINITY;
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            const int q = os[k - 1] & 255;
+            lx = fminf(lx, M.box[0][q][t]);
+            ly = fminf(ly, M.box[1][q][t]);
+            lz = fminf(lz, M.box[2][q][t]);
+            hx = fmaxf(hx, M.box[3][q][t]);
+            hy = fmaxf(hy, M.box[4][q][t]);
+            hz = fmaxf(hz, M.box[5][q][t]);
+            if (k >= kmin && k <= kmax && k < cnt) {
+                const float c = half_area(lx, ly, lz, hx, hy, hz) * (float)k + ra[k] * (float)(cnt - k);
+                if (c < best_cost) {
+                    best_cost = c;
+                    best_axis = axis;
+                    best_k = k;
+                }
+            }
+        }
+    }
+    L = WaveBox{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    R = L;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (k < cnt) {
+            const int q = os[k] & 255;
+            slot_out[first + k] = q;
+            WaveBox &B = k < best_k ? L : R;
+            B.lx = fminf(B.lx, M.box[0][q][t]);
+            B.ly = fminf(B.ly, M.box[1][q][t]);
+            B.lz = fminf(B.lz, M.box[2][q][t]);
+            B.hx = fmaxf(B.hx, M.box[3][q][t]);
+            B.hy = fmaxf(B.hy, M.box[4][q][t]);
+            B.hz = fmaxf(B.hz, M.box[5][q][t]);
+        }
+    }
+    return best_k;
+}
+
+__global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
+{
+    __shared__ MicroShared M;
+    const int t = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * kMicroBlock + t;
+    if (g >= v.n_tris)
+        return;
+    const int e = v.tri_env[g];
+    const int64_t base = v.env_tri_off[e];
+    const int j = (int)(g - base);
+    if (j >= v.env_micro[e])
+        return;
+    const int4 task = v.micro[base + j];  // node, begin, end, depth
+    int32_t *prim = v.prim + base;
+    Node *nodes = v.nodes + node_base(base, e);
+    const int cnt = task.z - task.y;
+    int slot[kMicro];
+#pragma unroll
+    for (int k = 0; k < kMicro; ++k) {
+        if (k < cnt) {
+            const int p = prim[task.y + k];
+            const float4 lo = v.box_lo[base + p], hi = v.box_hi[base + p];
+            M.box[0][k][t] = lo.x;
+            M.box[1][k][t] = lo.y;
+            M.box[2][k][t] = lo.z;
+            M.box[3][k][t] = hi.x;
+            M.box[4][k][t] = hi.y;
+            M.box[5][k][t] = hi.z;
+            M.pid[k][t] = p;
+        }
+        slot[k] = k;
+    }
+    WaveBox L, R;
+    // above 8 primitives each side may hold up to 8 (one more level); at most 8,
+    // both sides must be leaves (only one node id was reserved)
+    const int kb = micro_split<kMicro>(M, t, slot, 0, cnt, cnt > 2 * kLeafMax ? 2 * kLeafMax : kLeafMax, L, R);
+    write_boxes(nodes[task.x], L, R);
+    const int sub[2] = {0, kb}, sc[2] = {kb, cnt - kb};
+    int ref[2];
+    int next = task.x + 1;  // reserved ids (ranges above 8 only)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        if (sc[sd] <= kLeafMax) {
+            ref[sd] = leaf_ref(task.y + sub[sd], sc[sd]);
+        } else {
+            const int cid = next++;
+            ref[sd] = cid;
+            WaveBox L2, R2;
+            const int k2 = micro_split<2 * kLeafMax>(M, t, slot, sub[sd], sc[sd], kLeafMax, L2, R2);
+            Node &cn = nodes[cid];
+            write_boxes(cn, L2, R2);
+            cn.ch = make_int4(leaf_ref(task.y + sub[sd], k2), leaf_ref(task.y + sub[sd] + k2, sc[sd] - k2), task.x,
+                              task.w + 1);
+        }
+    }
+    // unused reserved ids: never referenced; a depth of -1 keeps refit away
+    if (cnt > 2 * kLeafMax)
+        for (int h = next; h < task.x + 3; ++h)
+            nodes[h].ch = make_int4(0, 0, -1, -1);
+    nodes[task.x].ch.x = ref[0];
+    nodes[task.x].ch.y = ref[1];
+#pragma unroll
+    for (int k = 0; k < kMicro; ++k)
+        if (k < cnt)
+            prim[task.y + k] = M.pid[slot[k]][t];
+}
+
+// K5c: leaf-ordered records and the inverse permutation, one thread per triangle.
+__global__ __launch_bounds__(256) void k_gather(BuildView v)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= v.n_tris)
+        return;
+    const int e = v.tri_env[g];
+    const int64_t base = v.env_tri_off[e];
+    const int i = (int)(g - base);
+    const int id = v.prim[g];
+    const float *w = v.world + 9 * (base + id);
+    TriRec rec;
+    rec.a = make_float4(w[0], w[1], w[2], w[3]);
+    rec.b = make_float4(w[4], w[5], w[6], w[7]);
+    rec.c = make_float4(w[8], __int_as_float(id), 0.f, 0.f);
+    v.recs[g] = rec;
+    v.pos_of[base + id] = i;
 }
 
 // ---------------------------------------------------------------------------
@@ -546,7 +754,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(BuildView v)
     const int e = blockIdx.x;
     const int64_t base = v.env_tri_off[e];
     const int nn = v.env_nodes[e];
-    Node *nodes = v.nodes + base;
+    Node *nodes = v.nodes + node_base(base, e);
     const TriRec *recs = v.recs + base;
     for (int level = kMaxNodeDepth; level >= 0; --level) {
         for (int m = threadIdx.x; m < nn; m += kRefitBlock) {
@@ -603,6 +811,13 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
     if (v.n_envs == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_build_sah, dim3(v.n_envs), dim3(64), 0, st, v);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || v.n_tris == 0)
+        return err;
+    hipLaunchKernelGGL(k_build_micro, dim3(blocks_for(v.n_tris, kMicroBlock)), dim3(kMicroBlock), 0, st, v);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
     return hipGetLastError();
 }
 

@@ -38,6 +38,11 @@ static_assert(sizeof(TriRec) == 48, "record is three 16-byte fetches");
 
 __host__ __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
 
+// First node slot of environment e (tri_off = env_tri_off[e]).  Each
+// environment gets n + n/4 + 2 slots for n triangles: internal nodes (< n)
+// plus the unused ids the builder may reserve for small ranges (< n/9).
+__host__ __device__ inline int64_t node_base(int64_t tri_off, int e) { return tri_off + (tri_off >> 2) + 2 * (int64_t)e; }
+
 // ---------------------------------------------------------------------------
 // Sensors.
 // ---------------------------------------------------------------------------
@@ -58,7 +63,7 @@ struct SensorModel {
 struct SceneView {
     const int64_t *env_tri_off;  // [E+1]
     const int32_t *env_root;     // [E]
-    const Node *nodes;           // [N] (env base = env_tri_off[e])
+    const Node *nodes;           // env e starts at node_base(env_tri_off[e], e)
     const TriRec *recs;          // [N] leaf order
     const int32_t *tri_seg;      // [N] global original order
     const float *world;          // [N][9] original order (reference path)
@@ -94,11 +99,13 @@ struct BuildView {
     float *world;                // [N][9] original order
     float4 *box_lo, *box_hi;     // [N] build scratch
     int32_t *prim, *tmp;         // [N] build scratch
-    Node *nodes;                 // [N]
+    Node *nodes;                 // env e starts at node_base(env_tri_off[e], e)
     TriRec *recs;                // [N]
     int32_t *pos_of;             // [N] leaf position of env-local id
     int32_t *env_root;           // [E]
-    int32_t *env_nodes;          // [E] internal nodes per environment
+    int32_t *env_nodes;          // [E] node slots per environment
+    int32_t *env_micro;          // [E] deferred small ranges per environment
+    int4 *micro;                 // [N] deferred ranges (node, begin, end, depth)
 };
 
 // ---------------------------------------------------------------------------

@@ -366,7 +366,7 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     gen_ray(se, t, row, col, r);
     Best b{r.tf, r.tf, -1, -1, false, 0.0};
     const int64_t base = sc.env_tri_off[t.env];
-    const Node *nodes = sc.nodes + base;
+    const Node *nodes = sc.nodes + node_base(base, t.env);
     const TriRec *recs = sc.recs + base;
     const int root = sc.env_root[t.env];
     if (root != kEmptyRoot)

@@ -238,11 +238,11 @@ def rc_debug_rays(ctx, s: int, ray_idx):
 
 
 def rc_debug_bvh(ctx, e: int, n_tris: int) -> dict:
-    cap = max(n_tris, 1)
+    cap = n_tris + n_tris // 4 + 2
     boxes = np.zeros((cap, 2, 6), np.float32)
     ch = np.zeros((cap, 2), np.int32)
     par = np.zeros(cap, np.int32)
-    ids = np.zeros(cap, np.int32)
+    ids = np.zeros(max(n_tris, 1), np.int32)
     nn = C.c_int32()
     root = C.c_int32()
     _check(lib().rc_debug_bvh(ctx, e, C.byref(nn), _ptr(boxes), _ptr(ch), _ptr(par), _ptr(ids), C.byref(root)))
