@@ -195,6 +195,86 @@ rc_status rc_render(rc_context *ctx, const rc_outputs *out, int32_t mode, void *
 rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
 
 /* ------------------------------------------------------------------------ */
+/* Batched form: launch choices and one captured graph per simulation step.  */
+/* ------------------------------------------------------------------------ */
+/* Choose the ray-tile shape (columns x rows of one 64-lane wavefront: 4x16, */
+/* 8x8, 16x4 or 32x2), the persistent grid size (1 or 2 workgroups per      */
+/* resident slot) and the queue order (largest estimated cost first, or     */
+/* natural) of the batched render by timing each combination on the loaded */
+/* scene, sensors and poses (temporary outputs are allocated within the     */
+/* budget).  cache_path (nullable): a text file of previous choices keyed   */
+/* by device and workload; a hit skips the timing, a miss appends a line.    */
+/* choice (nullable): host int32[3] = tile columns, grid scale, 1 if cost   */
+/* order.  Outputs are bit-identical for every choice.  Synchronous.        */
+rc_status rc_autotune(rc_context *ctx, const char *cache_path, int32_t *choice);
+/* Set those choices directly: choice host int32[3] = tile columns (4, 8,   */
+/* 16 or 32), grid scale (1 or 2), cost order (0 or 1).                     */
+rc_status rc_tuning_set(rc_context *ctx, const int32_t *choice);
+
+typedef struct rc_graph rc_graph;
+/* One simulation step captured as a HIP graph: dynamic instances move to the */
+/* graph's step counter s (translation fma(v, float(s)*dt, p0), see          */
+/* rc_move_instances), their triangles are re-transformed, every BVH is      */
+/* refitted, the work queue is reset and the batched render writes `out`;    */
+/* then s advances by one.  d_vel: caller device float[n_inst][3], read at   */
+/* every launch.  The graph is tied to the current scene and sensors: after  */
+/* rc_scene_load / rc_sensors_attach / rc_autotune its launch fails with     */
+/* RC_E_STATE.  Sensor poses are read at launch time (rc_set_sensor_poses).  */
+rc_status rc_step_graph_create(rc_context *ctx, const rc_outputs *out, const float *d_vel, float dt,
+                               rc_graph **graph);
+/* Set the step counter (asynchronous on `stream`). */
+rc_status rc_graph_set_step(rc_graph *graph, int32_t step, void *stream);
+rc_status rc_graph_launch(rc_graph *graph, void *stream);
+rc_status rc_graph_destroy(rc_graph *graph);
+
+/* ------------------------------------------------------------------------ */
+/* Served form: a request loop over the resident scene and BVHs.             */
+/* A request renders n_envs environments (ids into the loaded scene) with    */
+/* one sensor model at the given poses (host float[n_envs][12], nullable =   */
+/* the pose of each environment's first attached sensor instance, as set by  */
+/* rc_set_sensor_poses before rc_server_create).  Outputs: caller DEVICE     */
+/* buffers float depth / int32 seg [n_envs * rays of the model] (each        */
+/* nullable), ray-major per environment in request order, same values as    */
+/* rc_render; they must be ready when submitted (the server writes them on  */
+/* its own streams) and stay valid until the ticket completes.  Requests    */
+/* are admitted in arrival order while their in-flight */
+/* bytes (8 per ray of outputs + work lists) fit the server budget; in      */
+/* RC_SERVE_BATCHED mode every admission round merges the admitted requests */
+/* into one persistent launch on one of n_streams streams, so batches that   */
+/* arrive while others run overlap on the device (continuous batching);     */
+/* RC_SERVE_PLAIN renders requests one at a time, one launch per            */
+/* environment (the per-environment reference path).  While a server        */
+/* exists the context's scene, sensors and tuning are read-only (calls that */
+/* would change them return RC_E_BUSY).  Submit, poll and wait may be called */
+/* from any one client thread.                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct rc_server rc_server;
+typedef struct {
+    int32_t n_envs;
+    const int32_t *env_ids;
+    int32_t sensor_id;
+    const float *sensor_T;
+    float *depth;
+    int32_t *seg;
+} rc_request;
+#define RC_SERVE_PLAIN 0
+#define RC_SERVE_BATCHED 1
+
+rc_status rc_server_create(rc_context *ctx, int32_t mode, int32_t n_streams, size_t hbm_budget,
+                           rc_server **server);
+/* Non-blocking; host arrays are copied.  RC_E_OOM if the request alone     */
+/* exceeds the budget.  ticket: host uint64 (> 0).                          */
+rc_status rc_server_submit(rc_server *server, const rc_request *req, uint64_t *ticket);
+/* done = 1 once the request's outputs are written (device work complete);  */
+/* latency_s = completion time - submit time (host monotonic clock).  A      */
+/* completed ticket is released by the poll that reports it.                */
+rc_status rc_server_poll(rc_server *server, uint64_t ticket, int32_t *done, double *latency_s);
+/* Block until the ticket completes; releases it. */
+rc_status rc_server_wait(rc_server *server, uint64_t ticket, double *latency_s);
+/* Drains queued and running requests, then frees the server. */
+rc_status rc_server_destroy(rc_server *server);
+
+/* ------------------------------------------------------------------------ */
 /* Inspection (synchronous, host outputs; for validation).                   */
 /* ------------------------------------------------------------------------ */
 /* World triangles in global original order: host float[total_tris][9].      */

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librc.so")
-SOURCES = ["rc_build.hip", "rc_render.hip", "rc_api.cpp"]
+SOURCES = ["rc_build.hip", "rc_render.hip", "rc_api.cpp", "rc_batch.cpp", "rc_server.cpp"]
 ARCH = os.environ.get("RC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -16,13 +16,15 @@
 #include <string>
 #include <vector>
 
-#include "rc_common.hpp"
+#include "rc_runtime.hpp"
 
 using namespace rc;
 
-namespace {
+namespace rc {
 
+namespace {
 thread_local std::string g_err;
+}
 
 rc_status fail(rc_status s, const char *fmt, ...)
 {
@@ -35,171 +37,91 @@ rc_status fail(rc_status s, const char *fmt, ...)
     return s;
 }
 
-rc_status hip_fail(hipError_t e, const char *what)
-{
-    return fail(RC_E_HIP, "%s: %s", what, hipGetErrorString(e));
-}
+rc_status hip_fail(hipError_t e, const char *what) { return fail(RC_E_HIP, "%s: %s", what, hipGetErrorString(e)); }
 
-#define RC_HIP(call)                                  \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess)                         \
-            return hip_fail(e_, #call);               \
-    } while (0)
+const char *last_error() { return g_err.c_str(); }
 
-// Budgeted device allocation owned by a context.
-struct Pool;
-
-struct DBuf {
-    void *p = nullptr;
-    size_t n = 0;
-    Pool *pool = nullptr;
-    DBuf() = default;
-    DBuf(const DBuf &) = delete;
-    DBuf &operator=(const DBuf &) = delete;
-    ~DBuf();
-    template <class T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-struct Pool {
-    size_t budget = 0;
-    size_t used = 0;
-    rc_status alloc(DBuf &b, size_t bytes)
-    {
-        if (bytes == 0)
-            bytes = 16;
-        if (budget && used + bytes > budget)
-            return fail(RC_E_OOM, "memory budget exceeded: %zu used + %zu requested > %zu", used, bytes, budget);
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(RC_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-        }
-        b.p = p;
-        b.n = bytes;
-        b.pool = this;
-        used += bytes;
-        return RC_OK;
-    }
-};
-
-DBuf::~DBuf()
+void DBuf::reset()
 {
     if (p) {
         (void)hipFree(p);
         if (pool)
             pool->used -= n;
     }
+    p = nullptr;
+    n = 0;
 }
 
-struct Mesh {
-    int64_t vert_off, n_verts, tri_off, n_tris;
-};
-
-struct Scene {
-    int32_t n_envs = 0;
-    int64_t n_inst = 0, n_tris = 0, n_dyn = 0;
-    std::vector<int64_t> env_tri_off;  // host copy
-    std::vector<int64_t> inst_offsets;
-    DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
-    DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, env_micro, micro;
-    bool poses_set = false;
-    bool built = false;
-
-    BuildView view() const
-    {
-        BuildView v;
-        v.n_envs = n_envs;
-        v.n_tris = n_tris;
-        v.env_tri_off = d_env_tri_off.as<int64_t>();
-        v.tri_env = tri_env.as<int32_t>();
-        v.tri_src = tri_src.as<int2>();
-        v.proto_xyz = proto_xyz.as<float>();
-        v.proto_tri = proto_tri.as<int32_t>();
-        v.inst_T = inst_T.as<float>();
-        v.world = world.as<float>();
-        v.box_lo = box_lo.as<float4>();
-        v.box_hi = box_hi.as<float4>();
-        v.prim = prim.as<int32_t>();
-        v.tmp = tmp.as<int32_t>();
-        v.nodes = nodes.as<Node>();
-        v.recs = recs.as<TriRec>();
-        v.pos_of = pos_of.as<int32_t>();
-        v.env_root = env_root.as<int32_t>();
-        v.env_nodes = env_nodes.as<int32_t>();
-        v.env_micro = env_micro.as<int32_t>();
-        v.micro = micro.as<int4>();
-        return v;
-    }
-    SceneView sview() const
-    {
-        SceneView s;
-        s.env_tri_off = d_env_tri_off.as<int64_t>();
-        s.env_root = env_root.as<int32_t>();
-        s.nodes = nodes.as<Node>();
-        s.recs = recs.as<TriRec>();
-        s.tri_seg = tri_seg.as<int32_t>();
-        s.world = world.as<float>();
-        s.n_envs = n_envs;
-        return s;
-    }
-};
-
-struct ModelHost {
-    SensorModel m;
-    std::vector<float> table;  // lidar / table directions (FP32)
-};
-
-struct Sensors {
-    int64_t n_si = 0, n_items = 0, total_rays = 0;
-    std::vector<int64_t> ray_off, item_off;
-    DBuf models, tables, si_env, si_model, d_ray_off, pose, items, lpt_items, head, counters;
-    bool poses_set = false;
-
-    SensorView view() const
-    {
-        SensorView v;
-        v.models = models.as<SensorModel>();
-        v.tables = tables.as<float>();
-        v.si_env = si_env.as<int32_t>();
-        v.si_model = si_model.as<int32_t>();
-        v.ray_off = d_ray_off.as<int64_t>();
-        v.pose = pose.as<float>();
-        v.items = items.as<int2>();
-        return v;
-    }
-};
-
-}  // namespace
-
-struct rc_context {
-    int32_t device = 0;
-    hipStream_t stream = nullptr;
-    Pool pool;
-    std::vector<float> mesh_xyz;
-    std::vector<int32_t> mesh_tri;  // global vertex indices
-    std::vector<Mesh> meshes;
-    std::vector<ModelHost> models;
-    std::unique_ptr<Scene> scene;
-    std::unique_ptr<Sensors> sensors;
-    int batched_grid = 0;
-};
-
-namespace {
-
-hipStream_t pick(const rc_context *c, void *stream) { return stream ? (hipStream_t)stream : c->stream; }
-
-template <class T>
-rc_status upload(rc_context *c, DBuf &b, const T *src, size_t count, hipStream_t st)
+rc_status Pool::alloc(DBuf &b, size_t bytes)
 {
-    rc_status s = c->pool.alloc(b, count * sizeof(T));
-    if (s != RC_OK)
-        return s;
-    if (count)
-        RC_HIP(hipMemcpyAsync(b.p, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+    b.reset();
+    if (bytes == 0)
+        bytes = 16;
+    if (budget && used + bytes > budget)
+        return fail(RC_E_OOM, "memory budget exceeded: %zu used + %zu requested > %zu", (size_t)used, bytes, budget);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RC_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    b.p = p;
+    b.n = bytes;
+    b.pool = this;
+    used += bytes;
     return RC_OK;
+}
+
+BuildView Scene::view() const
+{
+    BuildView v;
+    v.n_envs = n_envs;
+    v.n_tris = n_tris;
+    v.env_tri_off = d_env_tri_off.as<int64_t>();
+    v.tri_env = tri_env.as<int32_t>();
+    v.tri_src = tri_src.as<int2>();
+    v.proto_xyz = proto_xyz.as<float>();
+    v.proto_tri = proto_tri.as<int32_t>();
+    v.inst_T = inst_T.as<float>();
+    v.world = world.as<float>();
+    v.box_lo = box_lo.as<float4>();
+    v.box_hi = box_hi.as<float4>();
+    v.prim = prim.as<int32_t>();
+    v.tmp = tmp.as<int32_t>();
+    v.nodes = nodes.as<Node>();
+    v.recs = recs.as<TriRec>();
+    v.pos_of = pos_of.as<int32_t>();
+    v.env_root = env_root.as<int32_t>();
+    v.env_nodes = env_nodes.as<int32_t>();
+    v.env_micro = env_micro.as<int32_t>();
+    v.micro = micro.as<int4>();
+    return v;
+}
+
+SceneView Scene::sview() const
+{
+    SceneView s;
+    s.env_tri_off = d_env_tri_off.as<int64_t>();
+    s.env_root = env_root.as<int32_t>();
+    s.nodes = nodes.as<Node>();
+    s.recs = recs.as<TriRec>();
+    s.tri_seg = tri_seg.as<int32_t>();
+    s.world = world.as<float>();
+    s.n_envs = n_envs;
+    return s;
+}
+
+SensorView Sensors::view() const
+{
+    SensorView v;
+    v.models = models.as<SensorModel>();
+    v.tables = tables.as<float>();
+    v.si_env = si_env_d.as<int32_t>();
+    v.si_model = si_model_d.as<int32_t>();
+    v.ray_off = d_ray_off.as<int64_t>();
+    v.pose = pose.as<float>();
+    v.items = items.as<int2>();
+    return v;
 }
 
 rc_status set_device(const rc_context *c)
@@ -208,19 +130,95 @@ rc_status set_device(const rc_context *c)
     return RC_OK;
 }
 
-#define RC_CHECK(cond, ...)                            \
-    do {                                               \
-        if (!(cond))                                   \
-            return fail(RC_E_INVALID, __VA_ARGS__);    \
-    } while (0)
-#define RC_TRY(expr)                                   \
-    do {                                               \
-        rc_status s_ = (expr);                         \
-        if (s_ != RC_OK)                               \
-            return s_;                                 \
-    } while (0)
+}  // namespace rc
+
+namespace {
+
+hipStream_t pick(const rc_context *c, void *stream) { return stream ? (hipStream_t)stream : c->stream; }
+
+template <class T>
+rc_status upload(rc_context *c, DBuf &b, const T *src, size_t count, hipStream_t st)
+{
+    RC_TRY(c->pool.alloc(b, count * sizeof(T)));
+    if (count)
+        RC_HIP(hipMemcpyAsync(b.p, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+    return RC_OK;
+}
+
+rc_status busy_check(const rc_context *c)
+{
+    if (c->servers.load() > 0)
+        return fail(RC_E_BUSY, "a request server is using this context");
+    return RC_OK;
+}
+
+// Models with the current tile shape, concatenated direction tables.
+void models_for(const rc_context *c, std::vector<SensorModel> &models, std::vector<float> &tables)
+{
+    models.clear();
+    tables.clear();
+    for (const ModelHost &h : c->models) {
+        SensorModel m = h.m;
+        m.tw_shift = c->tuning.tw_shift;
+        const int tw = 1 << m.tw_shift, th = 64 >> m.tw_shift;
+        m.tiles_x = (m.W + tw - 1) / tw;
+        m.tiles = m.tiles_x * ((m.H + th - 1) / th);
+        m.table_off = (int64_t)tables.size() / 3;
+        tables.insert(tables.end(), h.table.begin(), h.table.end());
+        models.push_back(m);
+    }
+}
 
 }  // namespace
+
+namespace rc {
+
+rc_status rebuild_items(rc_context *c, Sensors &se)
+{
+    const Scene &sc = *c->scene;
+    hipStream_t st = c->stream;
+    std::vector<SensorModel> models;
+    std::vector<float> tables;
+    models_for(c, models, tables);
+    const int64_t S = se.n_si;
+    se.item_off.assign(S + 1, 0);
+    for (int64_t s = 0; s < S; ++s)
+        se.item_off[s + 1] = se.item_off[s] + models[se.si_model[s]].tiles;
+    se.n_items = se.item_off[S];
+    RC_CHECK(se.n_items < INT32_MAX, "too many tiles");
+    std::vector<int2> items(se.n_items);
+    for (int64_t s = 0; s < S; ++s)
+        for (int64_t k = se.item_off[s]; k < se.item_off[s + 1]; ++k)
+            items[k] = make_int2((int)s, (int)(k - se.item_off[s]));
+    // queue order of the persistent form: sensor instances by estimated cost
+    // (rays x log2 of the environment's triangle count), largest first; the
+    // tiles of one instance stay together
+    std::vector<int64_t> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    if (c->tuning.lpt) {
+        std::vector<double> cost(S);
+        for (int64_t s = 0; s < S; ++s) {
+            const int e = se.si_env[s];
+            const double ntri = (double)(sc.env_tri_off[e + 1] - sc.env_tri_off[e]);
+            cost[s] = (double)(se.ray_off[s + 1] - se.ray_off[s]) * log2(ntri + 2.0);
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    }
+    std::vector<int2> lpt;
+    lpt.reserve(se.n_items);
+    for (int64_t s : order)
+        for (int64_t k = se.item_off[s]; k < se.item_off[s + 1]; ++k)
+            lpt.push_back(items[k]);
+    RC_HIP(hipStreamSynchronize(st));  // previous users of the old lists are done
+    RC_TRY(upload(c, se.models, models.data(), models.size(), st));
+    RC_TRY(upload(c, se.tables, tables.data(), tables.size(), st));
+    RC_TRY(upload(c, se.items, items.data(), items.size(), st));
+    RC_TRY(upload(c, se.lpt_items, lpt.data(), lpt.size(), st));
+    RC_HIP(hipStreamSynchronize(st));
+    return RC_OK;
+}
+
+}  // namespace rc
 
 extern "C" {
 
@@ -238,7 +236,7 @@ const char *rc_status_string(rc_status s)
     }
 }
 
-const char *rc_last_error(void) { return g_err.c_str(); }
+const char *rc_last_error(void) { return rc::last_error(); }
 
 rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context **out)
 {
@@ -252,7 +250,13 @@ rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context 
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->pool.budget = hbm_budget;
-    c->batched_grid = batched_grid_size(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return fail(RC_E_HIP, "hipGetDeviceProperties failed");
+    }
+    c->n_cu = prop.multiProcessorCount;
+    c->blocks_per_cu = batched_blocks_per_cu();
     *out = c;
     return RC_OK;
 }
@@ -261,6 +265,7 @@ rc_status rc_destroy(rc_context *c)
 {
     if (!c)
         return RC_OK;
+    RC_TRY(busy_check(c));
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->sensors.reset();
@@ -299,6 +304,7 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
                         const int32_t *inst_seg, const uint8_t *inst_dynamic)
 {
     RC_CHECK(c, "NULL context");
+    RC_TRY(busy_check(c));
     RC_CHECK(n_envs >= 0, "n_envs < 0");
     RC_CHECK(inst_offsets, "inst_offsets is NULL");
     RC_CHECK(inst_offsets[0] == 0, "inst_offsets[0] != 0");
@@ -372,6 +378,7 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);
+    ++c->generation;
     return RC_OK;
 }
 
@@ -388,8 +395,9 @@ rc_status rc_sensor_add(rc_context *c, const rc_sensor_desc *d, int32_t *sensor_
     m.kind = d->kind;
     m.W = d->width;
     m.H = d->height;
-    m.tiles_x = (d->width + 7) / 8;
-    m.tiles = m.tiles_x * ((d->height + 7) / 8);
+    m.tw_shift = 3;
+    m.tiles_x = 0;  // set per tile shape when work lists are built
+    m.tiles = 0;
     m.hw = (float)d->width * 0.5f;
     m.hh = (float)d->height * 0.5f;
     m.tn = d->near_;
@@ -431,6 +439,7 @@ rc_status rc_sensor_add(rc_context *c, const rc_sensor_desc *d, int32_t *sensor_
 rc_status rc_sensors_attach(rc_context *c, const int64_t *sens_offsets, const int32_t *sensor_ids)
 {
     RC_CHECK(c && sens_offsets, "NULL argument");
+    RC_TRY(busy_check(c));
     if (!c->scene)
         return fail(RC_E_STATE, "rc_sensors_attach before rc_scene_load");
     const Scene &sc = *c->scene;
@@ -447,63 +456,28 @@ rc_status rc_sensors_attach(rc_context *c, const int64_t *sens_offsets, const in
     hipStream_t st = c->stream;
     auto se = std::make_unique<Sensors>();
     se->n_si = S;
-    // models + concatenated tables
-    std::vector<SensorModel> models;
-    std::vector<float> tables;
-    for (const ModelHost &h : c->models) {
-        SensorModel m = h.m;
-        m.table_off = (int64_t)tables.size() / 3;
-        tables.insert(tables.end(), h.table.begin(), h.table.end());
-        models.push_back(m);
-    }
-    std::vector<int32_t> si_env(S), si_model(S);
+    se->sens_offsets.assign(sens_offsets, sens_offsets + E + 1);
+    se->si_env.assign(S, 0);
+    se->si_model.assign(S, 0);
     se->ray_off.assign(S + 1, 0);
-    se->item_off.assign(S + 1, 0);
     for (int32_t e = 0; e < E; ++e)
         for (int64_t s = sens_offsets[e]; s < sens_offsets[e + 1]; ++s)
-            si_env[s] = e;
+            se->si_env[s] = e;
     for (int64_t s = 0; s < S; ++s) {
-        si_model[s] = sensor_ids[s];
-        const SensorModel &m = models[sensor_ids[s]];
+        se->si_model[s] = sensor_ids[s];
+        const SensorModel &m = c->models[sensor_ids[s]].m;
         se->ray_off[s + 1] = se->ray_off[s] + (int64_t)m.W * m.H;
-        se->item_off[s + 1] = se->item_off[s] + m.tiles;
     }
     se->total_rays = se->ray_off[S];
-    se->n_items = se->item_off[S];
-    RC_CHECK(se->n_items < INT32_MAX, "too many tiles");
-    std::vector<int2> items(se->n_items);
-    for (int64_t s = 0; s < S; ++s)
-        for (int64_t k = se->item_off[s]; k < se->item_off[s + 1]; ++k)
-            items[k] = make_int2((int)s, (int)(k - se->item_off[s]));
-    // queue order for the persistent form: sensor instances by estimated cost
-    // (rays x log2 of the environment's triangle count), largest first; the
-    // tiles of one instance stay together
-    std::vector<int64_t> order(S);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(S);
-    for (int64_t s = 0; s < S; ++s) {
-        const int e = si_env[s];
-        const double ntri = (double)(sc.env_tri_off[e + 1] - sc.env_tri_off[e]);
-        cost[s] = (double)(se->ray_off[s + 1] - se->ray_off[s]) * log2(ntri + 2.0);
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-    std::vector<int2> lpt;
-    lpt.reserve(se->n_items);
-    for (int64_t s : order)
-        for (int64_t k = se->item_off[s]; k < se->item_off[s + 1]; ++k)
-            lpt.push_back(items[k]);
-    RC_TRY(upload(c, se->models, models.data(), models.size(), st));
-    RC_TRY(upload(c, se->tables, tables.data(), tables.size(), st));
-    RC_TRY(upload(c, se->si_env, si_env.data(), S, st));
-    RC_TRY(upload(c, se->si_model, si_model.data(), S, st));
+    RC_TRY(upload(c, se->si_env_d, se->si_env.data(), S, st));
+    RC_TRY(upload(c, se->si_model_d, se->si_model.data(), S, st));
     RC_TRY(upload(c, se->d_ray_off, se->ray_off.data(), S + 1, st));
-    RC_TRY(upload(c, se->items, items.data(), items.size(), st));
-    RC_TRY(upload(c, se->lpt_items, lpt.data(), lpt.size(), st));
     RC_TRY(c->pool.alloc(se->pose, 48 * (size_t)S));
     RC_TRY(c->pool.alloc(se->head, 256));
     RC_TRY(c->pool.alloc(se->counters, 256));
-    RC_HIP(hipStreamSynchronize(st));
+    RC_TRY(rebuild_items(c, *se));
     c->sensors = std::move(se);
+    ++c->generation;
     return RC_OK;
 }
 
@@ -531,6 +505,7 @@ rc_status rc_env_tri_offsets(const rc_context *c, int64_t *off)
 rc_status rc_set_instance_poses(rc_context *c, const float *d_inst_T, void *stream)
 {
     RC_CHECK(c, "NULL context");
+    RC_TRY(busy_check(c));
     if (!c->scene)
         return fail(RC_E_STATE, "no scene loaded");
     Scene &sc = *c->scene;
@@ -562,13 +537,14 @@ rc_status rc_set_sensor_poses(rc_context *c, const float *d_sensor_T, void *stre
 rc_status rc_move_instances(rc_context *c, const float *d_vel, int32_t step, float dt, void *stream)
 {
     RC_CHECK(c, "NULL context");
+    RC_TRY(busy_check(c));
     if (!c->scene || !c->scene->poses_set)
         return fail(RC_E_STATE, "instance poses not set");
     Scene &sc = *c->scene;
     RC_CHECK(sc.n_inst == 0 || d_vel, "d_vel is NULL");
     RC_CHECK(isfinite(dt), "dt not finite");
     RC_TRY(set_device(c));
-    RC_HIP(launch_move(sc.n_inst, sc.inst_T0.as<float>(), d_vel, sc.inst_dyn.as<uint8_t>(), step, dt,
+    RC_HIP(launch_move(sc.n_inst, sc.inst_T0.as<float>(), d_vel, sc.inst_dyn.as<uint8_t>(), step, nullptr, dt,
                        sc.inst_T.as<float>(), pick(c, stream)));
     return RC_OK;
 }
@@ -576,6 +552,7 @@ rc_status rc_move_instances(rc_context *c, const float *d_vel, int32_t step, flo
 rc_status rc_build(rc_context *c, int32_t builder, void *stream)
 {
     RC_CHECK(c, "NULL context");
+    RC_TRY(busy_check(c));
     RC_CHECK(builder == RC_BUILD_SAH, "unknown builder %d", builder);
     if (!c->scene || !c->scene->poses_set)
         return fail(RC_E_STATE, "rc_build needs a scene and instance poses");
@@ -592,6 +569,7 @@ rc_status rc_build(rc_context *c, int32_t builder, void *stream)
 rc_status rc_refit(rc_context *c, void *stream)
 {
     RC_CHECK(c, "NULL context");
+    RC_TRY(busy_check(c));
     if (!c->scene || !c->scene->built)
         return fail(RC_E_STATE, "rc_refit before rc_build");
     Scene &sc = *c->scene;
@@ -625,7 +603,7 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
     Sensors &se = *c->sensors;
     const SceneView sv = sc.sview();
     const SensorView ev = se.view();
-    const OutView ov{out->depth, out->seg, out->tri, out->hit_xyz};
+    const OutView ov{out->depth, out->seg, out->tri, out->hit_xyz, nullptr, nullptr};
     switch (mode) {
     case RC_RENDER_PLAIN:
         for (int64_t s = 0; s < se.n_si; ++s)
@@ -636,7 +614,7 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
         break;
     case RC_RENDER_BATCHED:
         RC_HIP(launch_render_batched(sv, ev, ov, se.lpt_items.as<int2>(), se.n_items, se.head.as<unsigned int>(),
-                                     c->batched_grid, st));
+                                     c->batched_grid(), st));
         break;
     case RC_RENDER_BRUTE:
         RC_HIP(launch_render_brute(sv, ev, ov, se.n_items, st));
@@ -652,7 +630,7 @@ rc_status rc_render_stats(rc_context *c, void *stream, int64_t *counters)
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
     Sensors &se = *c->sensors;
-    const OutView ov{nullptr, nullptr, nullptr, nullptr};
+    const OutView ov{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     RC_HIP(launch_fill_u32(se.counters.as<unsigned int>(), 8, 0u, st));
     RC_HIP(launch_render_stats(c->scene->sview(), se.view(), ov, se.n_items, se.counters.as<unsigned long long>(),
                                st));

@@ -1,0 +1,254 @@
+// rc_batch.cpp -- the batched form: autotuned launch choices and the
+// per-step HIP graph (motion -> transform -> refit -> queue reset -> render).
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include <string>
+#include <vector>
+
+#include "rc_runtime.hpp"
+
+using namespace rc;
+
+struct rc_graph {
+    rc_context *ctx = nullptr;
+    uint64_t generation = 0;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DBuf step;
+};
+
+namespace {
+
+rc_status ready(const rc_context *c)
+{
+    if (!c->scene || !c->scene->built)
+        return fail(RC_E_STATE, "needs a built scene");
+    if (!c->sensors || !c->sensors->poses_set)
+        return fail(RC_E_STATE, "needs attached sensors with poses");
+    return RC_OK;
+}
+
+std::string workload_key(const rc_context *c)
+{
+    hipDeviceProp_t p;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&p, c->device) == hipSuccess)
+        arch = p.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ' || ch == ':')
+            ch = '_';
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/cu%d/envs%d/tris%lld/rays%lld/si%lld", arch.c_str(), c->n_cu, c->scene->n_envs,
+             (long long)c->scene->n_tris, (long long)c->sensors->total_rays, (long long)c->sensors->n_si);
+    std::string key = buf;
+    for (const ModelHost &h : c->models) {
+        snprintf(buf, sizeof buf, "/m%d.%dx%d", h.m.kind, h.m.W, h.m.H);
+        key += buf;
+    }
+    return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
+{
+    RC_CHECK(c, "NULL context");
+    if (c->servers.load() > 0)
+        return fail(RC_E_BUSY, "a request server is using this context");
+    RC_TRY(ready(c));
+    RC_TRY(set_device(c));
+    Sensors &se = *c->sensors;
+    const Scene &sc = *c->scene;
+    const std::string key = workload_key(c);
+    Tuning best = c->tuning;
+    bool found = false;
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char k[1024];
+            int tw, gs, lpt;
+            while (fscanf(f, "%1023s %d %d %d", k, &tw, &gs, &lpt) == 4) {
+                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && (gs == 1 || gs == 2)) {
+                    best.tw_shift = __builtin_ctz(tw);
+                    best.grid_scale = gs;
+                    best.lpt = lpt != 0;
+                    found = true;
+                }
+            }
+            fclose(f);
+        }
+    }
+    if (!found) {
+        hipStream_t st = c->stream;
+        DBuf depth, seg;
+        RC_TRY(c->pool.alloc(depth, 4 * (size_t)se.total_rays));
+        RC_TRY(c->pool.alloc(seg, 4 * (size_t)se.total_rays));
+        const OutView ov{depth.as<float>(), seg.as<int32_t>(), nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t e0, e1;
+        RC_HIP(hipEventCreate(&e0));
+        RC_HIP(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        for (int tws = 2; tws <= 5; ++tws)
+            for (int gs = 1; gs <= 2; ++gs)
+                for (int lpt = 1; lpt >= 0; --lpt) {
+                    c->tuning = Tuning{tws, gs, lpt != 0};
+                    rc_status s = rebuild_items(c, se);
+                    if (s != RC_OK) {
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                        return s;
+                    }
+                    const SensorView ev = se.view();
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 4; ++rep) {
+                        if (rep == 1)
+                            RC_HIP(hipEventRecord(e0, st));
+                        RC_HIP(launch_render_batched(sc.sview(), ev, ov, se.lpt_items.as<int2>(), se.n_items,
+                                                     se.head.as<unsigned int>(), c->batched_grid(), st));
+                    }
+                    RC_HIP(hipEventRecord(e1, st));
+                    RC_HIP(hipEventSynchronize(e1));
+                    RC_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = c->tuning;
+                    }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (cache_path) {
+            if (FILE *f = fopen(cache_path, "a")) {
+                fprintf(f, "%s %d %d %d\n", key.c_str(), 1 << best.tw_shift, best.grid_scale, best.lpt ? 1 : 0);
+                fclose(f);
+            }
+        }
+    }
+    c->tuning = best;
+    RC_TRY(rebuild_items(c, se));
+    ++c->generation;
+    if (choice) {
+        choice[0] = 1 << best.tw_shift;
+        choice[1] = best.grid_scale;
+        choice[2] = best.lpt ? 1 : 0;
+    }
+    return RC_OK;
+}
+
+rc_status rc_tuning_set(rc_context *c, const int32_t *choice)
+{
+    RC_CHECK(c && choice, "NULL argument");
+    if (c->servers.load() > 0)
+        return fail(RC_E_BUSY, "a request server is using this context");
+    const int tw = choice[0];
+    RC_CHECK(tw == 4 || tw == 8 || tw == 16 || tw == 32, "tile columns must be 4, 8, 16 or 32");
+    RC_CHECK(choice[1] == 1 || choice[1] == 2, "grid scale must be 1 or 2");
+    RC_CHECK(choice[2] == 0 || choice[2] == 1, "cost order must be 0 or 1");
+    c->tuning = Tuning{__builtin_ctz(tw), choice[1], choice[2] != 0};
+    if (c->sensors) {
+        RC_TRY(set_device(c));
+        RC_TRY(rebuild_items(c, *c->sensors));
+    }
+    ++c->generation;
+    return RC_OK;
+}
+
+rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float *d_vel, float dt, rc_graph **graph)
+{
+    RC_CHECK(c && out && graph, "NULL argument");
+    *graph = nullptr;
+    RC_TRY(ready(c));
+    Scene &sc = *c->scene;
+    Sensors &se = *c->sensors;
+    RC_CHECK(sc.n_inst == 0 || d_vel, "d_vel is NULL");
+    RC_CHECK(std::isfinite(dt), "dt not finite");
+    RC_TRY(set_device(c));
+    auto g = new rc_graph;
+    g->ctx = c;
+    g->generation = c->generation;
+    rc_status s = c->pool.alloc(g->step, 256);
+    if (s != RC_OK) {
+        delete g;
+        return s;
+    }
+    hipError_t e = launch_fill_u32(g->step.as<unsigned int>(), 1, 0u, c->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e, "step graph setup");
+    }
+    const BuildView v = sc.view();
+    const OutView ov{out->depth, out->seg, out->tri, out->hit_xyz, nullptr, nullptr};
+    hipStream_t cs = g->capture;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t k = launch_move(sc.n_inst, sc.inst_T0.as<float>(), d_vel, sc.inst_dyn.as<uint8_t>(), 0,
+                                   g->step.as<int32_t>(), dt, sc.inst_T.as<float>(), cs);
+        if (k == hipSuccess)
+            k = launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, cs);
+        if (k == hipSuccess)
+            k = launch_refit(v, cs);
+        if (k == hipSuccess)
+            k = launch_render_batched(sc.sview(), se.view(), ov, se.lpt_items.as<int2>(), se.n_items,
+                                      se.head.as<unsigned int>(), c->batched_grid(), cs);
+        if (k == hipSuccess)
+            k = launch_bump(g->step.as<int32_t>(), cs);
+        e = hipStreamEndCapture(cs, &g->graph);
+        if (k != hipSuccess)
+            e = k;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        rc_graph_destroy(g);
+        return hip_fail(e, "step graph capture");
+    }
+    *graph = g;
+    return RC_OK;
+}
+
+rc_status rc_graph_set_step(rc_graph *g, int32_t step, void *stream)
+{
+    RC_CHECK(g, "NULL graph");
+    RC_TRY(set_device(g->ctx));
+    RC_HIP(launch_fill_u32(g->step.as<unsigned int>(), 1, (unsigned int)step,
+                           stream ? (hipStream_t)stream : g->ctx->stream));
+    return RC_OK;
+}
+
+rc_status rc_graph_launch(rc_graph *g, void *stream)
+{
+    RC_CHECK(g, "NULL graph");
+    if (g->generation != g->ctx->generation)
+        return fail(RC_E_STATE, "the scene, sensors or tuning changed after the graph was captured");
+    RC_TRY(set_device(g->ctx));
+    RC_HIP(hipGraphLaunch(g->exec, stream ? (hipStream_t)stream : g->ctx->stream));
+    return RC_OK;
+}
+
+rc_status rc_graph_destroy(rc_graph *g)
+{
+    if (!g)
+        return RC_OK;
+    (void)hipSetDevice(g->ctx->device);
+    if (g->capture)
+        (void)hipStreamSynchronize(g->capture);
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    if (g->capture)
+        (void)hipStreamDestroy(g->capture);
+    (void)hipDeviceSynchronize();
+    delete g;
+    return RC_OK;
+}
+
+}  // extern "C"

@@ -95,14 +95,16 @@ __global__ __launch_bounds__(256) void k_transform(BuildView v, const int32_t *_
 }
 
 // K8: constant-velocity motion of dynamic instances.
+// The step comes from d_step when it is set (a captured step graph advances
+// it on the device), else from the argument.
 __global__ __launch_bounds__(256) void k_move(int64_t n, const float *__restrict__ T0, const float *__restrict__ vel,
-                                              const uint8_t *__restrict__ dyn, int32_t step, float dt,
-                                              float *__restrict__ T)
+                                              const uint8_t *__restrict__ dyn, int32_t step,
+                                              const int32_t *__restrict__ d_step, float dt, float *__restrict__ T)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const float sdt = (float)step * dt;
+    const float sdt = (float)(d_step ? *d_step : step) * dt;
     float a[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k)
@@ -791,12 +793,25 @@ hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step, float dt,
-                       float *T, hipStream_t st)
+hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step,
+                       const int32_t *d_step, float dt, float *T, hipStream_t st)
 {
     if (n_inst == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_move, dim3(blocks_for(n_inst, 256)), dim3(256), 0, st, n_inst, T0, vel, dyn, step, dt, T);
+    hipLaunchKernelGGL(k_move, dim3(blocks_for(n_inst, 256)), dim3(256), 0, st, n_inst, T0, vel, dyn, step, d_step,
+                       dt, T);
+    return hipGetLastError();
+}
+
+__global__ void k_bump(int32_t *d_step)
+{
+    if (threadIdx.x == 0)
+        *d_step += 1;
+}
+
+hipError_t launch_bump(int32_t *d_step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, st, d_step);
     return hipGetLastError();
 }
 

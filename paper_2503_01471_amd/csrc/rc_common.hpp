@@ -49,7 +49,8 @@ __host__ __device__ inline int64_t node_base(int64_t tri_off, int e) { return tr
 struct SensorModel {
     int32_t kind;     // 0 pinhole, 1 lidar, 2 table
     int32_t W, H;     // pinhole W x H; lidar azimuths x channels
-    int32_t tiles_x;  // 8x8 ray tiles per row of tiles
+    int32_t tw_shift; // ray tile = (1 << tw_shift) columns x (64 >> tw_shift) rows (one wavefront)
+    int32_t tiles_x;  // ray tiles per row of tiles
     int32_t tiles;    // tiles per sensor instance
     float s;          // pinhole: tan(hfov/2)/(W/2)
     float hw, hh;     // W/2, H/2
@@ -80,11 +81,16 @@ struct SensorView {
     const int2 *items;       // (sensor instance, tile)
 };
 
+// Outputs: either one buffer per kind in the ray layout (ray_off), or, when
+// the tables are set, one buffer per sensor instance (requests of a served
+// batch write into their own buffers).
 struct OutView {
     float *depth;
     int32_t *seg;
     int32_t *tri;
     float *hit;
+    float *const *depth_tab;
+    int32_t *const *seg_tab;
 };
 
 struct BuildView {
@@ -114,7 +120,8 @@ struct BuildView {
 hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t n, bool to_recs,
                             hipStream_t st);
 hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step,
-                       float dt, float *T, hipStream_t st);
+                       const int32_t *d_step, float dt, float *T, hipStream_t st);
+hipError_t launch_bump(int32_t *d_step, hipStream_t st);
 hipError_t launch_build_sah(const BuildView &v, hipStream_t st);
 hipError_t launch_refit(const BuildView &v, hipStream_t st);
 
@@ -122,7 +129,7 @@ hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const O
                               int64_t n_items, hipStream_t st);
 hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const int2 *lpt_items,
                                  int64_t n_items, unsigned int *head, int grid, hipStream_t st);
-int batched_grid_size(int device);
+int batched_blocks_per_cu();
 hipError_t launch_render_brute(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
                                hipStream_t st);
 hipError_t launch_render_stats(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,

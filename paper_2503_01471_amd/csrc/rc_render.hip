@@ -37,7 +37,7 @@ struct Ray {
 
 // Unified wave-uniform view of one work item.
 struct Tile {
-    int s, env, W, H, kind, tiles_x;
+    int s, env, W, H, kind, tiles_x, tw_shift;
     float hw, hh, scale, tn, tf;
     int64_t table_off, ray_base;
 };
@@ -86,6 +86,7 @@ __device__ __forceinline__ Tile load_tile(const SensorView &se, int2 item)
     t.H = M.H;
     t.kind = M.kind;
     t.tiles_x = M.tiles_x;
+    t.tw_shift = M.tw_shift;
     t.hw = M.hw;
     t.hh = M.hh;
     t.scale = M.s;
@@ -315,7 +316,8 @@ __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ 
 
 // Final outputs of one ray from the winner (FP64 t, hit = o + t d).
 __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc, const Ray &r, int env,
-                                          const TriRec *__restrict__ recs, Best &b, int64_t idx)
+                                          const TriRec *__restrict__ recs, Best &b, int s, int64_t ray_base,
+                                          int64_t r_local)
 {
     float depth = -1.0f, hx = __builtin_nanf(""), hy = hx, hz = hx;
     int seg = -1, tri = -1;
@@ -337,6 +339,16 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
         tri = b.id;
         seg = sc.tri_seg[sc.env_tri_off[env] + b.id];
     }
+    if (o.depth_tab) {  // per-request buffers (served batches)
+        float *dp = o.depth_tab[s];
+        int32_t *sp = o.seg_tab[s];
+        if (dp)
+            dp[r_local] = depth;
+        if (sp)
+            sp[r_local] = seg;
+        return;
+    }
+    const int64_t idx = ray_base + r_local;
     if (o.depth)
         o.depth[idx] = depth;
     if (o.seg)
@@ -359,7 +371,8 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     const int lane = threadIdx.x & 63;
     const int tile = item.y;
     const int ty = tile / t.tiles_x, tx = tile - ty * t.tiles_x;
-    const int row = ty * 8 + (lane >> 3), col = tx * 8 + (lane & 7);
+    const int tw = 1 << t.tw_shift;
+    const int row = ty * (64 >> t.tw_shift) + (lane >> t.tw_shift), col = tx * tw + (lane & (tw - 1));
     if (row >= t.H || col >= t.W)
         return;
     Ray r;
@@ -371,7 +384,7 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     const int root = sc.env_root[t.env];
     if (root != kEmptyRoot)
         traverse<STATS>(r, nodes, recs, root, stk, b, st);
-    write_out(o, sc, r, t.env, recs, b, t.ray_base + (int64_t)row * t.W + col);
+    write_out(o, sc, r, t.env, recs, b, t.s, t.ray_base, (int64_t)row * t.W + col);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; map them so that each XCD walks
@@ -448,7 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
     const Tile t = load_tile(se, item);
     const int lane = threadIdx.x & 63;
     const int ty = item.y / t.tiles_x, tx = item.y - ty * t.tiles_x;
-    const int row = ty * 8 + (lane >> 3), col = tx * 8 + (lane & 7);
+    const int tw = 1 << t.tw_shift;
+    const int row = ty * (64 >> t.tw_shift) + (lane >> t.tw_shift), col = tx * tw + (lane & (tw - 1));
     if (row >= t.H || col >= t.W)
         return;
     Ray r;
@@ -511,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
         }
     }
     (void)st;
-    write_out(o, sc, r, t.env, nullptr, b, t.ray_base + (int64_t)row * t.W + col);
+    write_out(o, sc, r, t.env, nullptr, b, t.s, t.ray_base, (int64_t)row * t.W + col);
 }
 
 __global__ __launch_bounds__(256) void k_debug_rays(SensorView se, int32_t s, int64_t n,
@@ -554,15 +568,12 @@ hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const O
     return hipGetLastError();
 }
 
-int batched_grid_size(int device)
+int batched_blocks_per_cu()
 {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, device) != hipSuccess)
-        return 1024;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched, kBlock, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    return p.multiProcessorCount * per_cu;
+    return per_cu;
 }
 
 hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const int2 *lpt_items,

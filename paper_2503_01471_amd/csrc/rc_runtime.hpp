@@ -1,0 +1,125 @@
+// rc_runtime.hpp -- host-side state of a renderer context (internal).
+//
+// Shared by the ABI implementation (rc_api.cpp) and the request server
+// (rc_server.cpp).  All device memory of a context goes through its Pool,
+// which enforces the context's memory budget.
+#pragma once
+
+#include <stdint.h>
+
+#include <atomic>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "rc.h"
+#include "rc_common.hpp"
+
+namespace rc {
+
+rc_status fail(rc_status s, const char *fmt, ...);
+rc_status hip_fail(hipError_t e, const char *what);
+
+#define RC_HIP(call)                        \
+    do {                                    \
+        hipError_t e_ = (call);             \
+        if (e_ != hipSuccess)               \
+            return ::rc::hip_fail(e_, #call); \
+    } while (0)
+#define RC_CHECK(cond, ...)                                   \
+    do {                                                      \
+        if (!(cond))                                          \
+            return ::rc::fail(RC_E_INVALID, __VA_ARGS__);     \
+    } while (0)
+#define RC_TRY(expr)                 \
+    do {                             \
+        rc_status s_ = (expr);       \
+        if (s_ != RC_OK)             \
+            return s_;               \
+    } while (0)
+
+struct Pool;
+
+// Device buffer owned by a context (freed on destruction, budget released).
+struct DBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    Pool *pool = nullptr;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { reset(); }
+    void reset();
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct Pool {
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    rc_status alloc(DBuf &b, size_t bytes);
+};
+
+struct Mesh {
+    int64_t vert_off, n_verts, tri_off, n_tris;
+};
+
+struct Scene {
+    int32_t n_envs = 0;
+    int64_t n_inst = 0, n_tris = 0, n_dyn = 0;
+    std::vector<int64_t> env_tri_off;  // host copy
+    std::vector<int64_t> inst_offsets;
+    DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
+    DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, env_micro, micro;
+    bool poses_set = false;
+    bool built = false;
+    BuildView view() const;
+    SceneView sview() const;
+};
+
+struct ModelHost {
+    SensorModel m;
+    std::vector<float> table;  // lidar / table directions (FP32)
+};
+
+struct Sensors {
+    int64_t n_si = 0, n_items = 0, total_rays = 0;
+    std::vector<int64_t> ray_off, item_off, sens_offsets;
+    std::vector<int32_t> si_env, si_model;
+    DBuf models, tables, si_env_d, si_model_d, d_ray_off, pose, items, lpt_items, head, counters;
+    bool poses_set = false;
+    SensorView view() const;
+};
+
+// Launch choices of the batched form (set by rc_autotune).
+struct Tuning {
+    int tw_shift = 3;     // ray tile 8 x 8
+    int grid_scale = 1;   // persistent workgroups per CU slot
+    bool lpt = true;      // queue in decreasing estimated cost
+};
+
+}  // namespace rc
+
+struct rc_context {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    rc::Pool pool;
+    std::vector<float> mesh_xyz;
+    std::vector<int32_t> mesh_tri;  // global vertex indices
+    std::vector<rc::Mesh> meshes;
+    std::vector<rc::ModelHost> models;
+    std::unique_ptr<rc::Scene> scene;
+    std::unique_ptr<rc::Sensors> sensors;
+    rc::Tuning tuning;
+    int n_cu = 0, blocks_per_cu = 1;
+    uint64_t generation = 0;   // bumped whenever scene or sensors are replaced
+    std::atomic<int> servers{0};  // live request servers (scene is read-only meanwhile)
+    int batched_grid() const { return n_cu * blocks_per_cu * tuning.grid_scale; }
+};
+
+namespace rc {
+rc_status set_device(const rc_context *c);
+const char *last_error();
+// (Re)build the tile work lists of sensors `se` for the current tuning.
+rc_status rebuild_items(rc_context *c, Sensors &se);
+}  // namespace rc

@@ -1,0 +1,448 @@
+// rc_server.cpp -- request loop over a renderer context's resident scene.
+//
+// One worker thread owns all device work of the server.  Requests wait in a
+// FIFO; each admission round takes, in arrival order (with backfill of later
+// requests that still fit), the requests whose in-flight bytes fit the
+// server budget and launches them on a free stream: in batched mode all of
+// them in ONE persistent render launch whose work list concatenates their
+// tiles and whose per-sensor-instance output table points into each
+// request's own buffers; in plain mode one request at a time, one launch per
+// environment.  Completion is detected through one event per stream; while
+// a batch runs, newly arrived requests are admitted on the other streams, so
+// their work overlaps on the device.
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rc_runtime.hpp"
+
+using namespace rc;
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+    uint64_t ticket = 0;
+    std::vector<int32_t> envs;
+    int32_t model = 0;
+    std::vector<float> poses;  // 12 per environment
+    float *depth = nullptr;
+    int32_t *seg = nullptr;
+    int64_t rays_per_env = 0;
+    int64_t tiles = 0;  // work items
+    size_t bytes = 0;   // budget charge while queued or running
+    double t_submit = 0.0, t_done = 0.0;
+    int state = 0;  // 0 queued, 1 running, 2 done
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Req *> reqs;
+    size_t charged = 0;
+    DBuf items, si_env, si_model, ray_off, pose, dtab, stab, head;
+    int64_t cap_items = 0, cap_si = 0;
+    void *host = nullptr;
+    size_t host_cap = 0;
+};
+
+constexpr int64_t kMaxBatchRays = int64_t(48) << 20;  // bound on one admission round
+constexpr int kLookahead = 256;                       // backfill window of the FIFO
+
+}  // namespace
+
+struct rc_server {
+    rc_context *ctx = nullptr;
+    int mode = RC_SERVE_BATCHED;
+    size_t budget = 0, in_use = 0;
+    std::vector<SensorModel> models;  // host copies, current tile shape
+    std::vector<float> env_pose;      // first attached pose per environment
+    std::vector<uint8_t> env_has_pose;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+    uint64_t next_ticket = 1;
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::thread worker;
+    bool stop = false;
+    rc_status error = RC_OK;
+    std::string error_msg;
+};
+
+namespace {
+
+// Grow a device table (no budget check beyond the context pool).
+rc_status ensure(rc_context *c, DBuf &b, size_t bytes)
+{
+    if (b.n >= bytes)
+        return RC_OK;
+    return c->pool.alloc(b, bytes + bytes / 2);
+}
+
+// Launch one admitted batch on slot `sl` (worker thread, no lock held).
+rc_status launch(rc_server *sv, Slot &sl)
+{
+    rc_context *c = sv->ctx;
+    const Scene &sc = *c->scene;
+    const Sensors &se = *c->sensors;
+    int64_t S = 0, n_items = 0;
+    for (Req *r : sl.reqs) {
+        S += (int64_t)r->envs.size();
+        n_items += r->tiles;
+    }
+    if (S > sl.cap_si) {
+        RC_TRY(ensure(c, sl.si_env, 4 * S));
+        RC_TRY(ensure(c, sl.si_model, 4 * S));
+        RC_TRY(ensure(c, sl.ray_off, 8 * (S + 1)));
+        RC_TRY(ensure(c, sl.pose, 48 * S));
+        RC_TRY(ensure(c, sl.dtab, 8 * S));
+        RC_TRY(ensure(c, sl.stab, 8 * S));
+        RC_HIP(hipMemsetAsync(sl.ray_off.p, 0, sl.ray_off.n, sl.stream));
+        sl.cap_si = (int64_t)(sl.si_env.n / 4);
+    }
+    if (n_items > sl.cap_items) {
+        RC_TRY(ensure(c, sl.items, 8 * n_items));
+        sl.cap_items = (int64_t)(sl.items.n / 8);
+    }
+    if (!sl.head.p)
+        RC_TRY(c->pool.alloc(sl.head, 256));
+    // staging layout: items | si_env | si_model | pose | dtab | stab
+    const size_t o_items = 0, o_env = o_items + 8 * n_items, o_model = o_env + 4 * S, o_pose = o_model + 4 * S,
+                 o_dtab = o_pose + 48 * S, o_stab = o_dtab + 8 * S, total = o_stab + 8 * S;
+    if (total > sl.host_cap) {
+        if (sl.host)
+            RC_HIP(hipHostFree(sl.host));
+        sl.host = nullptr;
+        sl.host_cap = 0;
+        RC_HIP(hipHostMalloc(&sl.host, total + total / 2, hipHostMallocDefault));
+        sl.host_cap = total + total / 2;
+    }
+    char *h = (char *)sl.host;
+    int2 *items = (int2 *)(h + o_items);
+    int32_t *si_env = (int32_t *)(h + o_env);
+    int32_t *si_model = (int32_t *)(h + o_model);
+    float *pose = (float *)(h + o_pose);
+    float **dtab = (float **)(h + o_dtab);
+    int32_t **stab = (int32_t **)(h + o_stab);
+    int64_t k = 0, it = 0;
+    std::vector<int64_t> item_begin;  // per sensor instance (plain mode)
+    for (Req *r : sl.reqs) {
+        const SensorModel &m = sv->models[r->model];
+        for (size_t i = 0; i < r->envs.size(); ++i, ++k) {
+            si_env[k] = r->envs[i];
+            si_model[k] = r->model;
+            memcpy(pose + 12 * k, r->poses.data() + 12 * i, 48);
+            dtab[k] = r->depth ? r->depth + (int64_t)i * r->rays_per_env : nullptr;
+            stab[k] = r->seg ? r->seg + (int64_t)i * r->rays_per_env : nullptr;
+            item_begin.push_back(it);
+            for (int t = 0; t < m.tiles; ++t)
+                items[it++] = make_int2((int)k, t);
+        }
+    }
+    item_begin.push_back(it);
+    hipStream_t st = sl.stream;
+    RC_HIP(hipMemcpyAsync(sl.items.p, h + o_items, 8 * n_items, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.si_env.p, h + o_env, 4 * S, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.si_model.p, h + o_model, 4 * S, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.pose.p, h + o_pose, 48 * S, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.dtab.p, h + o_dtab, 8 * S, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.stab.p, h + o_stab, 8 * S, hipMemcpyHostToDevice, st));
+    SensorView ev;
+    ev.models = se.models.as<SensorModel>();
+    ev.tables = se.tables.as<float>();
+    ev.si_env = sl.si_env.as<int32_t>();
+    ev.si_model = sl.si_model.as<int32_t>();
+    ev.ray_off = sl.ray_off.as<int64_t>();
+    ev.pose = sl.pose.as<float>();
+    ev.items = sl.items.as<int2>();
+    const OutView ov{nullptr, nullptr, nullptr, nullptr, sl.dtab.as<float *>(), sl.stab.as<int32_t *>()};
+    if (sv->mode == RC_SERVE_BATCHED) {
+        RC_HIP(launch_render_batched(sc.sview(), ev, ov, ev.items, n_items, sl.head.as<unsigned int>(),
+                                     c->batched_grid(), st));
+    } else {
+        for (int64_t s = 0; s < S; ++s)
+            RC_HIP(launch_render_flat(sc.sview(), ev, ov, item_begin[s], item_begin[s + 1] - item_begin[s], st));
+    }
+    RC_HIP(hipEventRecord(sl.done, st));
+    return RC_OK;
+}
+
+void worker_main(rc_server *sv)
+{
+    (void)hipSetDevice(sv->ctx->device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    while (true) {
+        // completions
+        bool any_busy = false;
+        for (auto &slp : sv->slots) {
+            Slot &sl = *slp;
+            if (!sl.busy)
+                continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipSuccess) {
+                const double t = now_s();
+                for (Req *r : sl.reqs) {
+                    r->state = 2;
+                    r->t_done = t;
+                }
+                sl.reqs.clear();
+                sv->in_use -= sl.charged;
+                sl.charged = 0;
+                sl.busy = false;
+                sv->cv.notify_all();
+            } else if (q != hipErrorNotReady) {
+                sv->error = RC_E_HIP;
+                sv->error_msg = hipGetErrorString(q);
+                sv->stop = true;
+                for (Req *r : sl.reqs)
+                    r->state = 2;
+                sl.reqs.clear();
+                sl.busy = false;
+                sv->cv.notify_all();
+            } else {
+                any_busy = true;
+            }
+        }
+        if (sv->stop && (sv->queue.empty() || sv->error != RC_OK) && !any_busy)
+            break;
+        // admission
+        bool launched = false;
+        for (auto &slp : sv->slots) {
+            Slot &sl = *slp;
+            if (sl.busy || sv->queue.empty() || sv->error != RC_OK)
+                continue;
+            std::vector<Req *> batch;
+            size_t bytes = 0;
+            int64_t rays = 0;
+            int scanned = 0;
+            for (auto itq = sv->queue.begin(); itq != sv->queue.end() && scanned < kLookahead; ++scanned) {
+                Req *r = *itq;
+                const int64_t rr = r->rays_per_env * (int64_t)r->envs.size();
+                const bool fits = sv->in_use + bytes + r->bytes <= sv->budget &&
+                                  (batch.empty() || rays + rr <= kMaxBatchRays);
+                if (fits) {
+                    batch.push_back(r);
+                    bytes += r->bytes;
+                    rays += rr;
+                    itq = sv->queue.erase(itq);
+                    if (sv->mode == RC_SERVE_PLAIN)
+                        break;
+                } else {
+                    if (sv->mode == RC_SERVE_PLAIN)
+                        break;  // strict FIFO
+                    ++itq;
+                }
+            }
+            if (batch.empty())
+                continue;
+            for (Req *r : batch)
+                r->state = 1;
+            sv->in_use += bytes;
+            sl.reqs = batch;
+            sl.charged = bytes;
+            sl.busy = true;
+            lk.unlock();
+            const rc_status s = launch(sv, sl);
+            lk.lock();
+            if (s != RC_OK) {
+                sv->error = s;
+                sv->error_msg = last_error();
+                sv->stop = true;
+                for (Req *r : sl.reqs)
+                    r->state = 2;
+                sl.reqs.clear();
+                sl.busy = false;
+                sv->in_use -= sl.charged;
+                sv->cv.notify_all();
+            }
+            launched = true;
+        }
+        if (!launched) {
+            // short wait: new requests notify; running batches are polled
+            sv->cv.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 500));
+        }
+    }
+    // after a failure, release whatever is still queued so that no client waits forever
+    for (Req *r : sv->queue)
+        r->state = 2;
+    sv->queue.clear();
+    sv->cv.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_server_create(rc_context *c, int32_t mode, int32_t n_streams, size_t hbm_budget, rc_server **out)
+{
+    RC_CHECK(c && out, "NULL argument");
+    *out = nullptr;
+    RC_CHECK(mode == RC_SERVE_PLAIN || mode == RC_SERVE_BATCHED, "unknown server mode %d", mode);
+    RC_CHECK(n_streams >= 1 && n_streams <= 16, "n_streams must be in [1, 16]");
+    RC_CHECK(hbm_budget > 0, "hbm_budget must be positive");
+    if (!c->scene || !c->scene->built || !c->sensors || !c->sensors->poses_set)
+        return fail(RC_E_STATE, "server needs a built scene and attached, posed sensors");
+    RC_TRY(set_device(c));
+    auto sv = new rc_server;
+    sv->ctx = c;
+    sv->mode = mode;
+    sv->budget = hbm_budget;
+    const Sensors &se = *c->sensors;
+    // host copies of the models (current tile shape) and of the attached poses
+    sv->models.resize(c->models.size());
+    if (!c->models.empty() &&
+        hipMemcpy(sv->models.data(), se.models.p, sizeof(SensorModel) * c->models.size(), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
+        delete sv;
+        return fail(RC_E_HIP, "reading sensor models");
+    }
+    std::vector<float> pose(12 * (size_t)se.n_si);
+    if (se.n_si && hipMemcpy(pose.data(), se.pose.p, 48 * se.n_si, hipMemcpyDeviceToHost) != hipSuccess) {
+        delete sv;
+        return fail(RC_E_HIP, "reading sensor poses");
+    }
+    const int32_t E = c->scene->n_envs;
+    sv->env_pose.assign(12 * (size_t)E, 0.f);
+    sv->env_has_pose.assign(E, 0);
+    for (int32_t e = 0; e < E; ++e) {
+        const int64_t s = se.sens_offsets[e];
+        if (s < se.sens_offsets[e + 1]) {
+            memcpy(&sv->env_pose[12 * (size_t)e], &pose[12 * (size_t)s], 48);
+            sv->env_has_pose[e] = 1;
+        }
+    }
+    const int n_slots = mode == RC_SERVE_PLAIN ? 1 : n_streams;
+    for (int i = 0; i < n_slots; ++i)
+        sv->slots.push_back(std::make_unique<Slot>());
+    for (auto &slp : sv->slots) {
+        Slot &sl = *slp;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            rc_server_destroy(sv);
+            return fail(RC_E_HIP, "creating server streams");
+        }
+    }
+    c->servers += 1;
+    sv->worker = std::thread(worker_main, sv);
+    *out = sv;
+    return RC_OK;
+}
+
+rc_status rc_server_submit(rc_server *sv, const rc_request *q, uint64_t *ticket)
+{
+    RC_CHECK(sv && q && ticket, "NULL argument");
+    rc_context *c = sv->ctx;
+    RC_CHECK(q->n_envs >= 1 && q->env_ids, "request needs n_envs >= 1 and env_ids");
+    RC_CHECK(q->sensor_id >= 0 && q->sensor_id < (int32_t)sv->models.size(), "sensor_id %d invalid", q->sensor_id);
+    auto r = std::make_unique<Req>();
+    r->envs.assign(q->env_ids, q->env_ids + q->n_envs);
+    for (int32_t e : r->envs) {
+        RC_CHECK(e >= 0 && e < c->scene->n_envs, "environment id %d out of range", e);
+        RC_CHECK(q->sensor_T || sv->env_has_pose[e], "environment %d has no attached sensor pose", e);
+    }
+    r->model = q->sensor_id;
+    r->poses.resize(12 * (size_t)q->n_envs);
+    for (int32_t i = 0; i < q->n_envs; ++i)
+        memcpy(&r->poses[12 * (size_t)i], q->sensor_T ? q->sensor_T + 12 * (size_t)i : &sv->env_pose[12 * (size_t)r->envs[i]],
+               48);
+    r->depth = q->depth;
+    r->seg = q->seg;
+    const SensorModel &m = sv->models[r->model];
+    r->rays_per_env = (int64_t)m.W * m.H;
+    r->tiles = (int64_t)m.tiles * q->n_envs;
+    r->bytes = (size_t)(8 * r->rays_per_env * q->n_envs + 8 * r->tiles + 80 * (int64_t)q->n_envs);
+    if (r->bytes > sv->budget)
+        return fail(RC_E_OOM, "request needs %zu bytes in flight, server budget is %zu", r->bytes, sv->budget);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->error != RC_OK)
+        return fail(sv->error, "server failed: %s", sv->error_msg.c_str());
+    if (sv->stop)
+        return fail(RC_E_STATE, "server is stopping");
+    r->ticket = sv->next_ticket++;
+    r->t_submit = now_s();
+    *ticket = r->ticket;
+    sv->queue.push_back(r.get());
+    sv->reqs.emplace(r->ticket, std::move(r));
+    sv->cv.notify_all();
+    return RC_OK;
+}
+
+static rc_status finish(rc_server *sv, uint64_t ticket, bool block, int32_t *done, double *latency)
+{
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end())
+        return fail(RC_E_INVALID, "unknown or already released ticket %llu", (unsigned long long)ticket);
+    Req *r = it->second.get();
+    if (block)
+        sv->cv.wait(lk, [&] { return r->state == 2; });
+    if (r->state != 2) {
+        if (done)
+            *done = 0;
+        return RC_OK;
+    }
+    if (done)
+        *done = 1;
+    if (latency)
+        *latency = r->t_done - r->t_submit;
+    sv->reqs.erase(it);
+    if (sv->error != RC_OK)
+        return fail(sv->error, "server failed: %s", sv->error_msg.c_str());
+    return RC_OK;
+}
+
+rc_status rc_server_poll(rc_server *sv, uint64_t ticket, int32_t *done, double *latency_s)
+{
+    RC_CHECK(sv && done, "NULL argument");
+    return finish(sv, ticket, false, done, latency_s);
+}
+
+rc_status rc_server_wait(rc_server *sv, uint64_t ticket, double *latency_s)
+{
+    RC_CHECK(sv, "NULL server");
+    return finish(sv, ticket, true, nullptr, latency_s);
+}
+
+rc_status rc_server_destroy(rc_server *sv)
+{
+    if (!sv)
+        return RC_OK;
+    if (sv->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stop = true;
+        }
+        sv->cv.notify_all();
+        sv->worker.join();
+        sv->ctx->servers -= 1;
+    }
+    (void)hipSetDevice(sv->ctx->device);
+    for (auto &slp : sv->slots) {
+        Slot &sl = *slp;
+        if (sl.stream)
+            (void)hipStreamSynchronize(sl.stream);
+        if (sl.done)
+            (void)hipEventDestroy(sl.done);
+        if (sl.stream)
+            (void)hipStreamDestroy(sl.stream);
+        if (sl.host)
+            (void)hipHostFree(sl.host);
+    }
+    delete sv;
+    return RC_OK;
+}
+
+}  // extern "C"

@@ -26,8 +26,11 @@ ABI = [
     "rc_status_string", "rc_last_error", "rc_create", "rc_destroy", "rc_memory_used", "rc_mesh_add",
     "rc_scene_load", "rc_sensor_add", "rc_sensors_attach", "rc_ray_layout", "rc_env_tri_offsets",
     "rc_set_instance_poses", "rc_set_sensor_poses", "rc_move_instances", "rc_build", "rc_refit", "rc_render",
-    "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh",
+    "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh", "rc_autotune", "rc_tuning_set", "rc_step_graph_create",
+    "rc_graph_set_step", "rc_graph_launch", "rc_graph_destroy", "rc_server_create", "rc_server_submit",
+    "rc_server_poll", "rc_server_wait", "rc_server_destroy",
 ]
+RC_SERVE_PLAIN, RC_SERVE_BATCHED = 0, 1
 
 
 class RCError(RuntimeError):
@@ -44,6 +47,11 @@ class rc_sensor_desc(C.Structure):
 
 class rc_outputs(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("seg", C.c_void_p), ("tri", C.c_void_p), ("hit_xyz", C.c_void_p)]
+
+
+class rc_request(C.Structure):
+    _fields_ = [("n_envs", C.c_int32), ("env_ids", C.c_void_p), ("sensor_id", C.c_int32),
+                ("sensor_T", C.c_void_p), ("depth", C.c_void_p), ("seg", C.c_void_p)]
 
 
 _lib = None
@@ -79,6 +87,17 @@ def lib():
             "rc_debug_world": (I32, [P, P]),
             "rc_debug_rays": (I32, [P, I32, I64, P, P, P]),
             "rc_debug_bvh": (I32, [P, I32, C.POINTER(I32), P, P, P, P, C.POINTER(I32)]),
+            "rc_autotune": (I32, [P, C.c_char_p, P]),
+            "rc_tuning_set": (I32, [P, P]),
+            "rc_step_graph_create": (I32, [P, C.POINTER(rc_outputs), P, C.c_float, C.POINTER(P)]),
+            "rc_graph_set_step": (I32, [P, I32, P]),
+            "rc_graph_launch": (I32, [P, P]),
+            "rc_graph_destroy": (I32, [P]),
+            "rc_server_create": (I32, [P, I32, I32, SZ, C.POINTER(P)]),
+            "rc_server_submit": (I32, [P, C.POINTER(rc_request), C.POINTER(C.c_uint64)]),
+            "rc_server_poll": (I32, [P, C.c_uint64, C.POINTER(I32), C.POINTER(C.c_double)]),
+            "rc_server_wait": (I32, [P, C.c_uint64, C.POINTER(C.c_double)]),
+            "rc_server_destroy": (I32, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -249,3 +268,74 @@ def rc_debug_bvh(ctx, e: int, n_tris: int) -> dict:
     n = nn.value
     return dict(n_nodes=n, boxes=boxes[:n], children=ch[:n], parent=par[:n], leaf_ids=ids[:n_tris],
                 root=root.value)
+
+
+def rc_autotune(ctx, cache_path: Optional[str] = None):
+    """Returns (tile columns, grid scale, cost order flag)."""
+    ch = np.zeros(3, np.int32)
+    _check(lib().rc_autotune(ctx, None if cache_path is None else cache_path.encode(), _ptr(ch)))
+    return tuple(int(x) for x in ch)
+
+
+def rc_tuning_set(ctx, tile_cols: int = 8, grid_scale: int = 1, cost_order: int = 1) -> None:
+    ch = np.array([tile_cols, grid_scale, cost_order], np.int32)
+    _check(lib().rc_tuning_set(ctx, _ptr(ch)))
+
+
+def rc_step_graph_create(ctx, d_vel, dt: float, depth=None, seg=None, tri=None, hit_xyz=None, total_rays: int = 0):
+    out = rc_outputs(
+        None if depth is None else _dev(depth, "float32", total_rays, "depth"),
+        None if seg is None else _dev(seg, "int32", total_rays, "seg"),
+        None if tri is None else _dev(tri, "int32", total_rays, "tri"),
+        None if hit_xyz is None else _dev(hit_xyz, "float32", 3 * total_rays, "hit_xyz"))
+    g = C.c_void_p()
+    _check(lib().rc_step_graph_create(ctx, C.byref(out), _dev(d_vel, "float32", 0, "d_vel"), dt, C.byref(g)))
+    return g.value
+
+
+def rc_graph_set_step(graph, step: int, stream=None) -> None:
+    _check(lib().rc_graph_set_step(graph, step, _stream(stream)))
+
+
+def rc_graph_launch(graph, stream=None) -> None:
+    _check(lib().rc_graph_launch(graph, _stream(stream)))
+
+
+def rc_graph_destroy(graph) -> None:
+    _check(lib().rc_graph_destroy(graph))
+
+
+def rc_server_create(ctx, mode: int = RC_SERVE_BATCHED, n_streams: int = 4, hbm_budget: int = 4 << 30):
+    srv = C.c_void_p()
+    _check(lib().rc_server_create(ctx, mode, n_streams, hbm_budget, C.byref(srv)))
+    return srv.value
+
+
+def rc_server_submit(server, env_ids, sensor_id: int, depth=None, seg=None, sensor_T=None) -> int:
+    ids = _host(env_ids, np.int32)
+    T = None if sensor_T is None else _host(sensor_T, np.float32)
+    n = len(ids)
+    req = rc_request(n, ids.ctypes.data, sensor_id, None if T is None else T.ctypes.data,
+                     None if depth is None else _dev(depth, "float32", 0, "depth"),
+                     None if seg is None else _dev(seg, "int32", 0, "seg"))
+    t = C.c_uint64()
+    _check(lib().rc_server_submit(server, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def rc_server_poll(server, ticket: int):
+    """(done, latency_s); a reported completion releases the ticket."""
+    done = C.c_int32()
+    lat = C.c_double()
+    _check(lib().rc_server_poll(server, ticket, C.byref(done), C.byref(lat)))
+    return bool(done.value), lat.value
+
+
+def rc_server_wait(server, ticket: int) -> float:
+    lat = C.c_double()
+    _check(lib().rc_server_wait(server, ticket, C.byref(lat)))
+    return lat.value
+
+
+def rc_server_destroy(server) -> None:
+    _check(lib().rc_server_destroy(server))

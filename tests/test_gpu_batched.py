@@ -1,0 +1,197 @@
+"""GPU tests of the batched and served forms: every launch choice, the step
+graph and the request server give the same outputs, bit for bit, as the
+plain path (and therefore the oracle-checked values)."""
+import numpy as np
+import pytest
+
+import parity
+from oracle import oracle as O
+from paper_2503_01471_amd import rc, scenes as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _R(scene, **kw):
+    from paper_2503_01471_amd.renderer import Renderer
+    return Renderer(scene, **kw)
+
+
+def _host(out):
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+
+
+def test_every_tuning_is_bit_exact():
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=8)
+    R = _R(scene)
+    ref = _host(R.render(mode=rc.RC_RENDER_FLAT))
+    for tw in (4, 8, 16, 32):
+        for gs in (1, 2):
+            for lpt in (0, 1):
+                _say(f"tuning tile {tw} grid {gs} lpt {lpt}")
+                rc.rc_tuning_set(R.ctx, tw, gs, lpt)
+                for mode in (rc.RC_RENDER_BATCHED, rc.RC_RENDER_FLAT, rc.RC_RENDER_PLAIN):
+                    got = _host(R.render(mode=mode))
+                    for k in ("depth", "seg", "tri"):
+                        assert np.array_equal(got[k], ref[k]), (tw, gs, lpt, mode, k)
+    R.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    _need_gpu()
+    scene = S.make_cfg3(n_envs=16)
+    R = _R(scene)
+    ref = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    cache = str(tmp_path / "tune.txt")
+    _say("autotune")
+    ch = rc.rc_autotune(R.ctx, cache)
+    assert ch[0] in (4, 8, 16, 32) and ch[1] in (1, 2) and ch[2] in (0, 1)
+    got = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(got[k], ref[k])
+    rc.rc_tuning_set(R.ctx, 8, 1, 1)
+    assert rc.rc_autotune(R.ctx, cache) == ch  # cache hit
+    assert open(cache).read().count("\n") == 1
+    R.close()
+
+
+def test_step_graph_replays_match_eager():
+    """Replay the captured step several times, with eager work and
+    synchronisation in between, and compare every replay with the eager
+    step (motion to the same step, refit, batched render), and one step with
+    the oracle."""
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=6)
+    R = _R(scene)
+    n = R.total_rays
+    gout = dict(depth=torch.empty(n, device="cuda"), seg=torch.empty(n, dtype=torch.int32, device="cuda"),
+                tri=torch.empty(n, dtype=torch.int32, device="cuda"))
+    g = rc.rc_step_graph_create(R.ctx, R.inst_vel, float(scene.dt), depth=gout["depth"], seg=gout["seg"],
+                                tri=gout["tri"], total_rays=n)
+    rc.rc_graph_set_step(g, 1)
+    for step in range(1, 6):
+        _say(f"graph replay step {step}")
+        rc.rc_graph_launch(g)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in gout.items()}
+        # eager reference for the same step (also exercises eager work between replays)
+        R.move(step)
+        R.refit()
+        ref = _host(R.render(mode=rc.RC_RENDER_BATCHED, depth=True, seg=True, tri=True))
+        torch.cuda.synchronize()
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(got[k], ref[k]), (step, k)
+        if step == 3:
+            w = O.world(scene, O.moved_poses(scene, step))
+            rep = parity.compare(got, O.render(scene, w))
+            parity.assert_contract(rep)
+    # a changed tuning invalidates the graph
+    rc.rc_tuning_set(R.ctx, 16, 1, 1)
+    with pytest.raises(rc.RCError) as ei:
+        rc.rc_graph_launch(g)
+    assert ei.value.status == -4
+    rc.rc_graph_destroy(g)
+    R.close()
+
+
+def _requests(scene, rng, n_req, max_envs):
+    reqs = []
+    for _ in range(n_req):
+        k = int(rng.integers(1, max_envs + 1))
+        envs = rng.choice(scene.n_envs, k, replace=False).astype(np.int32)
+        sid = int(rng.integers(0, len(scene.sensors)))
+        reqs.append((envs, sid))
+    return reqs
+
+
+def _serve(R, reqs, mode, n_streams=4, budget=1 << 30, alone=False):
+    scene = R.scene
+    outs, lat = [], []
+    for envs, sid in reqs:
+        nr = scene.sensors[sid].n_rays * len(envs)
+        outs.append((torch.full((nr,), -7.0, device="cuda"), torch.full((nr,), -7, dtype=torch.int32, device="cuda")))
+    torch.cuda.synchronize()  # buffers must be ready: the server writes them on its own streams
+    srv = rc.rc_server_create(R.ctx, mode, n_streams, budget)
+    try:
+        tickets = []
+        for (envs, sid), (d, s) in zip(reqs, outs):
+            t = rc.rc_server_submit(srv, envs, sid, d, s)
+            if alone:
+                lat.append(rc.rc_server_wait(srv, t))
+            else:
+                tickets.append(t)
+        for t in tickets:
+            lat.append(rc.rc_server_wait(srv, t))
+    finally:
+        rc.rc_server_destroy(srv)
+    torch.cuda.synchronize()
+    return [(d.cpu().numpy(), s.cpu().numpy()) for d, s in outs], lat
+
+
+def test_server_alone_equals_mix_and_plain():
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=24)
+    R = _R(scene)
+    rng = np.random.default_rng(11)
+    reqs = _requests(scene, rng, 40, 8)
+    _say("server alone")
+    alone, _ = _serve(R, reqs, rc.RC_SERVE_BATCHED, alone=True)
+    _say("server mix")
+    mix, lat = _serve(R, reqs, rc.RC_SERVE_BATCHED)
+    _say("server plain")
+    plain, _ = _serve(R, reqs, rc.RC_SERVE_PLAIN)
+    for i in range(len(reqs)):
+        for j in range(2):
+            assert np.array_equal(alone[i][j], mix[i][j]), i
+            assert np.array_equal(alone[i][j], plain[i][j]), i
+        assert np.all(alone[i][0] != -7.0)
+    assert all(x > 0 for x in lat)
+    # requests with the environment's own sensor equal rc_render's rays
+    full = _host(R.render(mode=rc.RC_RENDER_FLAT))
+    for i, (envs, sid) in enumerate(reqs):
+        for q, e in enumerate(envs):
+            s_inst = int(scene.sens_offsets[e])
+            if int(scene.sensor_ids[s_inst]) != sid:
+                continue
+            nr = scene.sensors[sid].n_rays
+            a, b = R.ray_offsets[s_inst], R.ray_offsets[s_inst + 1]
+            assert np.array_equal(mix[i][0][q * nr:(q + 1) * nr], full["depth"][a:b])
+            assert np.array_equal(mix[i][1][q * nr:(q + 1) * nr], full["seg"][a:b])
+    R.close()
+
+
+def test_server_budget_and_busy():
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=12)
+    R = _R(scene)
+    rng = np.random.default_rng(3)
+    reqs = _requests(scene, rng, 20, 4)
+    budget = 8 * 480 * 270 * 4 + (1 << 20)  # about one 4-env camera request in flight
+    _say("server small budget")
+    mix, lat = _serve(R, reqs, rc.RC_SERVE_BATCHED, n_streams=3, budget=budget)
+    alone, _ = _serve(R, reqs, rc.RC_SERVE_BATCHED, alone=True)
+    for i in range(len(reqs)):
+        assert np.array_equal(alone[i][0], mix[i][0]) and np.array_equal(alone[i][1], mix[i][1])
+    srv = rc.rc_server_create(R.ctx, rc.RC_SERVE_BATCHED, 2, 1 << 20)
+    try:
+        big = torch.empty(8 * 480 * 270, device="cuda")
+        with pytest.raises(rc.RCError) as ei:  # alone larger than the budget
+            rc.rc_server_submit(srv, np.arange(8, dtype=np.int32), 0, big)
+        assert ei.value.status == -2
+        with pytest.raises(rc.RCError) as ei:  # scene is read-only while serving
+            rc.rc_build(R.ctx)
+        assert ei.value.status == -5
+    finally:
+        rc.rc_server_destroy(srv)
+    R.build()  # allowed again
+    R.close()
