@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the batched ray-cast renderer on one MI355X.
 
-One step = one pass of the rendering hot path over every environment of the
-workload: sensor poses uploaded, every instance transformed, one BVH built
-per environment, every ray generated, traversed and written (depth/range +
-segmentation).  Default workload: 4096 environments x one 64-channel x
-512-azimuth LiDAR in a 60-tree forest (4802 triangles per environment).
+Default (headline) workload: 4096 environments, each with one rotating LiDAR
+of 64 channels x 512 azimuths in a 60-tree forest (4802 triangles per
+environment), 134,217,728 rays per step.  One step = one pass of the whole
+rendering hot path over every environment: sensor poses uploaded, every
+instance transformed, one SAH BVH built per environment, every ray generated,
+traversed and written (range + segmentation), in the batched form (one
+persistent launch, device work queue, autotuned launch shape).
 
 Prints ONE JSON line: Mrays/s (whole job), env-steps/s, the render kernel's
-roofline position, the plain per-environment path on the same GPU, and the
-CPU oracle timed on this host on a bounded sample.
+roofline position, the same step on the plain per-environment path, a short
+served-form summary (p50/p99 latency) and the CPU oracle timed on this host
+on a bounded sample.  --cfg 4 times the per-step HIP graph of the uneven
+moving-obstacle batch, --cfg 5 the full request-serving run.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,7 +32,9 @@ WORKLOADS = {
     1: "1 env, 64x48 pinhole camera, ground + 8 boxes (98 tris)",
     2: "1024 envs x 480x270 pinhole camera, room + 40 random box/cylinder/sphere obstacles (~5.3k tris/env)",
     3: "4096 envs x 64ch x 512az rotating LiDAR (360 x 90 deg, 0.5-30 m), 60-tree forest (4802 tris/env)",
-    4: "2048 envs, 5-200 boxes (30% moving), mixed 480x270 / 240x135 cameras and 32x512 LiDAR",
+    4: "2048 envs, 5-200 boxes (30% moving, refit every step), mixed 480x270 / 240x135 cameras and 32x512 "
+       "LiDAR, 100 steps as one HIP graph each",
+    5: "requests of 1-512 envs (uneven box scenes, one sensor type each), Poisson arrivals, resident BVHs",
 }
 
 
@@ -69,7 +74,6 @@ def calibration_copy(nbytes=1 << 28):
 
 def cpu_baseline(cfg, seconds):
     """The oracle on a bounded sample of the same workload, all host cores."""
-    import numpy as np  # noqa: F401
     from oracle import oracle as O
     from paper_2503_01471_amd import scenes as S
     cores = len(os.sched_getaffinity(0))
@@ -90,30 +94,26 @@ def cpu_baseline(cfg, seconds):
             "env_steps_per_s": n_env / dt}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cfg", type=int, default=3, choices=[1, 2, 3, 4])
-    ap.add_argument("--mode", default="batched", choices=["plain", "flat", "batched"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); environments shard across GPUs "
-              "with no exchange, so a multi-GPU run is not part of this build.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def timed(fn, k):
     import torch
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(k):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / k
 
+
+# --------------------------------------------------------------------------
+# render-step workloads (cfg 1-3)
+# --------------------------------------------------------------------------
+def bench_step(args):
+    import torch
     from paper_2503_01471_amd import rc, scenes
     from paper_2503_01471_amd.renderer import Renderer
 
-    assert torch.cuda.is_available(), "bench needs a HIP device"
     mode = {"plain": rc.RC_RENDER_PLAIN, "flat": rc.RC_RENDER_FLAT, "batched": rc.RC_RENDER_BATCHED}[args.mode]
     log(f"generating cfg{args.cfg}")
     scene = scenes.make(args.cfg)
@@ -123,22 +123,17 @@ def main():
     out = R.alloc(depth=True, seg=True)
     rays = R.total_rays
     ctx = R.ctx
-    torch.cuda.synchronize()
+    tuning = rc.rc_autotune(ctx, args.tune_cache) if (mode == rc.RC_RENDER_BATCHED and not args.no_autotune) else None
+    log(f"tuning {tuning}")
+
+    def render(m=mode):
+        rc.rc_render(ctx, out["depth"], out["seg"], None, None, m, None, rays)
 
     def step():
         rc.rc_set_sensor_poses(ctx, R.sensor_T)
+        rc.rc_set_instance_poses(ctx, R.inst_T)
         rc.rc_build(ctx)
-        rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays)
-
-    def timed(fn, k):
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        s.record()
-        for _ in range(k):
-            fn()
-        e.record()
-        torch.cuda.synchronize()
-        return s.elapsed_time(e) / k
+        render()
 
     log("warmup")
     for _ in range(args.warmup):
@@ -146,29 +141,33 @@ def main():
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     ms = timed(step, args.steps)
-    log(f"step {ms:.3f} ms")
-    # components on the same stream
-    ms_render = timed(lambda: rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays), args.steps)
+    ms_render = timed(render, args.steps)
     ms_build = timed(lambda: rc.rc_build(ctx), max(2, args.steps // 2))
 
     def refit_step():
         rc.rc_set_sensor_poses(ctx, R.sensor_T)
         rc.rc_set_instance_poses(ctx, R.inst_T)
         rc.rc_refit(ctx)
-        rc.rc_render(ctx, out["depth"], out["seg"], None, None, mode, None, rays)
+        render()
 
     ms_refit_step = timed(refit_step, max(2, args.steps // 2))
-    log(f"render {ms_render:.3f} ms, build {ms_build:.3f} ms, refit step {ms_refit_step:.3f} ms")
+    log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, build {ms_build:.3f} ms, refit step {ms_refit_step:.3f} ms")
     plain = None
-    if not args.no_plain and mode != rc.RC_RENDER_PLAIN:
-        ms_plain = timed(lambda: rc.rc_render(ctx, out["depth"], out["seg"], None, None, rc.RC_RENDER_PLAIN, None,
-                                              rays), max(2, args.steps // 2))
-        plain = {"ms_render": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_vs_plain": ms_plain / ms_render}
-        log(f"plain render {ms_plain:.3f} ms")
+    if not args.no_plain:
+        def plain_step():
+            rc.rc_set_sensor_poses(ctx, R.sensor_T)
+            rc.rc_set_instance_poses(ctx, R.inst_T)
+            rc.rc_build(ctx)
+            render(rc.RC_RENDER_PLAIN)
+        ms_plain = timed(plain_step, max(2, args.steps // 4))
+        ms_plain_render = timed(lambda: render(rc.RC_RENDER_PLAIN), max(2, args.steps // 4))
+        plain = {"ms_per_step": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "ms_render": ms_plain_render,
+                 "render_Mrays_s": rays / ms_plain_render / 1e3, "speedup_batched_vs_plain": ms_plain / ms,
+                 "render_speedup_batched_vs_plain": ms_plain_render / ms_render}
+        log(f"plain step {ms_plain:.3f} ms, plain render {ms_plain_render:.3f} ms")
     stats = R.stats()
     from bytemodel import bytemodel
-    bm = bytemodel.load()[f"cfg{args.cfg}"]
-    b_ray = bm["bytes_per_ray"]
+    b_ray = bytemodel.load()[f"cfg{args.cfg}"]["bytes_per_ray"]
     achieved = b_ray * rays / (ms_render * 1e-3) / 1e9
     kernel = "k_render_batched" if mode == rc.RC_RENDER_BATCHED else "k_render_flat"
     traffic = traffic_record(kernel, args.cfg)
@@ -188,8 +187,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"cfg{args.cfg}: {WORKLOADS[args.cfg]}", "envs": n_envs, "rays_per_step": rays,
-                   "mode": args.mode, "outputs": "depth+seg",
-                   "step": "sensor poses + transform of every instance + SAH build of every env + render"},
+                   "mode": args.mode, "outputs": "depth+seg", "tuning": tuning,
+                   "step": "sensor poses + instance poses + transform of every instance + SAH build of every "
+                           "env + render"},
         "env_steps_per_s": n_envs / (ms * 1e-3),
         "render_ms": ms_render,
         "render_Mrays_s": rays / ms_render / 1e3,
@@ -210,7 +210,176 @@ def main():
     R.close()
     del out
     torch.cuda.synchronize()
-    if not args.no_cpu:
+    return result
+
+
+# --------------------------------------------------------------------------
+# cfg 4: uneven batch, moving obstacles, one HIP graph per step
+# --------------------------------------------------------------------------
+def bench_graph(args):
+    import torch
+    from paper_2503_01471_amd import rc, scenes
+    from paper_2503_01471_amd.renderer import Renderer
+
+    log("generating cfg4")
+    scene = scenes.make(4)
+    R = Renderer(scene, build=True)
+    rays, ctx = R.total_rays, R.ctx
+    tuning = rc.rc_autotune(ctx, args.tune_cache) if not args.no_autotune else None
+    out = R.alloc(depth=True, seg=True)
+    g = rc.rc_step_graph_create(ctx, R.inst_vel, float(scene.dt), depth=out["depth"], seg=out["seg"],
+                                total_rays=rays)
+    n_steps = 100
+    rc.rc_graph_set_step(g, 0)
+    for _ in range(10):
+        rc.rc_graph_launch(g)
+    rc.rc_graph_set_step(g, 0)
+    ms = timed(lambda: rc.rc_graph_launch(g), n_steps)
+    log(f"graph step {ms:.3f} ms")
+
+    step = [0]
+
+    def plain_step():
+        R.move(step[0])
+        R.refit()
+        rc.rc_render(ctx, out["depth"], out["seg"], None, None, rc.RC_RENDER_PLAIN, None, rays)
+        step[0] += 1
+
+    ms_plain = timed(plain_step, 5)
+    log(f"plain step {ms_plain:.3f} ms")
+    rc.rc_graph_destroy(g)
+    R.close()
+    return {"metric": METRIC, "value": rays / ms / 1e3, "unit": "Mrays/s", "n_gpus": 1, "steps": n_steps,
+            "warmup": 10, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"cfg4: {WORKLOADS[4]}", "envs": scene.n_envs, "rays_per_step": rays,
+                       "tuning": tuning, "step": "move + transform + refit + queue reset + batched render (graph)"},
+            "env_steps_per_s": scene.n_envs / (ms * 1e-3),
+            "plain": {"ms_per_step": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_graph_vs_plain":
+                      ms_plain / ms}}
+
+
+# --------------------------------------------------------------------------
+# cfg 5: serving
+# --------------------------------------------------------------------------
+def make_requests(n_envs_pool, n_sensors, n_req, rate, seed):
+    import numpy as np
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 5]))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    reqs = []
+    for _ in range(n_req):
+        k = int(rng.integers(1, 513))
+        envs = rng.choice(n_envs_pool, k, replace=False).astype(np.int32)
+        reqs.append((envs, int(rng.integers(0, n_sensors))))
+    return arrivals, reqs
+
+
+def serve_run(R, reqs, arrivals, mode, budget, n_streams, scratch):
+    """Submit requests at their arrival times; every request writes its full
+    outputs into one shared scratch buffer (contents discarded)."""
+    import numpy as np
+    from paper_2503_01471_amd import rc
+    srv = rc.rc_server_create(R.ctx, mode, n_streams, budget)
+    lat = []
+    tickets = []
+    rays = 0
+    try:
+        t0 = time.perf_counter()
+        for i, (envs, sid) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            tickets.append(rc.rc_server_submit(srv, envs, sid, scratch[0], scratch[1]))
+            rays += len(envs) * R.scene.sensors[sid].n_rays
+        for t in tickets:
+            lat.append(rc.rc_server_wait(srv, t))
+        t_end = time.perf_counter()
+    finally:
+        rc.rc_server_destroy(srv)
+    lat = np.array(lat)
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "Mrays_s": rays / (t_end - t0) / 1e6, "offered_req_s": len(reqs) / arrivals[-1],
+            "wall_s": t_end - t0}
+
+
+def bench_serve(args, short=False):
+    import torch
+    from paper_2503_01471_amd import rc, scenes
+    from paper_2503_01471_amd.renderer import Renderer
+
+    log("generating the resident pool (cfg4 scenes at step 0)")
+    scene = scenes.make(4)
+    R = Renderer(scene, build=True)
+    if not args.no_autotune:
+        rc.rc_autotune(R.ctx, args.tune_cache)
+    max_rays = 512 * max(s.n_rays for s in scene.sensors)
+    scratch = (torch.empty(max_rays, device="cuda"), torch.empty(max_rays, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    budget, K = 4 << 30, 4
+    n_full = 600 if short else args.requests
+    # saturated throughput: a burst of requests all arriving at t = 0
+    arr, reqs = make_requests(scene.n_envs, len(scene.sensors), 150 if short else 400, 1e9, 1)
+    sat = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, scratch)
+    mean_rays = sum(len(e) * scene.sensors[s].n_rays for e, s in reqs) / len(reqs)
+    sat_req_s = sat["Mrays_s"] * 1e6 / mean_rays
+    log(f"saturated {sat['Mrays_s']:.0f} Mrays/s ({sat_req_s:.0f} req/s)")
+    res = {"workload": f"cfg5: {WORKLOADS[5]}", "budget_bytes": budget, "streams": K,
+           "saturated_Mrays_s": sat["Mrays_s"], "saturated_req_s": sat_req_s}
+    # the stated arrival process (2000 req/s), batched
+    arr, reqs = make_requests(scene.n_envs, len(scene.sensors), n_full, 2000.0, 0)
+    res["stated_2000_req_s"] = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, scratch)
+    log(f"stated rate: {res['stated_2000_req_s']}")
+    # below saturation, where latency is meaningful; plain server on the same arrivals
+    sweep = []
+    for frac in ((0.5,) if short else (0.25, 0.5, 0.75)):
+        rate = frac * sat_req_s
+        n = max(40, int(rate * (2.0 if short else 5.0)))
+        arr, reqs = make_requests(scene.n_envs, len(scene.sensors), n, rate, 2)
+        b = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, scratch)
+        m = min(n, 40 if short else 120)
+        p = serve_run(R, reqs[:m], arr[:m], rc.RC_SERVE_PLAIN, budget, 1, scratch)
+        sweep.append({"load_frac": frac, "rate_req_s": rate, "batched": b, "plain_same_arrivals_first_n": p})
+        log(f"load {frac}: batched p50 {b['p50_ms']:.1f} p99 {b['p99_ms']:.1f} ms; plain p50 {p['p50_ms']:.1f} "
+            f"p99 {p['p99_ms']:.1f} ms")
+    res["sweep"] = sweep
+    R.close()
+    del scratch
+    torch.cuda.synchronize()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cfg", type=int, default=3, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--mode", default="batched", choices=["plain", "flat", "batched"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reused choices skip the timing)")
+    ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); environments shard across GPUs "
+              "with no exchange, so a multi-GPU run is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.cfg == 4:
+        result = bench_graph(args)
+    elif args.cfg == 5:
+        result = {"metric": METRIC, "n_gpus": 1, "data": "synthetic", "served": bench_serve(args)}
+    else:
+        result = bench_step(args)
+        if not args.no_serve and args.cfg == 3:
+            log("served summary")
+            result["served"] = bench_serve(args, short=True)
+    if not args.no_cpu and args.cfg in (1, 2, 3, 4):
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(args.cfg, args.cpu_seconds)
     print(json.dumps(result), flush=True)
