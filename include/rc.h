@@ -172,8 +172,8 @@ rc_status rc_refit(rc_context *ctx, void *stream);
 /* id).  Every mode computes bit-identical outputs:                          */
 /*   RC_RENDER_PLAIN   one launch per sensor instance (per-env path);        */
 /*   RC_RENDER_FLAT    one launch over every ray tile;                       */
-/*   RC_RENDER_BATCHED one persistent launch popping tiles from a device     */
-/*                     work queue (largest estimated cost first);            */
+/*   RC_RENDER_BATCHED one persistent launch popping tiles from device work  */
+/*                     queues, one per XCD (largest estimated cost first);   */
 /*   RC_RENDER_BRUTE   no BVH: every triangle tested (reference path).       */
 /* ------------------------------------------------------------------------ */
 #define RC_RENDER_PLAIN 0
@@ -198,17 +198,17 @@ rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
 /* Batched form: launch choices and one captured graph per simulation step.  */
 /* ------------------------------------------------------------------------ */
 /* Choose the ray-tile shape (columns x rows of one 64-lane wavefront: 4x16, */
-/* 8x8, 16x4 or 32x2), the persistent grid size (1 or 2 workgroups per      */
-/* resident slot) and the queue order (largest estimated cost first, or     */
-/* natural) of the batched render by timing each combination on the loaded */
+/* 8x8, 16x4 or 32x2), the tiles taken per work-queue pop (2, 4 or 16), the */
+/* queue order (largest estimated cost first, or natural) of the batched    */
+/* render by timing each combination on the loaded                          */
 /* scene, sensors and poses (temporary outputs are allocated within the     */
 /* budget).  cache_path (nullable): a text file of previous choices keyed   */
 /* by device and workload; a hit skips the timing, a miss appends a line.    */
-/* choice (nullable): host int32[3] = tile columns, grid scale, 1 if cost   */
-/* order.  Outputs are bit-identical for every choice.  Synchronous.        */
+/* choice (nullable): host int32[3] = tile columns, tiles per pop, 1 if     */
+/* cost order.  Outputs are bit-identical for every choice.  Synchronous.   */
 rc_status rc_autotune(rc_context *ctx, const char *cache_path, int32_t *choice);
 /* Set those choices directly: choice host int32[3] = tile columns (4, 8,   */
-/* 16 or 32), grid scale (1 or 2), cost order (0 or 1).                     */
+/* 16 or 32), tiles per pop (1..64), cost order (0 or 1).                   */
 rc_status rc_tuning_set(rc_context *ctx, const int32_t *choice);
 
 typedef struct rc_graph rc_graph;

@@ -111,6 +111,35 @@ SceneView Scene::sview() const
     return s;
 }
 
+QueueView Sensors::queue(int chunk) const
+{
+    QueueView q;
+    q.items = lpt_items.as<int2>();
+    for (int i = 0; i <= kQueues; ++i)
+        q.off[i] = qoff[i];
+    q.head = head.as<unsigned int>();
+    q.chunk = chunk;
+    return q;
+}
+
+void deal_queues(const std::vector<int64_t> &order, const std::vector<int64_t> &tiles, std::vector<int2> &items,
+                 int64_t off[kQueues + 1])
+{
+    std::vector<std::vector<int2>> per(kQueues);
+    for (size_t i = 0; i < order.size(); ++i) {
+        const int64_t s = order[i];
+        std::vector<int2> &dst = per[i % kQueues];
+        for (int64_t t = 0; t < tiles[s]; ++t)
+            dst.push_back(make_int2((int)s, (int)t));
+    }
+    items.clear();
+    off[0] = 0;
+    for (int q = 0; q < kQueues; ++q) {
+        items.insert(items.end(), per[q].begin(), per[q].end());
+        off[q + 1] = (int64_t)items.size();
+    }
+}
+
 SensorView Sensors::view() const
 {
     SensorView v;
@@ -204,11 +233,11 @@ rc_status rebuild_items(rc_context *c, Sensors &se)
         }
         std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
     }
+    std::vector<int64_t> tiles(S);
+    for (int64_t s = 0; s < S; ++s)
+        tiles[s] = se.item_off[s + 1] - se.item_off[s];
     std::vector<int2> lpt;
-    lpt.reserve(se.n_items);
-    for (int64_t s : order)
-        for (int64_t k = se.item_off[s]; k < se.item_off[s + 1]; ++k)
-            lpt.push_back(items[k]);
+    deal_queues(order, tiles, lpt, se.qoff);
     RC_HIP(hipStreamSynchronize(st));  // previous users of the old lists are done
     RC_TRY(upload(c, se.models, models.data(), models.size(), st));
     RC_TRY(upload(c, se.tables, tables.data(), tables.size(), st));
@@ -473,7 +502,7 @@ rc_status rc_sensors_attach(rc_context *c, const int64_t *sens_offsets, const in
     RC_TRY(upload(c, se->si_model_d, se->si_model.data(), S, st));
     RC_TRY(upload(c, se->d_ray_off, se->ray_off.data(), S + 1, st));
     RC_TRY(c->pool.alloc(se->pose, 48 * (size_t)S));
-    RC_TRY(c->pool.alloc(se->head, 256));
+    RC_TRY(c->pool.alloc(se->head, sizeof(unsigned int) * kQueues * kQueueStride));
     RC_TRY(c->pool.alloc(se->counters, 256));
     RC_TRY(rebuild_items(c, *se));
     c->sensors = std::move(se);
@@ -613,8 +642,7 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
         RC_HIP(launch_render_flat(sv, ev, ov, 0, se.n_items, st));
         break;
     case RC_RENDER_BATCHED:
-        RC_HIP(launch_render_batched(sv, ev, ov, se.lpt_items.as<int2>(), se.n_items, se.head.as<unsigned int>(),
-                                     c->batched_grid(), st));
+        RC_HIP(launch_render_batched(sv, ev, ov, se.queue(c->tuning.chunk), c->batched_grid(), st));
         break;
     case RC_RENDER_BRUTE:
         RC_HIP(launch_render_brute(sv, ev, ov, se.n_items, st));

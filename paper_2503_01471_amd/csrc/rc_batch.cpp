@@ -71,11 +71,11 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char k[1024];
-            int tw, gs, lpt;
-            while (fscanf(f, "%1023s %d %d %d", k, &tw, &gs, &lpt) == 4) {
-                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && (gs == 1 || gs == 2)) {
+            int tw, ch, lpt;
+            while (fscanf(f, "%1023s %d %d %d", k, &tw, &ch, &lpt) == 4) {
+                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && ch >= 1 && ch <= 64) {
                     best.tw_shift = __builtin_ctz(tw);
-                    best.grid_scale = gs;
+                    best.chunk = ch;
                     best.lpt = lpt != 0;
                     found = true;
                 }
@@ -93,10 +93,11 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
         RC_HIP(hipEventCreate(&e0));
         RC_HIP(hipEventCreate(&e1));
         float best_ms = 1e30f;
+        const int chunks[3] = {2, 4, 16};
         for (int tws = 2; tws <= 5; ++tws)
-            for (int gs = 1; gs <= 2; ++gs)
+            for (int ci = 0; ci < 3; ++ci)
                 for (int lpt = 1; lpt >= 0; --lpt) {
-                    c->tuning = Tuning{tws, gs, lpt != 0};
+                    c->tuning = Tuning{tws, chunks[ci], lpt != 0};
                     rc_status s = rebuild_items(c, se);
                     if (s != RC_OK) {
                         (void)hipEventDestroy(e0);
@@ -108,8 +109,8 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
                     for (int rep = 0; rep < 4; ++rep) {
                         if (rep == 1)
                             RC_HIP(hipEventRecord(e0, st));
-                        RC_HIP(launch_render_batched(sc.sview(), ev, ov, se.lpt_items.as<int2>(), se.n_items,
-                                                     se.head.as<unsigned int>(), c->batched_grid(), st));
+                        RC_HIP(launch_render_batched(sc.sview(), ev, ov, se.queue(c->tuning.chunk),
+                                                     c->batched_grid(), st));
                     }
                     RC_HIP(hipEventRecord(e1, st));
                     RC_HIP(hipEventSynchronize(e1));
@@ -123,7 +124,7 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
         (void)hipEventDestroy(e1);
         if (cache_path) {
             if (FILE *f = fopen(cache_path, "a")) {
-                fprintf(f, "%s %d %d %d\n", key.c_str(), 1 << best.tw_shift, best.grid_scale, best.lpt ? 1 : 0);
+                fprintf(f, "%s %d %d %d\n", key.c_str(), 1 << best.tw_shift, best.chunk, best.lpt ? 1 : 0);
                 fclose(f);
             }
         }
@@ -133,7 +134,7 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
     ++c->generation;
     if (choice) {
         choice[0] = 1 << best.tw_shift;
-        choice[1] = best.grid_scale;
+        choice[1] = best.chunk;
         choice[2] = best.lpt ? 1 : 0;
     }
     return RC_OK;
@@ -146,7 +147,7 @@ rc_status rc_tuning_set(rc_context *c, const int32_t *choice)
         return fail(RC_E_BUSY, "a request server is using this context");
     const int tw = choice[0];
     RC_CHECK(tw == 4 || tw == 8 || tw == 16 || tw == 32, "tile columns must be 4, 8, 16 or 32");
-    RC_CHECK(choice[1] == 1 || choice[1] == 2, "grid scale must be 1 or 2");
+    RC_CHECK(choice[1] >= 1 && choice[1] <= 64, "tiles per pop must be in [1, 64]");
     RC_CHECK(choice[2] == 0 || choice[2] == 1, "cost order must be 0 or 1");
     c->tuning = Tuning{__builtin_ctz(tw), choice[1], choice[2] != 0};
     if (c->sensors) {
@@ -196,8 +197,7 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
         if (k == hipSuccess)
             k = launch_refit(v, cs);
         if (k == hipSuccess)
-            k = launch_render_batched(sc.sview(), se.view(), ov, se.lpt_items.as<int2>(), se.n_items,
-                                      se.head.as<unsigned int>(), c->batched_grid(), cs);
+            k = launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk), c->batched_grid(), cs);
         if (k == hipSuccess)
             k = launch_bump(g->step.as<int32_t>(), cs);
         e = hipStreamEndCapture(cs, &g->graph);

@@ -14,9 +14,12 @@ namespace rc {
 // env_tri_off[e]); < 0 leaf ~(first << 3 | (count - 1)) over the
 // environment's leaf-ordered triangle records.
 // ---------------------------------------------------------------------------
-constexpr int kLeafMax = 4;        // triangles per leaf (<= 8 by the encoding)
-constexpr int kMaxNodeDepth = 30;  // internal-node depth bound enforced by the builder
-constexpr int kStack = 32;         // traversal stack entries (> kMaxNodeDepth)
+#ifndef RC_MAX_NODE_DEPTH
+#define RC_MAX_NODE_DEPTH 30
+#endif
+constexpr int kLeafMax = 4;                        // triangles per leaf (<= 8 by the encoding)
+constexpr int kMaxNodeDepth = RC_MAX_NODE_DEPTH;   // internal-node depth bound enforced by the builder
+constexpr int kStack = RC_MAX_NODE_DEPTH + 2;      // traversal stack entries (> kMaxNodeDepth)
 constexpr int kBins = 16;          // SAH bins per axis
 constexpr int kEmptyRoot = INT32_MIN;
 
@@ -127,8 +130,20 @@ hipError_t launch_refit(const BuildView &v, hipStream_t st);
 
 hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const OutView &o, int64_t item_begin,
                               int64_t n_items, hipStream_t st);
-hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const int2 *lpt_items,
-                                 int64_t n_items, unsigned int *head, int grid, hipStream_t st);
+// Persistent-form work queues: one per XCD (blocks are dealt round-robin to
+// the 8 XCDs, so block b serves queue b % 8 first), counters kQueueStride
+// words apart; a wavefront pops `chunk` tiles at a time and moves on to the
+// next queue when its own is empty.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 64;
+struct QueueView {
+    const int2 *items;          // kQueues consecutive ranges of (sensor instance, tile)
+    int64_t off[kQueues + 1];   // range q = [off[q], off[q+1])
+    unsigned int *head;         // kQueues * kQueueStride counters
+    int chunk;                  // tiles per pop
+};
+hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const QueueView &q,
+                                 int grid, hipStream_t st);
 int batched_blocks_per_cu();
 hipError_t launch_render_brute(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
                                hipStream_t st);

@@ -26,6 +26,11 @@ constexpr float kU = 0x1p-24f;              // unit roundoff
 constexpr float kErr = 0x1p-17f;            // triple-product error factor (>= 48 u)
 constexpr float kBoxGrow = 1.0f + 0x1p-20f;  // >= 1 + 4 gamma_3 (robust slab test)
 constexpr int kBlock = 256;
+#ifdef RC_MIN_WAVES
+#define RC_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(RC_MIN_WAVES, 8)))
+#else
+#define RC_WAVES_PER_EU
+#endif
 
 struct Ray {
     float ox, oy, oz;
@@ -396,7 +401,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return x * q + (x < rem ? x : rem) + (b >> 3);
 }
 
-__global__ __launch_bounds__(kBlock) void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
+__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
                                                         int64_t n_items)
 {
     __shared__ int s_stack[kStack * kBlock];
@@ -408,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_render_flat(SceneView sc, SensorView
     render_tile<false>(sc, se, o, se.items[item_begin + k], s_stack + threadIdx.x, st);
 }
 
-__global__ __launch_bounds__(kBlock) void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
+__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
                                                          unsigned long long *counters)
 {
     __shared__ int s_stack[kStack * kBlock];
@@ -432,22 +437,29 @@ __global__ __launch_bounds__(kBlock) void k_render_stats(SceneView sc, SensorVie
     }
 }
 
-// Persistent form: every wavefront pops tiles from a device queue.
-__global__ __launch_bounds__(kBlock) void k_render_batched(SceneView sc, SensorView se, OutView o,
-                                                           const int2 *__restrict__ items, int64_t n_items,
-                                                           unsigned int *head)
+// Persistent form: every wavefront pops `chunk` tiles at a time from its
+// XCD's queue and, once that is empty, from the other queues in turn.
+__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_batched(SceneView sc, SensorView se, OutView o,
+                                                                           QueueView q)
 {
     __shared__ int s_stack[kStack * kBlock];
     const int lane = threadIdx.x & 63;
+    int qi = blockIdx.x & (kQueues - 1);
     Stats st{0, 0, 0};
-    while (true) {
-        unsigned int k = 0;
+    for (int exhausted = 0; exhausted < kQueues;) {
+        unsigned int base = 0;
         if (lane == 0)
-            k = atomicAdd(head, 1u);
-        k = (unsigned)uniform((int)k);
-        if ((int64_t)k >= n_items)
-            break;
-        render_tile<false>(sc, se, o, items[k], s_stack + threadIdx.x, st);
+            base = atomicAdd(q.head + qi * kQueueStride, (unsigned int)q.chunk);
+        base = (unsigned int)uniform((int)base);
+        const int64_t b = q.off[qi] + (int64_t)base, e = q.off[qi + 1];
+        if (b >= e) {
+            qi = (qi + 1) & (kQueues - 1);
+            ++exhausted;
+            continue;
+        }
+        const int64_t stop = b + q.chunk < e ? b + q.chunk : e;
+        for (int64_t k = b; k < stop; ++k)
+            render_tile<false>(sc, se, o, q.items[k], s_stack + threadIdx.x, st);
     }
 }
 
@@ -576,15 +588,15 @@ int batched_blocks_per_cu()
     return per_cu;
 }
 
-hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const int2 *lpt_items,
-                                 int64_t n_items, unsigned int *head, int grid, hipStream_t st)
+hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const QueueView &q,
+                                 int grid, hipStream_t st)
 {
-    if (n_items == 0)
+    if (q.off[kQueues] == 0)
         return hipSuccess;
-    hipError_t err = launch_fill_u32(head, 1, 0u, st);
+    hipError_t err = launch_fill_u32(q.head, kQueues * kQueueStride, 0u, st);
     if (err != hipSuccess)
         return err;
-    hipLaunchKernelGGL(k_render_batched, dim3(grid), dim3(kBlock), 0, st, sc, se, o, lpt_items, n_items, head);
+    hipLaunchKernelGGL(k_render_batched, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
     return hipGetLastError();
 }
 

@@ -87,14 +87,16 @@ struct Sensors {
     std::vector<int64_t> ray_off, item_off, sens_offsets;
     std::vector<int32_t> si_env, si_model;
     DBuf models, tables, si_env_d, si_model_d, d_ray_off, pose, items, lpt_items, head, counters;
+    int64_t qoff[kQueues + 1] = {};  // queue ranges of lpt_items
     bool poses_set = false;
     SensorView view() const;
+    QueueView queue(int chunk) const;
 };
 
 // Launch choices of the batched form (set by rc_autotune).
 struct Tuning {
     int tw_shift = 3;     // ray tile 8 x 8
-    int grid_scale = 1;   // persistent workgroups per CU slot
+    int chunk = 4;        // tiles per queue pop
     bool lpt = true;      // queue in decreasing estimated cost
 };
 
@@ -114,10 +116,15 @@ struct rc_context {
     int n_cu = 0, blocks_per_cu = 1;
     uint64_t generation = 0;   // bumped whenever scene or sensors are replaced
     std::atomic<int> servers{0};  // live request servers (scene is read-only meanwhile)
-    int batched_grid() const { return n_cu * blocks_per_cu * tuning.grid_scale; }
+    int batched_grid() const { return n_cu * blocks_per_cu; }
 };
 
 namespace rc {
+// Deal sensor instances (in priority order) round-robin to the kQueues
+// queues; each queue keeps the order and the tiles of one instance together.
+// tiles[s] = number of tiles of sensor instance s.
+void deal_queues(const std::vector<int64_t> &order, const std::vector<int64_t> &tiles, std::vector<int2> &items,
+                 int64_t off[kQueues + 1]);
 rc_status set_device(const rc_context *c);
 const char *last_error();
 // (Re)build the tile work lists of sensors `se` for the current tuning.

@@ -118,7 +118,7 @@ rc_status launch(rc_server *sv, Slot &sl)
         sl.cap_items = (int64_t)(sl.items.n / 8);
     }
     if (!sl.head.p)
-        RC_TRY(c->pool.alloc(sl.head, 256));
+        RC_TRY(c->pool.alloc(sl.head, sizeof(unsigned int) * kQueues * kQueueStride));
     // staging layout: items | si_env | si_model | pose | dtab | stab
     const size_t o_items = 0, o_env = o_items + 8 * n_items, o_model = o_env + 4 * S, o_pose = o_model + 4 * S,
                  o_dtab = o_pose + 48 * S, o_stab = o_dtab + 8 * S, total = o_stab + 8 * S;
@@ -137,8 +137,9 @@ rc_status launch(rc_server *sv, Slot &sl)
     float *pose = (float *)(h + o_pose);
     float **dtab = (float **)(h + o_dtab);
     int32_t **stab = (int32_t **)(h + o_stab);
-    int64_t k = 0, it = 0;
-    std::vector<int64_t> item_begin;  // per sensor instance (plain mode)
+    int64_t k = 0;
+    std::vector<int64_t> item_begin;  // per sensor instance, request order (plain mode)
+    std::vector<int64_t> order, tiles;  // batched mode: queue order of the sensor instances
     for (Req *r : sl.reqs) {
         const SensorModel &m = sv->models[r->model];
         for (size_t i = 0; i < r->envs.size(); ++i, ++k) {
@@ -147,12 +148,24 @@ rc_status launch(rc_server *sv, Slot &sl)
             memcpy(pose + 12 * k, r->poses.data() + 12 * i, 48);
             dtab[k] = r->depth ? r->depth + (int64_t)i * r->rays_per_env : nullptr;
             stab[k] = r->seg ? r->seg + (int64_t)i * r->rays_per_env : nullptr;
-            item_begin.push_back(it);
-            for (int t = 0; t < m.tiles; ++t)
-                items[it++] = make_int2((int)k, t);
+            order.push_back(k);
+            tiles.push_back(m.tiles);
         }
     }
-    item_begin.push_back(it);
+    int64_t qoff[kQueues + 1];
+    if (sv->mode == RC_SERVE_BATCHED) {
+        std::vector<int2> dealt;
+        deal_queues(order, tiles, dealt, qoff);
+        memcpy(items, dealt.data(), sizeof(int2) * dealt.size());
+    } else {
+        int64_t it = 0;
+        for (int64_t s = 0; s < k; ++s) {
+            item_begin.push_back(it);
+            for (int64_t t = 0; t < tiles[s]; ++t)
+                items[it++] = make_int2((int)s, (int)t);
+        }
+        item_begin.push_back(it);
+    }
     hipStream_t st = sl.stream;
     RC_HIP(hipMemcpyAsync(sl.items.p, h + o_items, 8 * n_items, hipMemcpyHostToDevice, st));
     RC_HIP(hipMemcpyAsync(sl.si_env.p, h + o_env, 4 * S, hipMemcpyHostToDevice, st));
@@ -170,8 +183,13 @@ rc_status launch(rc_server *sv, Slot &sl)
     ev.items = sl.items.as<int2>();
     const OutView ov{nullptr, nullptr, nullptr, nullptr, sl.dtab.as<float *>(), sl.stab.as<int32_t *>()};
     if (sv->mode == RC_SERVE_BATCHED) {
-        RC_HIP(launch_render_batched(sc.sview(), ev, ov, ev.items, n_items, sl.head.as<unsigned int>(),
-                                     c->batched_grid(), st));
+        QueueView qv;
+        qv.items = ev.items;
+        for (int i = 0; i <= kQueues; ++i)
+            qv.off[i] = qoff[i];
+        qv.head = sl.head.as<unsigned int>();
+        qv.chunk = c->tuning.chunk;
+        RC_HIP(launch_render_batched(sc.sview(), ev, ov, qv, c->batched_grid(), st));
     } else {
         for (int64_t s = 0; s < S; ++s)
             RC_HIP(launch_render_flat(sc.sview(), ev, ov, item_begin[s], item_begin[s + 1] - item_begin[s], st));
