@@ -3,11 +3,14 @@
 
 Default (headline) workload: 4096 environments, each with one rotating LiDAR
 of 64 channels x 512 azimuths in a 60-tree forest (4802 triangles per
-environment), 134,217,728 rays per step.  One step = one pass of the whole
-rendering hot path over every environment: sensor poses uploaded, every
-instance transformed, one SAH BVH built per environment, every ray generated,
-traversed and written (range + segmentation), in the batched form (one
-persistent launch, device work queue, autotuned launch shape).
+environment), 134,217,728 rays per step.  One step = one pass of the rendering
+hot path over every environment with every object treated as moving: sensor
+and instance poses uploaded, every instance re-transformed, every
+environment's BVH refitted, every ray generated, traversed and written
+(range + segmentation) in the batched form (one persistent launch, per-XCD
+device work queues, autotuned launch shape).  The reset path (a full SAH
+rebuild of every BVH, done at randomisation) is timed beside it, alone and as
+a step that rebuilds instead of refitting.
 
 Prints ONE JSON line: Mrays/s (whole job), env-steps/s, the render kernel's
 roofline position, the same step on the plain per-environment path, a short
@@ -117,6 +120,7 @@ def bench_step(args):
     mode = {"plain": rc.RC_RENDER_PLAIN, "flat": rc.RC_RENDER_FLAT, "batched": rc.RC_RENDER_BATCHED}[args.mode]
     log(f"generating cfg{args.cfg}")
     scene = scenes.make(args.cfg)
+    scene.inst_dynamic[:] = 1  # every object may move: re-transform and refit all of them each step
     n_envs = scene.n_envs
     log(f"loading {n_envs} envs, {int(scene.env_tri_counts().sum())} tris, {scene.total_rays()} rays")
     R = Renderer(scene, build=True)
@@ -132,6 +136,12 @@ def bench_step(args):
     def step():
         rc.rc_set_sensor_poses(ctx, R.sensor_T)
         rc.rc_set_instance_poses(ctx, R.inst_T)
+        rc.rc_refit(ctx)
+        render()
+
+    def rebuild_step():
+        rc.rc_set_sensor_poses(ctx, R.sensor_T)
+        rc.rc_set_instance_poses(ctx, R.inst_T)
         rc.rc_build(ctx)
         render()
 
@@ -142,22 +152,17 @@ def bench_step(args):
     log(f"timing {args.steps} steps")
     ms = timed(step, args.steps)
     ms_render = timed(render, args.steps)
+    ms_refit = timed(lambda: rc.rc_refit(ctx), args.steps)
     ms_build = timed(lambda: rc.rc_build(ctx), max(2, args.steps // 2))
-
-    def refit_step():
-        rc.rc_set_sensor_poses(ctx, R.sensor_T)
-        rc.rc_set_instance_poses(ctx, R.inst_T)
-        rc.rc_refit(ctx)
-        render()
-
-    ms_refit_step = timed(refit_step, max(2, args.steps // 2))
-    log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, build {ms_build:.3f} ms, refit step {ms_refit_step:.3f} ms")
+    ms_rebuild_step = timed(rebuild_step, max(2, args.steps // 2))
+    log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, transform+refit {ms_refit:.3f} ms; reset: build "
+        f"{ms_build:.3f} ms, step with rebuild {ms_rebuild_step:.3f} ms")
     plain = None
     if not args.no_plain:
         def plain_step():
             rc.rc_set_sensor_poses(ctx, R.sensor_T)
             rc.rc_set_instance_poses(ctx, R.inst_T)
-            rc.rc_build(ctx)
+            rc.rc_refit(ctx)
             render(rc.RC_RENDER_PLAIN)
         ms_plain = timed(plain_step, max(2, args.steps // 4))
         ms_plain_render = timed(lambda: render(rc.RC_RENDER_PLAIN), max(2, args.steps // 4))
@@ -188,14 +193,15 @@ def bench_step(args):
         "data": "synthetic",
         "config": {"workload": f"cfg{args.cfg}: {WORKLOADS[args.cfg]}", "envs": n_envs, "rays_per_step": rays,
                    "mode": args.mode, "outputs": "depth+seg", "tuning": tuning,
-                   "step": "sensor poses + instance poses + transform of every instance + SAH build of every "
-                           "env + render"},
+                   "step": "sensor + instance poses, transform of every instance, refit of every env's BVH, "
+                           "batched render"},
         "env_steps_per_s": n_envs / (ms * 1e-3),
         "render_ms": ms_render,
         "render_Mrays_s": rays / ms_render / 1e3,
-        "build_ms": ms_build,
-        "refit_step_ms": ms_refit_step,
-        "refit_step_Mrays_s": rays / ms_refit_step / 1e3,
+        "transform_refit_ms": ms_refit,
+        "reset": {"sah_build_ms": ms_build, "step_with_rebuild_ms": ms_rebuild_step,
+                  "step_with_rebuild_Mrays_s": rays / ms_rebuild_step / 1e3,
+                  "env_steps_per_s": n_envs / (ms_rebuild_step * 1e-3)},
         "plain": plain,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
                       "fp64_evals_per_ray": stats[2] / rays},

@@ -145,7 +145,10 @@ __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 // stack is back at its height, is one of its descendants.
 // ---------------------------------------------------------------------------
 constexpr int kTaskCap = kMaxNodeDepth + 4;
-constexpr int kSmall = 128;   // subtrees up to this size are built from LDS
+#ifndef RC_SMALL
+#define RC_SMALL 128
+#endif
+constexpr int kSmall = RC_SMALL;  // subtrees up to this size are built from LDS
 constexpr int kMicro = 16;    // ranges of 5..16 go to the per-thread builder
 
 struct WaveBox {

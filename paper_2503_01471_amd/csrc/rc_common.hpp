@@ -20,7 +20,10 @@ namespace rc {
 constexpr int kLeafMax = 4;                        // triangles per leaf (<= 8 by the encoding)
 constexpr int kMaxNodeDepth = RC_MAX_NODE_DEPTH;   // internal-node depth bound enforced by the builder
 constexpr int kStack = RC_MAX_NODE_DEPTH + 2;      // traversal stack entries (> kMaxNodeDepth)
-constexpr int kBins = 16;          // SAH bins per axis
+#ifndef RC_BINS
+#define RC_BINS 16
+#endif
+constexpr int kBins = RC_BINS;     // SAH bins per axis
 constexpr int kEmptyRoot = INT32_MIN;
 
 struct alignas(16) Node {

@@ -274,15 +274,25 @@ __device__ __forceinline__ void offer(const Ray &r, const TriRec *__restrict__ r
     }
 }
 
-// Stack-based traversal of one ray (nearest child first).
+// Stack-based traversal of one ray (nearest child first), in two phases per
+// round so that the wavefront stays converged: phase 1 walks internal nodes
+// and postpones the first leaf it meets (continuing down the tree until every
+// active lane holds a leaf or finishes); phase 2 tests the postponed leaves.
+constexpr int kDone = INT32_MIN;  // never a leaf reference
+
 template <bool STATS>
 __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ nodes,
                                          const TriRec *__restrict__ recs, int root, int *stk, Best &b, Stats &st)
 {
     int sp = 0;
-    int ref = root;
+    int ref = root;   // next node to visit (internal >= 0, leaf < 0) or kDone
+    int leaf = kDone; // postponed leaf
+    if (root < 0) {   // the whole tree is one leaf
+        leaf = root;
+        ref = kDone;
+    }
     while (true) {
-        if (ref >= 0) {
+        while (ref >= 0) {
             const Node *n = nodes + ref;
             const float4 a = n->xy0, c = n->xy1, z = n->z01;
             const int4 ch = n->ch;
@@ -296,14 +306,20 @@ __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ 
                 stk[sp * kBlock] = first0 ? ch.y : ch.x;
                 ++sp;
                 ref = first0 ? ch.x : ch.y;
-                continue;
-            }
-            if (h0 || h1) {
+            } else if (h0 || h1) {
                 ref = h0 ? ch.x : ch.y;
-                continue;
+            } else {
+                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
             }
-        } else {
-            const int code = ~ref;
+            if (ref < 0 && ref != kDone && leaf == kDone) {
+                leaf = ref;
+                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+            }
+            if (__all(leaf != kDone))
+                break;
+        }
+        while (leaf != kDone) {
+            const int code = ~leaf;
             const int first = code >> 3, cnt = (code & 7) + 1;
             for (int k = 0; k < cnt; ++k) {
                 const TriRec T = recs[first + k];
@@ -311,11 +327,15 @@ __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ 
                     ++st.tri;
                 offer<STATS>(r, recs, first + k, T.a, T.b, T.c, b, st);
             }
+            if (ref < 0 && ref != kDone) {
+                leaf = ref;
+                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+            } else {
+                leaf = kDone;
+            }
         }
-        if (sp == 0)
+        if (ref == kDone)
             break;
-        --sp;
-        ref = stk[sp * kBlock];
     }
 }
 
