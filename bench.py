@@ -293,7 +293,7 @@ def serve_run(R, reqs, arrivals, mode, budget, n_streams, scratch):
         t0 = time.perf_counter()
         for i, (envs, sid) in enumerate(reqs):
             while time.perf_counter() - t0 < arrivals[i]:
-                pass
+                time.sleep(0)  # yield the GIL: the server's worker may call back into Python
             tickets.append(rc.rc_server_submit(srv, envs, sid, scratch[0], scratch[1]))
             rays += len(envs) * R.scene.sensors[sid].n_rays
         for t in tickets:

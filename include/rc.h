@@ -56,11 +56,22 @@ const char *rc_last_error(void);
 /* ------------------------------------------------------------------------ */
 /* Context.                                                                  */
 /* device: HIP device ordinal; stream: default hipStream_t for the context's */
-/* work (NULL = the null stream); hbm_budget: cap in bytes on library-owned  */
+/* work (NULL = the null stream); alloc: optional allocator for every        */
+/* library-owned device buffer (NULL = hipMalloc / hipFree), e.g. a          */
+/* framework's caching allocator; the struct is copied.  alloc(user, bytes,  */
+/* stream) returns device memory or NULL (reported as RC_E_OOM);             */
+/* free(user, ptr, bytes, stream) is called only after the device has        */
+/* finished every use of ptr.  Either hook may be called from the request    */
+/* server's worker thread.  hbm_budget: cap in bytes on library-owned        */
 /* device memory (0 = no cap).  Allocation above the cap fails with          */
 /* RC_E_OOM and leaves the previous state intact.                            */
 /* ------------------------------------------------------------------------ */
-rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context **out);
+typedef struct {
+    void *(*alloc)(void *user, size_t bytes, void *stream);
+    void (*free)(void *user, void *ptr, size_t bytes, void *stream);
+    void *user;
+} rc_allocator;
+rc_status rc_create(int32_t device, void *stream, const rc_allocator *alloc, size_t hbm_budget, rc_context **out);
 rc_status rc_destroy(rc_context *ctx);
 /* Library-owned device bytes currently allocated. */
 rc_status rc_memory_used(const rc_context *ctx, size_t *bytes);
@@ -153,10 +164,15 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /* heuristic, one wavefront per environment).  rc_refit re-transforms the    */
 /* dynamic instances and recomputes the bounds bottom-up on the fixed        */
 /* topology.  Both are asynchronous on `stream`.                             */
+/* d_env_mask: NULL (every environment) or a caller DEVICE uint8[n_envs],    */
+/* read on `stream`; environments whose byte is 0 are left exactly as they  */
+/* are (world triangles, BVH, records), so e.g. the environments reset by a  */
+/* randomisation can be rebuilt alone.  A masked rc_build needs a full       */
+/* build first (RC_E_STATE).                                                 */
 /* ------------------------------------------------------------------------ */
 #define RC_BUILD_SAH 0
-rc_status rc_build(rc_context *ctx, int32_t builder, void *stream);
-rc_status rc_refit(rc_context *ctx, void *stream);
+rc_status rc_build(rc_context *ctx, const uint8_t *d_env_mask, int32_t builder, void *stream);
+rc_status rc_refit(rc_context *ctx, const uint8_t *d_env_mask, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Render (Sec. III-D: one ray per pixel or beam, nearest hit over the       */

@@ -44,12 +44,26 @@ const char *last_error() { return g_err.c_str(); }
 void DBuf::reset()
 {
     if (p) {
-        (void)hipFree(p);
         if (pool)
-            pool->used -= n;
+            pool->release(p, n);
+        else
+            (void)hipFree(p);
     }
     p = nullptr;
     n = 0;
+}
+
+void Pool::release(void *p, size_t bytes)
+{
+    if (hook.alloc) {
+        // the caller's allocator may hand the block out at once: let every
+        // queued use of it finish first (hipFree does the same implicitly)
+        (void)hipDeviceSynchronize();
+        hook.free(hook.user, p, bytes, (void *)stream);
+    } else {
+        (void)hipFree(p);
+    }
+    used -= bytes;
 }
 
 rc_status Pool::alloc(DBuf &b, size_t bytes)
@@ -60,10 +74,16 @@ rc_status Pool::alloc(DBuf &b, size_t bytes)
     if (budget && used + bytes > budget)
         return fail(RC_E_OOM, "memory budget exceeded: %zu used + %zu requested > %zu", (size_t)used, bytes, budget);
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(RC_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    if (hook.alloc) {
+        p = hook.alloc(hook.user, bytes, (void *)stream);
+        if (!p)
+            return fail(RC_E_OOM, "allocator hook returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RC_E_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
     }
     b.p = p;
     b.n = bytes;
@@ -95,6 +115,7 @@ BuildView Scene::view() const
     v.env_nodes = env_nodes.as<int32_t>();
     v.env_micro = env_micro.as<int32_t>();
     v.micro = micro.as<int4>();
+    v.env_mask = nullptr;
     return v;
 }
 
@@ -267,10 +288,11 @@ const char *rc_status_string(rc_status s)
 
 const char *rc_last_error(void) { return rc::last_error(); }
 
-rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context **out)
+rc_status rc_create(int32_t device, void *stream, const rc_allocator *alloc, size_t hbm_budget, rc_context **out)
 {
     RC_CHECK(out, "out is NULL");
     *out = nullptr;
+    RC_CHECK(!alloc || (alloc->alloc && alloc->free), "allocator needs both alloc and free");
     int n = 0;
     RC_HIP(hipGetDeviceCount(&n));
     RC_CHECK(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
@@ -279,6 +301,9 @@ rc_status rc_create(int32_t device, void *stream, size_t hbm_budget, rc_context 
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->pool.budget = hbm_budget;
+    c->pool.stream = (hipStream_t)stream;
+    if (alloc)
+        c->pool.hook = *alloc;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
         delete c;
@@ -578,7 +603,7 @@ rc_status rc_move_instances(rc_context *c, const float *d_vel, int32_t step, flo
     return RC_OK;
 }
 
-rc_status rc_build(rc_context *c, int32_t builder, void *stream)
+rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, void *stream)
 {
     RC_CHECK(c, "NULL context");
     RC_TRY(busy_check(c));
@@ -586,16 +611,19 @@ rc_status rc_build(rc_context *c, int32_t builder, void *stream)
     if (!c->scene || !c->scene->poses_set)
         return fail(RC_E_STATE, "rc_build needs a scene and instance poses");
     Scene &sc = *c->scene;
+    if (d_env_mask && !sc.built)
+        return fail(RC_E_STATE, "a masked rc_build needs a full build first");
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
-    const BuildView v = sc.view();
+    BuildView v = sc.view();
+    v.env_mask = d_env_mask;
     RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
     RC_HIP(launch_build_sah(v, st));
     sc.built = true;
     return RC_OK;
 }
 
-rc_status rc_refit(rc_context *c, void *stream)
+rc_status rc_refit(rc_context *c, const uint8_t *d_env_mask, void *stream)
 {
     RC_CHECK(c, "NULL context");
     RC_TRY(busy_check(c));
@@ -604,7 +632,8 @@ rc_status rc_refit(rc_context *c, void *stream)
     Scene &sc = *c->scene;
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
-    const BuildView v = sc.view();
+    BuildView v = sc.view();
+    v.env_mask = d_env_mask;
     RC_HIP(launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, st));
     RC_HIP(launch_refit(v, st));
     return RC_OK;

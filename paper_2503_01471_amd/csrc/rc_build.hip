@@ -66,6 +66,8 @@ __global__ __launch_bounds__(256) void k_transform(BuildView v, const int32_t *_
     if (k >= n)
         return;
     const int64_t g = tri_list ? tri_list[k] : k;
+    if (masked_out(v, v.tri_env[g]))
+        return;
     const int2 src = v.tri_src[g];
     const float *A = v.inst_T + 12 * (int64_t)src.x;
     float w[9];
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(256) void k_move(int64_t n, const float *__restrict
 __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= v.n_tris)
+    if (g >= v.n_tris || masked_out(v, v.tri_env[g]))
         return;
     const float *w = v.world + 9 * g;
     const float lx = fminf(fminf(w[0], w[3]), w[6]), hx = fmaxf(fmaxf(w[0], w[3]), w[6]);
@@ -194,6 +196,8 @@ __device__ __forceinline__ void write_boxes(Node &nd, const WaveBox &L, const Wa
 __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 {
     const int e = blockIdx.x;
+    if (masked_out(v, e))
+        return;
     const int lane = threadIdx.x;
     const int64_t base = v.env_tri_off[e];
     const int n = (int)(v.env_tri_off[e + 1] - base);
@@ -631,6 +635,8 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
     if (g >= v.n_tris)
         return;
     const int e = v.tri_env[g];
+    if (masked_out(v, e))
+        return;
     const int64_t base = v.env_tri_off[e];
     const int j = (int)(g - base);
     if (j >= v.env_micro[e])
@@ -697,6 +703,8 @@ __global__ __launch_bounds__(256) void k_gather(BuildView v)
     if (g >= v.n_tris)
         return;
     const int e = v.tri_env[g];
+    if (masked_out(v, e))
+        return;
     const int64_t base = v.env_tri_off[e];
     const int i = (int)(g - base);
     const int id = v.prim[g];
@@ -757,6 +765,8 @@ constexpr int kRefitBlock = 256;
 __global__ __launch_bounds__(kRefitBlock) void k_refit(BuildView v)
 {
     const int e = blockIdx.x;
+    if (masked_out(v, e))
+        return;
     const int64_t base = v.env_tri_off[e];
     const int nn = v.env_nodes[e];
     Node *nodes = v.nodes + node_base(base, e);

@@ -118,7 +118,11 @@ struct BuildView {
     int32_t *env_nodes;          // [E] node slots per environment
     int32_t *env_micro;          // [E] deferred small ranges per environment
     int4 *micro;                 // [N] deferred ranges (node, begin, end, depth)
+    const uint8_t *env_mask;     // [E] environments to process (nullptr: all)
 };
+
+// True when environment e is excluded by the build/refit mask.
+__host__ __device__ inline bool masked_out(const BuildView &v, int e) { return v.env_mask && !v.env_mask[e]; }
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (rc_build.hip / rc_render.hip).

@@ -57,7 +57,10 @@ struct DBuf {
 struct Pool {
     size_t budget = 0;
     std::atomic<size_t> used{0};
+    rc_allocator hook{};      // caller allocator (hook.alloc == nullptr: hipMalloc)
+    hipStream_t stream = nullptr;
     rc_status alloc(DBuf &b, size_t bytes);
+    void release(void *p, size_t bytes);
 };
 
 struct Mesh {

@@ -12,6 +12,7 @@
 // their work overlaps on the device.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -56,6 +57,9 @@ struct Slot {
     int64_t cap_items = 0, cap_si = 0;
     void *host = nullptr;
     size_t host_cap = 0;
+    // tables replaced by larger ones: kept until the server is destroyed, so
+    // growing one never waits for the device
+    std::vector<std::unique_ptr<DBuf>> retired;
 };
 
 constexpr int64_t kMaxBatchRays = int64_t(48) << 20;  // bound on one admission round
@@ -84,12 +88,66 @@ struct rc_server {
 
 namespace {
 
-// Grow a device table (no budget check beyond the context pool).
-rc_status ensure(rc_context *c, DBuf &b, size_t bytes)
+// Grow a device table of a slot (no budget check beyond the context pool).
+rc_status ensure(rc_context *c, Slot &sl, DBuf &b, size_t bytes)
 {
     if (b.n >= bytes)
         return RC_OK;
+    if (b.p) {
+        auto old = std::make_unique<DBuf>();
+        std::swap(old->p, b.p);
+        std::swap(old->n, b.n);
+        std::swap(old->pool, b.pool);
+        sl.retired.push_back(std::move(old));
+    }
     return c->pool.alloc(b, bytes + bytes / 2);
+}
+
+// Byte offsets of the pinned staging block: items | si_env | si_model | pose | dtab | stab.
+struct Staging {
+    size_t o_items, o_env, o_model, o_pose, o_dtab, o_stab, total;
+    Staging(int64_t n_items, int64_t S)
+    {
+        o_items = 0;
+        o_env = o_items + 8 * n_items;
+        o_model = o_env + 4 * S;
+        o_pose = o_model + 4 * S;
+        o_dtab = o_pose + 48 * S;
+        o_stab = o_dtab + 8 * S;
+        total = o_stab + 8 * S;
+    }
+};
+
+// Make the slot's tables hold a batch of S sensor instances and n_items tiles.
+rc_status reserve(rc_context *c, Slot &sl, int64_t S, int64_t n_items)
+{
+    if (S > sl.cap_si) {
+        RC_TRY(ensure(c, sl, sl.si_env, 4 * S));
+        RC_TRY(ensure(c, sl, sl.si_model, 4 * S));
+        RC_TRY(ensure(c, sl, sl.ray_off, 8 * (S + 1)));
+        RC_TRY(ensure(c, sl, sl.pose, 48 * S));
+        RC_TRY(ensure(c, sl, sl.dtab, 8 * S));
+        RC_TRY(ensure(c, sl, sl.stab, 8 * S));
+        RC_HIP(hipMemsetAsync(sl.ray_off.p, 0, sl.ray_off.n, sl.stream));
+        sl.cap_si = (int64_t)(sl.si_env.n / 4);
+    }
+    if (n_items > sl.cap_items) {
+        RC_TRY(ensure(c, sl, sl.items, 8 * n_items));
+        sl.cap_items = (int64_t)(sl.items.n / 8);
+    }
+    if (!sl.head.p)
+        RC_TRY(c->pool.alloc(sl.head, sizeof(unsigned int) * kQueues * kQueueStride));
+    const Staging g(n_items, S);
+    if (g.total > sl.host_cap) {
+        // the slot is idle here: its previous batch has completed
+        if (sl.host)
+            RC_HIP(hipHostFree(sl.host));
+        sl.host = nullptr;
+        sl.host_cap = 0;
+        RC_HIP(hipHostMalloc(&sl.host, g.total + g.total / 2, hipHostMallocDefault));
+        sl.host_cap = g.total + g.total / 2;
+    }
+    return RC_OK;
 }
 
 // Launch one admitted batch on slot `sl` (worker thread, no lock held).
@@ -103,33 +161,10 @@ rc_status launch(rc_server *sv, Slot &sl)
         S += (int64_t)r->envs.size();
         n_items += r->tiles;
     }
-    if (S > sl.cap_si) {
-        RC_TRY(ensure(c, sl.si_env, 4 * S));
-        RC_TRY(ensure(c, sl.si_model, 4 * S));
-        RC_TRY(ensure(c, sl.ray_off, 8 * (S + 1)));
-        RC_TRY(ensure(c, sl.pose, 48 * S));
-        RC_TRY(ensure(c, sl.dtab, 8 * S));
-        RC_TRY(ensure(c, sl.stab, 8 * S));
-        RC_HIP(hipMemsetAsync(sl.ray_off.p, 0, sl.ray_off.n, sl.stream));
-        sl.cap_si = (int64_t)(sl.si_env.n / 4);
-    }
-    if (n_items > sl.cap_items) {
-        RC_TRY(ensure(c, sl.items, 8 * n_items));
-        sl.cap_items = (int64_t)(sl.items.n / 8);
-    }
-    if (!sl.head.p)
-        RC_TRY(c->pool.alloc(sl.head, sizeof(unsigned int) * kQueues * kQueueStride));
-    // staging layout: items | si_env | si_model | pose | dtab | stab
-    const size_t o_items = 0, o_env = o_items + 8 * n_items, o_model = o_env + 4 * S, o_pose = o_model + 4 * S,
-                 o_dtab = o_pose + 48 * S, o_stab = o_dtab + 8 * S, total = o_stab + 8 * S;
-    if (total > sl.host_cap) {
-        if (sl.host)
-            RC_HIP(hipHostFree(sl.host));
-        sl.host = nullptr;
-        sl.host_cap = 0;
-        RC_HIP(hipHostMalloc(&sl.host, total + total / 2, hipHostMallocDefault));
-        sl.host_cap = total + total / 2;
-    }
+    RC_TRY(reserve(c, sl, S, n_items));
+    const Staging g(n_items, S);
+    const size_t o_items = g.o_items, o_env = g.o_env, o_model = g.o_model, o_pose = g.o_pose, o_dtab = g.o_dtab,
+                 o_stab = g.o_stab;
     char *h = (char *)sl.host;
     int2 *items = (int2 *)(h + o_items);
     int32_t *si_env = (int32_t *)(h + o_env);
@@ -352,6 +387,28 @@ rc_status rc_server_create(rc_context *c, int32_t mode, int32_t n_streams, size_
             rc_server_destroy(sv);
             return fail(RC_E_HIP, "creating server streams");
         }
+    }
+    // size every slot's tables for the largest batch one admission round
+    // forms (bounded by kMaxBatchRays, or one larger request alone), so the
+    // worker rarely has to allocate
+    {
+        int64_t max_tiles = 0;
+        for (const SensorModel &m : sv->models)
+            max_tiles = std::max<int64_t>(max_tiles, (int64_t)m.tiles);
+        const int64_t S0 = std::max<int64_t>(E, 1);
+        const int64_t items0 = kMaxBatchRays / 64 + S0 * std::max<int64_t>(max_tiles / 16, 1);
+        for (auto &slp : sv->slots) {
+            rc_status st = reserve(c, *slp, S0, mode == RC_SERVE_PLAIN ? 1 : items0);
+            if (st != RC_OK) {
+                rc_server_destroy(sv);
+                return st;
+            }
+        }
+        for (auto &slp : sv->slots)
+            if (hipStreamSynchronize(slp->stream) != hipSuccess) {
+                rc_server_destroy(sv);
+                return fail(RC_E_HIP, "server table setup");
+            }
     }
     c->servers += 1;
     sv->worker = std::thread(worker_main, sv);

@@ -49,6 +49,31 @@ class rc_outputs(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("seg", C.c_void_p), ("tri", C.c_void_p), ("hit_xyz", C.c_void_p)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class rc_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+def torch_allocator(device: int = 0) -> rc_allocator:
+    """An ``rc_allocator`` that takes the library's device memory from torch's
+    caching allocator (so it shows in ``torch.cuda.memory_allocated``)."""
+    import torch
+
+    def _alloc(user, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except Exception:  # reported by the library as RC_E_OOM
+            return None
+
+    def _free(user, ptr, nbytes, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return rc_allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+
+
 class rc_request(C.Structure):
     _fields_ = [("n_envs", C.c_int32), ("env_ids", C.c_void_p), ("sensor_id", C.c_int32),
                 ("sensor_T", C.c_void_p), ("depth", C.c_void_p), ("seg", C.c_void_p)]
@@ -68,7 +93,7 @@ def lib():
         sig = {
             "rc_status_string": (C.c_char_p, [I32]),
             "rc_last_error": (C.c_char_p, []),
-            "rc_create": (I32, [I32, P, SZ, C.POINTER(P)]),
+            "rc_create": (I32, [I32, P, C.POINTER(rc_allocator), SZ, C.POINTER(P)]),
             "rc_destroy": (I32, [P]),
             "rc_memory_used": (I32, [P, C.POINTER(SZ)]),
             "rc_mesh_add": (I32, [P, P, I32, P, I32, C.POINTER(I32)]),
@@ -80,8 +105,8 @@ def lib():
             "rc_set_instance_poses": (I32, [P, P, P]),
             "rc_set_sensor_poses": (I32, [P, P, P]),
             "rc_move_instances": (I32, [P, P, I32, C.c_float, P]),
-            "rc_build": (I32, [P, I32, P]),
-            "rc_refit": (I32, [P, P]),
+            "rc_build": (I32, [P, P, I32, P]),
+            "rc_refit": (I32, [P, P, P]),
             "rc_render": (I32, [P, C.POINTER(rc_outputs), I32, P]),
             "rc_render_stats": (I32, [P, P, P]),
             "rc_debug_world": (I32, [P, P]),
@@ -145,14 +170,21 @@ def _stream(stream) -> Optional[int]:
 # --------------------------------------------------------------------------
 # one wrapper per entry point
 # --------------------------------------------------------------------------
-def rc_create(device: int = 0, stream=None, hbm_budget: int = 0):
+_allocators = {}  # context -> its rc_allocator (the callbacks must outlive the context)
+
+
+def rc_create(device: int = 0, stream=None, hbm_budget: int = 0, allocator: Optional[rc_allocator] = None):
     out = C.c_void_p()
-    _check(lib().rc_create(device, _stream(stream) if stream is not None else None, hbm_budget, C.byref(out)))
+    _check(lib().rc_create(device, _stream(stream) if stream is not None else None,
+                           None if allocator is None else C.byref(allocator), hbm_budget, C.byref(out)))
+    if allocator is not None:
+        _allocators[out.value] = allocator
     return out.value
 
 
 def rc_destroy(ctx) -> None:
     _check(lib().rc_destroy(ctx))
+    _allocators.pop(ctx, None)
 
 
 def rc_memory_used(ctx) -> int:
@@ -218,12 +250,18 @@ def rc_move_instances(ctx, d_vel, step: int, dt: float, stream=None) -> None:
     _check(lib().rc_move_instances(ctx, _dev(d_vel, "float32", 0, "d_vel"), step, dt, _stream(stream)))
 
 
-def rc_build(ctx, builder: int = RC_BUILD_SAH, stream=None) -> None:
-    _check(lib().rc_build(ctx, builder, _stream(stream)))
+def _mask(env_mask):
+    return None if env_mask is None else _dev(env_mask, "uint8", 0, "env_mask")
 
 
-def rc_refit(ctx, stream=None) -> None:
-    _check(lib().rc_refit(ctx, _stream(stream)))
+def rc_build(ctx, builder: int = RC_BUILD_SAH, stream=None, env_mask=None) -> None:
+    """env_mask: None (every environment) or a uint8 device tensor [n_envs]."""
+    _check(lib().rc_build(ctx, _mask(env_mask), builder, _stream(stream)))
+
+
+def rc_refit(ctx, stream=None, env_mask=None) -> None:
+    """env_mask: None (every environment) or a uint8 device tensor [n_envs]."""
+    _check(lib().rc_refit(ctx, _mask(env_mask), _stream(stream)))
 
 
 def rc_render(ctx, depth=None, seg=None, tri=None, hit_xyz=None, mode: int = RC_RENDER_FLAT, stream=None,

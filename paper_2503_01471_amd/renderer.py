@@ -14,10 +14,13 @@ from . import rc
 
 
 class Renderer:
-    def __init__(self, scene, device: int = 0, hbm_budget: int = 0, build: bool = True):
+    def __init__(self, scene, device: int = 0, hbm_budget: int = 0, build: bool = True, allocator: str = "torch"):
+        """allocator: "torch" (library memory from torch's caching allocator) or
+        "hip" (the library's own hipMalloc)."""
         self.scene = scene
         self.device = torch.device("cuda", device)
-        self.ctx = rc.rc_create(device, None, hbm_budget)
+        hook = {"torch": lambda: rc.torch_allocator(device), "hip": lambda: None}[allocator]()
+        self.ctx = rc.rc_create(device, None, hbm_budget, allocator=hook)
         for v, t in scene.protos:
             rc.rc_mesh_add(self.ctx, v, t)
         rc.rc_scene_load(self.ctx, scene.inst_offsets, scene.inst_mesh, scene.inst_seg, scene.inst_dynamic)
@@ -44,11 +47,21 @@ class Renderer:
             self.build()
 
     # -- acceleration structure --------------------------------------------
-    def build(self, stream=None):
-        rc.rc_build(self.ctx, rc.RC_BUILD_SAH, stream)
+    def _mask(self, envs):
+        """uint8 device mask over environments from a list of env ids (None: all)."""
+        if envs is None:
+            return None
+        m = torch.zeros(self.scene.n_envs, dtype=torch.uint8, device=self.device)
+        ids = torch.as_tensor(np.asarray(envs, np.int64), device=self.device)
+        if ids.numel():
+            m[ids] = 1
+        return m
 
-    def refit(self, stream=None):
-        rc.rc_refit(self.ctx, stream)
+    def build(self, stream=None, envs=None):
+        rc.rc_build(self.ctx, rc.RC_BUILD_SAH, stream, env_mask=self._mask(envs))
+
+    def refit(self, stream=None, envs=None):
+        rc.rc_refit(self.ctx, stream, env_mask=self._mask(envs))
 
     def move(self, step: int, stream=None):
         rc.rc_move_instances(self.ctx, self.inst_vel, step, float(self.scene.dt), stream)

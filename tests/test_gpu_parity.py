@@ -142,6 +142,100 @@ def test_cfg4_motion_refit_equals_rebuild():
     R.close()
 
 
+def _mix_poses(scene, new, old, envs):
+    """Instance poses: `new` for the instances of `envs`, `old` elsewhere."""
+    T = np.array(old, np.float32, copy=True).reshape(-1, 12)
+    new = np.asarray(new, np.float32).reshape(-1, 12)
+    for e in envs:
+        a, b = int(scene.inst_offsets[e]), int(scene.inst_offsets[e + 1])
+        T[a:b] = new[a:b]
+    return T
+
+
+def test_env_mask_build_and_refit():
+    """A masked build (refit) updates only the masked environments: the
+    outputs equal, bit for bit, a full build at the mixed poses (new poses
+    inside the mask, the previous ones outside), and match the oracle."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=6, env_ids=None)
+    R = _renderer(scene)
+    T0 = np.asarray(scene.inst_T, np.float32).reshape(-1, 12)
+    T1, T2 = O.moved_poses(scene, 40), O.moved_poses(scene, 90)
+    # masked rebuild of envs {1, 4} at T1
+    _say("masked build")
+    rc.rc_set_instance_poses(R.ctx, torch.from_numpy(np.ascontiguousarray(T1)).cuda())
+    R.build(envs=[1, 4])
+    got_b = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    mix_b = _mix_poses(scene, T1, T0, [1, 4])
+    # masked refit of envs {0, 4, 5} at T2
+    _say("masked refit")
+    rc.rc_set_instance_poses(R.ctx, torch.from_numpy(np.ascontiguousarray(T2)).cuda())
+    R.refit(envs=[0, 4, 5])
+    got_r = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    mix_r = _mix_poses(scene, T2, mix_b, [0, 4, 5])
+    # an empty mask changes nothing
+    R.refit(envs=[])
+    R.build(envs=[])
+    got_e = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    R.close()
+    for mix, got in ((mix_b, got_b), (mix_r, got_r)):
+        R2 = _renderer(scene, build=False)
+        rc.rc_set_instance_poses(R2.ctx, torch.from_numpy(np.ascontiguousarray(mix)).cuda())
+        R2.build()
+        ref = _host(R2.render(mode=rc.RC_RENDER_BATCHED))
+        R2.close()
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(got[k], ref[k]), k
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(got_e[k], got_r[k]), k
+    rep = parity.compare(got_r, O.render(scene, O.world(scene, mix_r)))
+    print(rep, flush=True)
+    parity.assert_contract(rep)
+
+
+def test_masked_build_needs_full_build():
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    R = _renderer(S.make_cfg1(), build=False)
+    with pytest.raises(rc.RCError) as ei:
+        R.build(envs=[0])
+    assert ei.value.status == -4
+    R.build()
+    R.build(envs=[0])
+    R.close()
+
+
+def test_allocator_hook():
+    """Library memory taken from torch's caching allocator gives the same
+    outputs as the library's own hipMalloc; a failing hook is RC_E_OOM."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=4, env_ids=None)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    R = _renderer(scene, allocator="torch")
+    used = rc.rc_memory_used(R.ctx)
+    assert torch.cuda.memory_allocated() - before >= used > 0
+    a = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    R.close()
+    R = _renderer(scene, allocator="hip")
+    b = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+    R.close()
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    calls = []
+    bad = rc.rc_allocator(rc.ALLOC_FN(lambda u, n, s: calls.append(n)), rc.FREE_FN(lambda u, p, n, s: None), None)
+    ctx = rc.rc_create(0, None, 0, allocator=bad)
+    try:
+        mid = rc.rc_mesh_add(ctx, *S.box_mesh())
+        with pytest.raises(rc.RCError) as ei:
+            rc.rc_scene_load(ctx, [0, 1], [mid], [1])
+        assert ei.value.status == -2 and calls
+    finally:
+        rc.rc_destroy(ctx)
+
+
 def test_deterministic():
     from paper_2503_01471_amd import rc
     _need_gpu()
