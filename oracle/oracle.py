@@ -49,7 +49,7 @@ def load(path: str):
     L.orc_transform.argtypes = [C.c_int64, f32, i32, f32, f32]
     L.orc_transform.restype = None
     L.orc_rays.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
-                           C.c_float, C.c_float, C.c_void_p, f32, C.c_int64, i64, f32, f32]
+                           C.c_float, C.c_float, C.c_void_p, f32, C.c_int64, i64, f32, f32, C.c_void_p]
     L.orc_rays.restype = None
     L.orc_cast.argtypes = [f32, i64, C.c_int64, i32, f32, f32, f32, f32, C.c_int32,
                            f64, i32, f64, f64, f64, f64, f64, f64, i32]
@@ -57,6 +57,8 @@ def load(path: str):
     L.orc_move.argtypes = [C.c_int64, f32, f32, np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"),
                            C.c_int32, C.c_float, f32]
     L.orc_move.restype = None
+    L.orc_extras.argtypes = [f32, i64, C.c_int64, i32, i32, f32, f32, f64, f32, f32]
+    L.orc_extras.restype = None
     return L
 
 
@@ -125,8 +127,9 @@ def moved_poses(scene, step: int) -> np.ndarray:
 # --------------------------------------------------------------------------
 # rays
 # --------------------------------------------------------------------------
-def sensor_rays(scene, s: int, ray_idx=None):
-    """World rays (FP32 origin and direction) of sensor instance ``s``."""
+def sensor_rays(scene, s: int, ray_idx=None, local=False):
+    """World rays (FP32 origin and direction) of sensor instance ``s``; with
+    ``local`` also the sensor-frame directions."""
     desc = scene.sensors[int(scene.sensor_ids[s])]
     n_all = desc.width * desc.height
     idx = np.arange(n_all, dtype=np.int64) if ray_idx is None else np.ascontiguousarray(ray_idx, np.int64)
@@ -136,10 +139,11 @@ def sensor_rays(scene, s: int, ray_idx=None):
     if desc.kind == 2:
         table = np.ascontiguousarray(desc.dir_table, np.float32)
     pose = np.ascontiguousarray(scene.sensor_T[s], np.float32)
+    dl = np.empty((len(idx), 3), np.float32)
     lib().orc_rays(desc.kind, desc.width, desc.height, desc.hfov, desc.vmin, desc.vmax, desc.hmin,
                    desc.hmax, None if table is None else table.ctypes.data_as(C.c_void_p), pose,
-                   len(idx), idx, o, d)
-    return o, d
+                   len(idx), idx, o, d, dl.ctypes.data_as(C.c_void_p))
+    return (o, d, dl) if local else (o, d)
 
 
 def sensor_env(scene) -> np.ndarray:
@@ -178,6 +182,10 @@ class Render:
     t: np.ndarray  # float64
     cls: np.ndarray  # classification bits
     raw: dict
+    normal: np.ndarray = None  # float32 [n,3] unit, facing the sensor; NaN on miss
+    bary: np.ndarray = None    # float32 [n,2] (u, v) of the winner; NaN on miss
+    point: np.ndarray = None   # float32 [n,3] sensor frame; NaN on miss
+    vert: np.ndarray = None    # int32 [n,3] global prototype vertex ids; -1 on miss
 
 
 def render(scene, w: World = None, sensor_inst=None, ray_idx=None, nthreads: int = 0) -> Render:
@@ -194,12 +202,13 @@ def render(scene, w: World = None, sensor_inst=None, ray_idx=None, nthreads: int
     n = len(sensor_inst)
     o = np.empty((n, 3), np.float32)
     d = np.empty((n, 3), np.float32)
+    dl = np.empty((n, 3), np.float32)
     near = np.empty(n, np.float32)
     far = np.empty(n, np.float32)
     senv = sensor_env(scene)
     for s in np.unique(sensor_inst):
         sel = np.nonzero(sensor_inst == s)[0]
-        o[sel], d[sel] = sensor_rays(scene, int(s), ray_idx[sel])
+        o[sel], d[sel], dl[sel] = sensor_rays(scene, int(s), ray_idx[sel], local=True)
         desc = scene.sensors[int(scene.sensor_ids[s])]
         near[sel], far[sel] = desc.near, desc.far
     ray_env = senv[sensor_inst]
@@ -209,4 +218,22 @@ def render(scene, w: World = None, sensor_inst=None, ray_idx=None, nthreads: int
     glob = w.env_off[ray_env] + np.maximum(r["tri"], 0)
     seg = np.where(hitm, w.tri_seg[glob], -1).astype(np.int32)
     hit = np.where(hitm[:, None], r["hit"], np.nan).astype(np.float32)
-    return Render(depth, seg, r["tri"].copy(), hit, r["t"], r["cls"], r)
+    # further data types of the same hit (Sec. III-D): normal and point cloud
+    # (orc_extras), barycentric coordinates (the winner's u, v) and the
+    # winner's prototype vertex ids for vertex-level annotations
+    normal = np.empty((n, 3), np.float32)
+    point = np.empty((n, 3), np.float32)
+    lib().orc_extras(np.ascontiguousarray(w.tris, np.float32), np.ascontiguousarray(w.env_off, np.int64), n,
+                     np.ascontiguousarray(ray_env, np.int32), np.ascontiguousarray(r["tri"], np.int32), d, dl,
+                     np.ascontiguousarray(r["t"]), normal, point)
+    bary = np.where(hitm[:, None], np.stack([r["u"], r["v"]], 1), np.nan).astype(np.float32)
+    vert = np.where(hitm[:, None], tri_vertex_ids(scene)[glob], -1).astype(np.int32)
+    return Render(depth, seg, r["tri"].copy(), hit, r["t"], r["cls"], r, normal, bary, point, vert)
+
+
+def tri_vertex_ids(scene) -> np.ndarray:
+    """Global vertex ids (prototypes' vertices numbered in prototype order) of
+    the three corners of every world triangle, in world-triangle order."""
+    vbase = np.concatenate([[0], np.cumsum([len(v) for v, _ in scene.protos])]).astype(np.int64)
+    per = [np.asarray(t, np.int64) + vbase[m] for m, (_, t) in enumerate(scene.protos)]
+    return np.concatenate([per[m] for m in scene.inst_mesh]) if scene.n_inst else np.zeros((0, 3), np.int64)

@@ -101,7 +101,7 @@ ORC_API void orc_move(int64_t n_inst, const float *T0, const float *vel, const u
 /* ---------------------------------------------------------------------- */
 ORC_API void orc_rays(int32_t kind, int32_t W, int32_t H, float hfov, float vmin, float vmax,
                       float hmin, float hmax, const float *table, const float *pose,
-                      int64_t n, const int64_t *ray_idx, float *o, float *d)
+                      int64_t n, const int64_t *ray_idx, float *o, float *d, float *dl_out)
 {
     const float s = (float)(tan((double)hfov * 0.5) / ((double)W * 0.5));
     for (int64_t i = 0; i < n; ++i) {
@@ -130,6 +130,8 @@ ORC_API void orc_rays(int32_t kind, int32_t W, int32_t H, float hfov, float vmin
             const float *row = pose + 4 * k;
             o[3 * i + k] = row[3];
             d[3 * i + k] = fmaf(row[0], dl[0], fmaf(row[1], dl[1], row[2] * dl[2]));
+            if (dl_out)
+                dl_out[3 * i + k] = dl[k];
         }
     }
 }
@@ -261,5 +263,48 @@ ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
                 cls |= ORC_B_NEARMISS;
         }
         cls_out[r] = cls;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Further data types of a hit (Sec. III-D: surface normals and point       */
+/* clouds come from the same intersection).  For ray r with winner tri[r]  */
+/* (env-local, -1 on a miss) of environment ray_env[r]:                     */
+/*   normal: the cross product (v1 - v0) x (v2 - v0) of the winner's world  */
+/*           vertices in FP64, divided by its length and negated when it    */
+/*           points along the ray (positive dot product with d), so that it */
+/*           faces the sensor;                                              */
+/*   point:  the hit in the sensor frame, t times the ray's local direction */
+/*           (the sensor pose maps it to o + t d).                          */
+/* Both rounded to FP32 once; NaN on a miss.                                */
+/* ---------------------------------------------------------------------- */
+ORC_API void orc_extras(const float *tris, const int64_t *env_off, int64_t n, const int32_t *ray_env,
+                        const int32_t *tri, const float *d, const float *dl, const double *t,
+                        float *normal, float *point)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        if (tri[r] < 0) {
+            for (int k = 0; k < 3; ++k) {
+                normal[3 * r + k] = NAN;
+                point[3 * r + k] = NAN;
+            }
+            continue;
+        }
+        const float *v = tris + 9 * (env_off[ray_env[r]] + tri[r]);
+        double e1[3], e2[3], nv[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = (double)v[3 + k] - (double)v[k];
+            e2[k] = (double)v[6 + k] - (double)v[k];
+        }
+        nv[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        nv[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        nv[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double len = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        const double along = nv[0] * (double)d[3 * r] + nv[1] * (double)d[3 * r + 1] + nv[2] * (double)d[3 * r + 2];
+        const double sgn = along > 0.0 ? -1.0 : 1.0;
+        for (int k = 0; k < 3; ++k) {
+            normal[3 * r + k] = (float)(sgn * nv[k] / len);
+            point[3 * r + k] = (float)(t[r] * (double)dl[3 * r + k]);
+        }
     }
 }

@@ -98,6 +98,11 @@ def pin_exact(seeds=range(200), near=0.05, far=50.0, margin_tol=1e-12):
                 continue
             if k >= 0 and abs(r["t"][i] - float(t)) > _t_tol(tris[k], o[i], d[i], float(t)):
                 fails.append(f"exact seed {seed} ray {i}: t {r['t'][i]} exact {float(t)}")
+            if k >= 0:  # barycentric coordinates of the winner (vertex-level annotations)
+                tol = _t_tol(tris[k], o[i], d[i], float(t)) / max(abs(float(t)), 1e-300)
+                if abs(r["u"][i] - float(u)) > tol or abs(r["v"][i] - float(v)) > tol:
+                    fails.append(f"exact seed {seed} ray {i}: (u, v) ({r['u'][i]}, {r['v'][i]}) exact "
+                                 f"({float(u)}, {float(v)})")
     return fails
 
 
@@ -476,5 +481,137 @@ def pin_classifier():
     return fails
 
 
+# --------------------------------------------------------------------------
+# 6. further data types of a hit: normals, barycentrics, point clouds,
+#    vertex ids
+# --------------------------------------------------------------------------
+def _rot(T):
+    return np.asarray(T, np.float64).reshape(-1, 3, 4)
+
+
+def pin_normals(seed=0):
+    """cfg1 (ground + axis-aligned boxes): every robust hit's normal is the
+    signed unit axis of the face it lies on, pointing back to the sensor: the
+    ground seen from above gives +z exactly; a box face gives its outward axis
+    (inward when the camera sits inside that box).  Also unit length,
+    orthogonal to the triangle and facing the ray, on a rotated-object scene."""
+    fails = []
+    sc = S.make_cfg1(seed)
+    w = O.world(sc)
+    r = O.render(sc, w, nthreads=1)
+    o, d = O.sensor_rays(sc, 0)
+    rob = ((r.cls & O.BORDER_MASK) == 0) & (r.tri >= 0)
+    if rob.sum() < 200:
+        fails.append("normals: too few robust hits")
+    owner = w.tri_inst[r.tri[rob]]
+    hit = r.raw["hit"][rob]
+    cam = o[0].astype(np.float64)
+    want = np.zeros((rob.sum(), 3))
+    for q, j in enumerate(owner):
+        pts = w.tris[w.tri_inst == j].reshape(-1, 3).astype(np.float64)
+        lo, hi = pts.min(0), pts.max(0)
+        dist = np.r_[np.abs(hit[q] - lo), np.abs(hit[q] - hi)]
+        k = int(np.argmin(dist))
+        axis, sign = k % 3, (-1.0 if k < 3 else 1.0)
+        if hi[axis] - lo[axis] == 0:  # flat quad (ground): facing the camera side
+            sign = 1.0 if cam[axis] > lo[axis] else -1.0
+        elif np.all((cam > lo) & (cam < hi)):
+            sign = -sign
+        want[q, axis] = sign
+    if not np.array_equal(r.normal[rob].astype(np.float64), want):
+        bad = np.nonzero(np.any(r.normal[rob] != want, axis=1))[0]
+        fails.append(f"normals: {len(bad)} box/ground normals differ, e.g. {r.normal[rob][bad[0]]} vs {want[bad[0]]}")
+    sc2 = S.make_cfg2(n_envs=1, W=64, H=36)
+    w2 = O.world(sc2)
+    r2 = O.render(sc2, w2)
+    h = r2.tri >= 0
+    n = r2.normal[h].astype(np.float64)
+    T = w2.tris[r2.tri[h]].astype(np.float64)
+    e1, e2 = T[:, 3:6] - T[:, :3], T[:, 6:] - T[:, :3]
+    _, d2 = O.sensor_rays(sc2, 0)
+    if not np.all(np.abs(np.linalg.norm(n, axis=1) - 1) <= 1e-6):  # NaN fails too
+        fails.append("normals: not unit length")
+    orth = np.abs(np.c_[(n * e1).sum(1) / np.linalg.norm(e1, axis=1), (n * e2).sum(1) / np.linalg.norm(e2, axis=1)])
+    if not np.all(orth <= 1e-6):
+        fails.append(f"normals: not orthogonal to the triangle ({np.nanmax(orth)})")
+    if not np.all((n * d2[h]).sum(1) < 0):
+        fails.append("normals: some face away from the sensor")
+    if not (np.all(np.isnan(r2.normal[~h])) and np.all(np.isnan(r.normal[r.tri < 0]))):
+        fails.append("normals: misses not NaN")
+    return fails
+
+
+def pin_barycentric():
+    """The winner's (u, v) rebuild the hit point: (1-u-v) v0 + u v1 + v v2 =
+    o + t d (FP64, rotated objects), and the reported FP32 pair is their
+    rounding.  (Exact rational u, v on tiny scenes: ``pin_exact``.)"""
+    fails = []
+    sc = S.make_cfg2(n_envs=1, W=64, H=36)
+    w = O.world(sc)
+    r = O.render(sc, w)
+    h = r.tri >= 0
+    u, v = r.raw["u"][h], r.raw["v"][h]
+    T = w.tris[r.tri[h]].astype(np.float64)
+    a, b, c = T[:, :3], T[:, 3:6], T[:, 6:]
+    p = (1 - u - v)[:, None] * a + u[:, None] * b + v[:, None] * c
+    err = np.linalg.norm(p - r.raw["hit"][h], axis=1)
+    scale = 1.0 + np.abs(r.raw["hit"][h]).max(1)
+    if not np.all(err / scale <= 1e-9 / r.raw["g"][h].clip(1e-3).min()):
+        fails.append(f"barycentric: rebuilt hit off by {(err / scale).max()}")
+    if not np.array_equal(r.bary[h], np.c_[u, v].astype(np.float32)):
+        fails.append("barycentric: reported pair is not the rounded (u, v)")
+    if not np.all(np.isnan(r.bary[~h])):
+        fails.append("barycentric: misses not NaN")
+    return fails
+
+
+def pin_point_cloud():
+    """Sensor-frame points: for a pinhole the forward coordinate is the depth
+    itself (local forward component 1); mapped back through the sensor pose
+    (R p + o) they are the world hit points; for a LiDAR their length is the
+    range."""
+    fails = []
+    for sc in (S.make_cfg2(n_envs=1, W=64, H=36), S.make_cfg3(n_envs=1, azimuths=64, channels=8)):
+        w = O.world(sc)
+        r = O.render(sc, w)
+        h = r.tri >= 0
+        P = _rot(sc.sensor_T)[0]
+        world = r.point[h].astype(np.float64) @ P[:, :3].T + P[:, 3]
+        err = np.linalg.norm(world - r.raw["hit"][h], axis=1) / np.maximum(r.t[h], 1.0)
+        if not np.all(err <= 1e-6):
+            fails.append(f"point cloud: R p + o off the hit by {np.nanmax(err)} (relative)")
+        if sc.sensors[0].kind == 0 and not np.array_equal(r.point[h][:, 0], r.depth[h]):
+            fails.append("point cloud: pinhole forward coordinate != depth")
+        if sc.sensors[0].kind == 1:
+            rel = np.abs(np.linalg.norm(r.point[h].astype(np.float64), axis=1) - r.t[h]) / r.t[h]
+            if not np.all(rel <= 1e-6):
+                fails.append(f"point cloud: lidar |p| != range ({rel.max()})")
+        if not np.all(np.isnan(r.point[~h])):
+            fails.append("point cloud: misses not NaN")
+    return fails
+
+
+def pin_vertex_ids():
+    """The reported global vertex ids, looked up in the prototype vertex lists
+    and moved by the owning instance's pose, are the winner's world vertices."""
+    fails = []
+    sc = S.make_cfg2(n_envs=1, W=64, H=36)
+    w = O.world(sc)
+    r = O.render(sc, w)
+    h = r.tri >= 0
+    allv = np.concatenate([np.asarray(v, np.float64) for v, _ in sc.protos])
+    A = _rot(sc.inst_T)[w.tri_inst[r.tri[h]]]
+    for k in range(3):
+        pv = allv[r.vert[h][:, k]]
+        moved = np.einsum("nij,nj->ni", A[:, :, :3], pv) + A[:, :, 3]
+        err = np.abs(moved - w.tris[r.tri[h]][:, 3 * k:3 * k + 3])
+        if not np.all(err <= 1e-5):
+            fails.append(f"vertex ids: corner {k} off by {err}")
+    if not np.all(r.vert[~h] == -1):
+        fails.append("vertex ids: misses not -1")
+    return fails
+
+
 ALL_PINS = [pin_exact, pin_duplicate_tie, pin_ray_plane, pin_boxes, pin_tessellated,
-            pin_invariants, pin_transform, pin_motion, pin_rays, pin_classifier]
+            pin_invariants, pin_transform, pin_motion, pin_rays, pin_classifier,
+            pin_normals, pin_barycentric, pin_point_cloud, pin_vertex_ids]

@@ -40,6 +40,12 @@ MUTANTS = {
     "candidates_strict": ("if (m >= -MARGIN && t >= lo && t <= hi)", "if (m >= 0.0 && t >= lo && t <= hi)"),
     "motion_no_step": ("fmaf(vel[3 * i + r], sdt, T0[12 * i + 4 * r + 3])",
                        "fmaf(vel[3 * i + r], dt, T0[12 * i + 4 * r + 3])"),
+    "normal_not_flipped": ("const double sgn = along > 0.0 ? -1.0 : 1.0;", "const double sgn = 1.0;"),
+    "normal_cross_index": ("nv[1] = e1[2] * e2[0] - e1[0] * e2[2];", "nv[1] = e1[2] * e2[1] - e1[0] * e2[2];"),
+    "point_world_dir": ("point[3 * r + k] = (float)(t[r] * (double)dl[3 * r + k]);",
+                        "point[3 * r + k] = (float)(t[r] * (double)d[3 * r + k]);"),
+    "local_dir_rotated": ("dl_out[3 * i + k] = dl[k];", "dl_out[3 * i + k] = dl[(k + 1) % 3];"),
+    "bary_swapped": ("u_out[r] = bu;", "u_out[r] = bv;"),
 }
 
 FAST_ARGS = {pins.pin_exact: dict(seeds=range(60))}
@@ -70,3 +76,16 @@ def test_mutant_is_caught(name, tmp_path):
         assert caught, f"mutant {name} passed every pin"
     finally:
         O._lib = saved
+
+
+def test_vertex_id_mutant_is_caught(monkeypatch):
+    """The vertex-id mapping lives in Python: dropping each prototype's vertex
+    offset must be caught by the vertex-id pin."""
+    import numpy as np
+
+    def no_offset(scene):
+        per = [np.asarray(t, np.int64) for _, t in scene.protos]
+        return np.concatenate([per[m] for m in scene.inst_mesh])
+
+    monkeypatch.setattr(O, "tri_vertex_ids", no_offset)
+    assert pins.pin_vertex_ids()
