@@ -59,6 +59,9 @@ def load(path: str):
     L.orc_move.restype = None
     L.orc_extras.argtypes = [f32, i64, C.c_int64, i32, i32, f32, f32, f64, f32, f32]
     L.orc_extras.restype = None
+    L.orc_shadow.argtypes = [f32, i64, C.c_int64, i32, i32, f32, f32, f32, C.c_int32,
+                             np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"), i32]
+    L.orc_shadow.restype = None
     return L
 
 
@@ -186,6 +189,8 @@ class Render:
     bary: np.ndarray = None    # float32 [n,2] (u, v) of the winner; NaN on miss
     point: np.ndarray = None   # float32 [n,3] sensor frame; NaN on miss
     vert: np.ndarray = None    # int32 [n,3] global prototype vertex ids; -1 on miss
+    shadow: np.ndarray = None  # uint8 [n] 1 = hidden from the stereo pair's second camera
+    shadow_cls: np.ndarray = None  # int32 [n] bit 1 occluded, bit 2 borderline
 
 
 def render(scene, w: World = None, sensor_inst=None, ray_idx=None, nthreads: int = 0) -> Render:
@@ -228,7 +233,26 @@ def render(scene, w: World = None, sensor_inst=None, ray_idx=None, nthreads: int
                      np.ascontiguousarray(r["t"]), normal, point)
     bary = np.where(hitm[:, None], np.stack([r["u"], r["v"]], 1), np.nan).astype(np.float32)
     vert = np.where(hitm[:, None], tri_vertex_ids(scene)[glob], -1).astype(np.int32)
-    return Render(depth, seg, r["tri"].copy(), hit, r["t"], r["cls"], r, normal, bary, point, vert)
+    # stereo shadows: segments from the FP32 hit points back to the second
+    # camera of sensors that have one (orc_shadow)
+    base = np.array([scene.sensors[int(k)].stereo for k in scene.sensor_ids], np.float32).reshape(-1, 3)
+    has = np.any(base != 0, 1)[sensor_inst]
+    shadow = np.zeros(n, np.uint8)
+    shadow_cls = np.zeros(n, np.int32)
+    sel = np.nonzero(has & hitm)[0]
+    if len(sel):
+        occ = np.zeros(len(sel), np.uint8)
+        cls = np.zeros(len(sel), np.int32)
+        lib().orc_shadow(np.ascontiguousarray(w.tris, np.float32), np.ascontiguousarray(w.env_off, np.int64),
+                         len(sel), np.ascontiguousarray(ray_env[sel], np.int32),
+                         np.ascontiguousarray(r["tri"][sel], np.int32), np.ascontiguousarray(hit[sel]),
+                         np.ascontiguousarray(np.asarray(scene.sensor_T, np.float32)[sensor_inst[sel]]),
+                         np.ascontiguousarray(base[sensor_inst[sel]]), nthreads if nthreads > 0 else
+                         len(os.sched_getaffinity(0)), occ, cls)
+        shadow[sel] = occ
+        shadow_cls[sel] = cls
+    return Render(depth, seg, r["tri"].copy(), hit, r["t"], r["cls"], r, normal, bary, point, vert, shadow,
+                  shadow_cls)
 
 
 def tri_vertex_ids(scene) -> np.ndarray:

@@ -308,3 +308,79 @@ ORC_API void orc_extras(const float *tris, const int64_t *env_off, int64_t n, co
         }
     }
 }
+
+/* ---------------------------------------------------------------------- */
+/* Stereo shadows (Sec. III-D): a pixel seen by the rendered camera is      */
+/* invalid when the second camera of the stereo pair cannot see the same    */
+/* point, i.e. when the segment from the hit point back to the second       */
+/* camera's centre meets the environment.  For ray r with winner win[r]     */
+/* (env-local, -1 on a miss: not tested) and FP32 hit point p[r]:           */
+/*   c2: the second centre, pose applied to the baseline b in the sensor    */
+/*       frame, coordinate k = fma(P_k0, b0, fma(P_k1, b1, fma(P_k2, b2,    */
+/*       P_k3))) in FP32 (the vertex transform's order);                    */
+/*   D = c2 - p in FP32;                                                    */
+/*   occluded iff a triangle of the environment meets p + s D at some s in  */
+/*       [SHADOW_S0, 1] (FP64 Moller-Trumbore on the FP32 inputs, two-      */
+/*       sided, only det == 0 rejects).  SHADOW_S0 keeps the surface around */
+/*       p (the winner and its neighbours meet the segment at s ~ 0, within */
+/*       the rounding of p) from shadowing itself.                          */
+/* cls: bit 1 occluded; bit 2 borderline: neither a triangle that occludes  */
+/* with margin (all barycentrics > MARGIN, s in [2 S0, 1 - MARGIN],         */
+/* grazing cosine >= GRAZE) nor the absence of loose candidates             */
+/* (barycentrics >= -MARGIN, s in [S0 / 2, 1 + MARGIN]).                    */
+/* ---------------------------------------------------------------------- */
+#define SHADOW_S0 1e-4
+
+ORC_API void orc_shadow(const float *tris, const int64_t *env_off, int64_t n, const int32_t *ray_env,
+                        const int32_t *win, const float *p, const float *pose, const float *b, int32_t nthreads,
+                        uint8_t *occ_out, int32_t *cls_out)
+{
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t r = 0; r < n; ++r) {
+        occ_out[r] = 0;
+        cls_out[r] = 0;
+        if (win[r] < 0)
+            continue;
+        const float *P = pose + 12 * r;
+        const float *B = b + 3 * r;
+        float D32[3];
+        for (int k = 0; k < 3; ++k) {
+            const float c2 = fmaf(P[4 * k + 0], B[0], fmaf(P[4 * k + 1], B[1], fmaf(P[4 * k + 2], B[2], P[4 * k + 3])));
+            D32[k] = c2 - p[3 * r + k];
+        }
+        const double ox = p[3 * r], oy = p[3 * r + 1], oz = p[3 * r + 2];
+        const double dx = D32[0], dy = D32[1], dz = D32[2];
+        const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+        int occluded = 0, robust_occ = 0, loose = 0;
+        const int64_t base = env_off[ray_env[r]], cnt = env_off[ray_env[r] + 1] - base;
+        for (int64_t k = 0; k < cnt; ++k) {
+            const float *T = tris + 9 * (base + k);
+            const double ax = T[0], ay = T[1], az = T[2];
+            const double e1x = (double)T[3] - ax, e1y = (double)T[4] - ay, e1z = (double)T[5] - az;
+            const double e2x = (double)T[6] - ax, e2y = (double)T[7] - ay, e2z = (double)T[8] - az;
+            const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+            const double det = e1x * px + e1y * py + e1z * pz;
+            if (det == 0.0)
+                continue;
+            const double inv = 1.0 / det;
+            const double sx = ox - ax, sy = oy - ay, sz = oz - az;
+            const double u = (sx * px + sy * py + sz * pz) * inv;
+            const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+            const double v = (dx * qx + dy * qy + dz * qz) * inv;
+            const double t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+            const double m = fmin(u, fmin(v, 1.0 - u - v));
+            if (u >= 0.0 && v >= 0.0 && u + v <= 1.0 && t >= SHADOW_S0 && t <= 1.0)
+                occluded = 1;
+            if (m >= -MARGIN && t >= 0.5 * SHADOW_S0 && t <= 1.0 + MARGIN)
+                loose = 1;
+            if (m > MARGIN && t >= 2.0 * SHADOW_S0 && t <= 1.0 - MARGIN) {
+                const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+                const double g = fabs(nx * dx + ny * dy + nz * dz) / (sqrt(nx * nx + ny * ny + nz * nz) * dn);
+                if (g >= GRAZE)
+                    robust_occ = 1;
+            }
+        }
+        occ_out[r] = (uint8_t)occluded;
+        cls_out[r] = occluded | ((robust_occ || !loose) ? 0 : 2);
+    }
+}

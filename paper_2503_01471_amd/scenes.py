@@ -36,7 +36,9 @@ DEG = math.pi / 180.0
 class SensorDesc:
     """Sensor model.  ``width``/``height`` are W/H for pinholes and
     azimuths/channels for LiDARs; angles in radians; ``near``/``far`` bound the
-    measured quantity (depth for pinholes, range for LiDARs)."""
+    measured quantity (depth for pinholes, range for LiDARs).  ``stereo`` is
+    the centre of a stereo pair's second camera in this sensor's frame
+    (metres; all zero: no second camera)."""
 
     kind: int
     width: int
@@ -49,6 +51,7 @@ class SensorDesc:
     near: float = 0.0
     far: float = 0.0
     dir_table: Optional[np.ndarray] = field(default=None, compare=False, hash=False)
+    stereo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
 
     @property
     def n_rays(self) -> int:

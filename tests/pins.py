@@ -612,6 +612,124 @@ def pin_vertex_ids():
     return fails
 
 
+# --------------------------------------------------------------------------
+# 7. stereo shadows
+# --------------------------------------------------------------------------
+SHADOW_S0 = 1e-4
+
+
+def _pillar_scene(baseline=(0.0, -0.3, 0.0)):
+    """Floor + one floating pillar, a pitched camera whose second camera sits
+    `baseline` away in its own frame."""
+    desc = S.pinhole(96, 54, 87.0, 0.05, 30.0)
+    desc = S.SensorDesc(**{**desc.__dict__, "stereo": tuple(float(x) for x in baseline)})
+    floor = (0, 0, S.affine(np.diag([40.0, 40.0, 1.0]), (-20.0, -20.0, 0.0)), 0, (0, 0, 0))
+    pillar = (1, 1, S.affine(np.diag([0.3, 0.3, 1.9]), (3.15, 0.35, 1.0)), 0, (0, 0, 0))
+    pose = S.sensor_pose(S.rot_zyx(0.05, 20 * S.DEG), (0.0, 0.0, 1.5))
+    return S.custom_scene([S.quad_mesh(), S.box_mesh()], [([floor, pillar], [(0, pose)])], [desc])
+
+
+def pin_stereo_pillar():
+    """Closed form: a hit point is hidden from the second camera iff the
+    segment from it to that camera crosses the pillar's surface at a
+    parameter in [S0, 1]; the crossings are the FP64 slab entry and exit of
+    the pillar box (the floor cannot be crossed: both ends lie above it)."""
+    fails = []
+    sc = _pillar_scene()
+    w = O.world(sc)
+    r = O.render(sc, w, nthreads=1)
+    h = r.tri >= 0
+    P = _rot(sc.sensor_T)[0]
+    c2 = P[:, :3] @ np.array(sc.sensors[0].stereo, np.float64) + P[:, 3]
+    pts = w.tris[w.tri_inst == 1].reshape(-1, 3).astype(np.float64)
+    lo, hi = pts.min(0), pts.max(0)
+    p = r.hit[h].astype(np.float64)
+    D = c2[None, :] - p
+    tmin, tmax = _slab(lo, hi, p, D)
+    cross = (tmin <= tmax) & (((tmin >= SHADOW_S0) & (tmin <= 1)) | ((tmax >= SHADOW_S0) & (tmax <= 1)))
+    # decisions within the classifier's margins of an edge, S0 or the camera are not compared
+    rob = ((r.cls[h] & O.BORDER_MASK) == 0) & ((r.shadow_cls[h] & 2) == 0)
+    bad = rob & (cross != (r.shadow[h] == 1))
+    if bad.any():
+        fails.append(f"stereo pillar: {bad.sum()} robust pixels disagree with the slab closed form")
+    if cross[rob].sum() < 20 or (~cross[rob]).sum() < 20:
+        fails.append(f"stereo pillar: degenerate case ({cross[rob].sum()} shadowed)")
+    if np.any(r.shadow[~h] != 0):
+        fails.append("stereo pillar: shadow set on a miss")
+    return fails
+
+
+def pin_stereo_zero_baseline():
+    """With the second camera at the first one's centre, the segment from a
+    hit back to the camera is the primary ray itself: nothing can lie on it
+    (the camera is clear of every object by more than the near distance), so
+    no pixel is shadowed."""
+    sc = S.make_cfg2(n_envs=2, W=64, H=36)
+    desc = S.SensorDesc(**{**sc.sensors[0].__dict__, "near": 0.01})
+    sc = S.Scene(**{**sc.__dict__, "sensors": [desc]})
+    w = O.world(sc)
+    r = O.render(sc, w)
+    h = np.nonzero(r.tri >= 0)[0]
+    senv = np.repeat(O.sensor_env(sc), sc.rays_per_sensor_inst())
+    si = np.repeat(np.arange(len(sc.sensor_ids)), sc.rays_per_sensor_inst())
+    occ = np.zeros(len(h), np.uint8)
+    cls = np.zeros(len(h), np.int32)
+    O.lib().orc_shadow(np.ascontiguousarray(w.tris), np.ascontiguousarray(w.env_off), len(h),
+                       np.ascontiguousarray(senv[h], np.int32), np.ascontiguousarray(r.tri[h], np.int32),
+                       np.ascontiguousarray(r.hit[h]), np.ascontiguousarray(np.asarray(sc.sensor_T, np.float32)[si[h]]),
+                       np.zeros((len(h), 3), np.float32), 1, occ, cls)
+    return [f"stereo zero baseline: {int(occ.sum())} pixels shadowed"] if occ.any() else []
+
+
+def pin_stereo_exact(seeds=range(40)):
+    """Exact rational segment tests on the tiny scenes: the segment from the hit
+    point to a second camera at o + b (identity rotation, so the centre is
+    o + b rounded once; b alternates between a short baseline and two that
+    bring the second camera down among the triangles), occluded iff some
+    triangle meets it at an exact s in [S0, 1]."""
+    fails = []
+    from fractions import Fraction as Fr
+    s0 = Fr(SHADOW_S0)
+    n_cmp = {False: 0, True: 0}
+    for seed in seeds:
+        tris, o, d = tiny_scene(seed)
+        wd = _world_of(tris)
+        r = O.cast(wd, np.zeros(len(o), np.int32), o, d, 0.05, 50.0, nthreads=1)
+        h = np.nonzero(r["tri"] >= 0)[0]
+        if not len(h):
+            continue
+        b = np.array([(0.0, 0.3, 0.1), (1.5, -1.2, -2.0), (-2.0, 1.0, -2.2)][seed % 3], np.float32)
+        pose = np.zeros((len(h), 12), np.float32)
+        pose[:, [0, 5, 10]] = 1.0
+        pose[:, [3, 7, 11]] = o[h]
+        p = r["hit"][h].astype(np.float32)
+        occ = np.zeros(len(h), np.uint8)
+        cls = np.zeros(len(h), np.int32)
+        O.lib().orc_shadow(np.ascontiguousarray(wd.tris), wd.env_off, len(h), np.zeros(len(h), np.int32),
+                           np.ascontiguousarray(r["tri"][h], np.int32), np.ascontiguousarray(p), pose,
+                           np.tile(b, (len(h), 1)), 1, occ, cls)
+        for q, i in enumerate(h):
+            c2 = (o[i].astype(np.float64) + b.astype(np.float64)).astype(np.float32)
+            D = c2 - p[q]
+            want, margin = False, math.inf
+            for tri in tris:
+                res = exact.intersect(tri, p[q], D)
+                if res is None:
+                    continue
+                t, u, v = res
+                margin = min(margin, float(abs(t - s0)), float(abs(t - 1)), float(abs(min(u, v, 1 - u - v))))
+                if u >= 0 and v >= 0 and u + v <= 1 and s0 <= t <= 1:
+                    want = True
+            if margin > 1e-12:
+                n_cmp[want] += 1
+                if bool(occ[q]) != want:
+                    fails.append(f"stereo exact seed {seed} ray {i}: oracle {occ[q]} exact {want}")
+    if min(n_cmp.values()) < 20:
+        fails.append(f"stereo exact: too few decided cases {n_cmp}")
+    return fails
+
+
 ALL_PINS = [pin_exact, pin_duplicate_tie, pin_ray_plane, pin_boxes, pin_tessellated,
             pin_invariants, pin_transform, pin_motion, pin_rays, pin_classifier,
-            pin_normals, pin_barycentric, pin_point_cloud, pin_vertex_ids]
+            pin_normals, pin_barycentric, pin_point_cloud, pin_vertex_ids,
+            pin_stereo_pillar, pin_stereo_zero_baseline, pin_stereo_exact]

@@ -46,6 +46,13 @@ MUTANTS = {
                         "point[3 * r + k] = (float)(t[r] * (double)d[3 * r + k]);"),
     "local_dir_rotated": ("dl_out[3 * i + k] = dl[k];", "dl_out[3 * i + k] = dl[(k + 1) % 3];"),
     "bary_swapped": ("u_out[r] = bu;", "u_out[r] = bv;"),
+    "shadow_backward": ("u + v <= 1.0 && t >= SHADOW_S0 && t <= 1.0)", "u + v <= 1.0 && t >= -1.0 && t <= 1.0)"),
+    "shadow_beyond_camera": ("u + v <= 1.0 && t >= SHADOW_S0 && t <= 1.0)",
+                             "u + v <= 1.0 && t >= SHADOW_S0 && t <= 4.0)"),
+    "shadow_no_sum": ("u + v <= 1.0 && t >= SHADOW_S0 && t <= 1.0)", "t >= SHADOW_S0 && t <= 1.0)"),
+    "shadow_centre_transposed": ("fmaf(P[4 * k + 0], B[0], fmaf(P[4 * k + 1], B[1], fmaf(P[4 * k + 2], B[2], P[4 * k + 3])))",
+                                 "fmaf(P[k], B[0], fmaf(P[4 + k], B[1], fmaf(P[8 + k], B[2], P[4 * k + 3])))"),
+    "shadow_dir_reversed": ("D32[k] = c2 - p[3 * r + k];", "D32[k] = p[3 * r + k] - c2;"),
 }
 
 FAST_ARGS = {pins.pin_exact: dict(seeds=range(60))}
