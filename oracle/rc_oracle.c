@@ -329,7 +329,7 @@ ORC_API void orc_extras(const float *tris, const int64_t *env_off, int64_t n, co
 /* grazing cosine >= GRAZE) nor the absence of loose candidates             */
 /* (barycentrics >= -MARGIN, s in [S0 / 2, 1 + MARGIN]).                    */
 /* ---------------------------------------------------------------------- */
-#define SHADOW_S0 1e-4
+#define SHADOW_S0 0x1p-13 /* 1.22e-4, exact in FP32 and FP64 */
 
 ORC_API void orc_shadow(const float *tris, const int64_t *env_off, int64_t n, const int32_t *ray_env,
                         const int32_t *win, const float *p, const float *pose, const float *b, int32_t nthreads,

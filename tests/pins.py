@@ -615,7 +615,7 @@ def pin_vertex_ids():
 # --------------------------------------------------------------------------
 # 7. stereo shadows
 # --------------------------------------------------------------------------
-SHADOW_S0 = 1e-4
+SHADOW_S0 = 2.0 ** -13
 
 
 def _pillar_scene(baseline=(0.0, -0.3, 0.0)):
