@@ -121,6 +121,12 @@ def bench_step(args):
     log(f"generating cfg{args.cfg}")
     scene = scenes.make(args.cfg)
     scene.inst_dynamic[:] = 1  # every object may move: re-transform and refit all of them each step
+    # cameras become stereo pairs (second camera 9.5 cm to the right) for the stereo-shadow measurement;
+    # the rendering of every other output is unaffected
+    import dataclasses
+    stereo = any(d.kind == scenes.PINHOLE for d in scene.sensors)
+    scene.sensors = [dataclasses.replace(d, stereo=(0.0, -0.095, 0.0)) if d.kind == scenes.PINHOLE else d
+                     for d in scene.sensors]
     n_envs = scene.n_envs
     log(f"loading {n_envs} envs, {int(scene.env_tri_counts().sum())} tris, {scene.total_rays()} rays")
     R = Renderer(scene, build=True)
@@ -157,6 +163,35 @@ def bench_step(args):
     ms_rebuild_step = timed(rebuild_step, max(2, args.steps // 2))
     log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, transform+refit {ms_refit:.3f} ms; reset: build "
         f"{ms_build:.3f} ms, step with rebuild {ms_rebuild_step:.3f} ms")
+    # further data types from the same hits (Sec. III-D): normal, barycentrics, sensor-frame point and
+    # vertex ids derived by a second pass from the winner ids; stereo shadows by segment tests
+    xo = R.alloc(depth=True, seg=True, tri=True, normal=True, bary=True, point=True, vert=True, shadow=stereo)
+
+    def render_tri():
+        rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays)
+
+    def render_all():
+        rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays, normal=xo["normal"],
+                     bary=xo["bary"], point=xo["point"], vert=xo["vert"])
+
+    def render_shadow():
+        rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays, shadow=xo["shadow"])
+
+    n_x = max(2, args.steps // 2)
+    ms_tri = timed(render_tri, n_x)
+    ms_all = timed(render_all, n_x)
+    further = {"render_with_tri_ms": ms_tri, "render_with_all_further_outputs_ms": ms_all,
+               "further_outputs_pass_ms": ms_all - ms_tri,
+               "outputs": "depth, seg, tri, normal[3], bary[2], sensor-frame point[3], vertex ids[3]"}
+    if stereo:
+        ms_sh = timed(render_shadow, n_x)
+        torch.cuda.synchronize()
+        hits = int((xo["tri"] >= 0).sum())
+        further.update({"render_with_stereo_shadow_ms": ms_sh, "stereo_shadow_pass_ms": ms_sh - ms_tri,
+                        "stereo_baseline_m": 0.095, "shadowed_fraction_of_hits":
+                        float(xo["shadow"].sum()) / max(hits, 1)})
+    log(f"further outputs: {further}")
+    del xo
     plain = None
     if not args.no_plain:
         def plain_step():
@@ -203,6 +238,7 @@ def bench_step(args):
                   "step_with_rebuild_Mrays_s": rays / ms_rebuild_step / 1e3,
                   "env_steps_per_s": n_envs / (ms_rebuild_step * 1e-3)},
         "plain": plain,
+        "further_outputs": further,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
                       "fp64_evals_per_ray": stats[2] / rays},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

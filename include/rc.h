@@ -95,7 +95,9 @@ rc_status rc_mesh_add(rc_context *ctx, const float *xyz, int32_t n_verts, const 
 /* Environment-local triangle numbering: instances in CSR order, then the    */
 /* prototype's triangle order.  Replaces any previous scene atomically: on   */
 /* error the previous scene (and its BVH) is untouched.  Sensors must be     */
-/* attached again after a new scene.                                         */
+/* attached again after a new scene.  An environment holds at most 2^25     */
+/* triangles (the BVH depth bound that sizes the traversal stack), the      */
+/* whole scene fewer than 2^31; larger inputs are RC_E_INVALID.             */
 /* ------------------------------------------------------------------------ */
 rc_status rc_scene_load(rc_context *ctx, int32_t n_envs, const int64_t *inst_offsets,
                         const int32_t *inst_mesh, const int32_t *inst_seg, const uint8_t *inst_dynamic);
@@ -114,6 +116,10 @@ rc_status rc_scene_load(rc_context *ctx, int32_t n_envs, const int64_t *inst_off
 /* Rays are indexed r = row*width + col (pinhole row = image row, LiDAR row  */
 /* = channel).  near_/far_ bound the ray parameter t: a triangle counts only */
 /* if near_ <= t <= far_ (0 <= near_ <= far_).                               */
+/* stereo: centre of a stereo pair's second camera in this sensor's frame    */
+/* (metres, x forward, y left, z up; all zero = no second camera).  Sec.     */
+/* III-D simulates stereo shadows: rendering with the shadow output marks    */
+/* the pixels whose hit point the second camera cannot see.                  */
 /* ------------------------------------------------------------------------ */
 #define RC_PINHOLE 0
 #define RC_LIDAR 1
@@ -125,6 +131,7 @@ typedef struct {
     float vmin, vmax, hmin, hmax;
     float near_, far_;
     const float *dir_table;
+    float stereo[3];
 } rc_sensor_desc;
 
 rc_status rc_sensor_add(rc_context *ctx, const rc_sensor_desc *desc, int32_t *sensor_id);
@@ -183,6 +190,29 @@ rc_status rc_refit(rc_context *ctx, const uint8_t *d_env_mask, void *stream);
 /*   seg    int32[total]: label of the instance owning the hit triangle, -1; */
 /*   tri    int32[total]: environment-local triangle id, -1;                 */
 /*   hit_xyz float[total][3]: world hit point o + t d, NaN on a miss.        */
+/* Further data types from the same hit record (Sec. III-D: surface normals, */
+/* point clouds, vertex-level annotations through face indices and          */
+/* barycentric coordinates), each evaluated in FP64 from the winner's FP32   */
+/* world vertices v0 v1 v2 (prototype vertex order) and rounded once:        */
+/*   normal float[total][3]: unit normal of the hit triangle, (v1-v0) x      */
+/*          (v2-v0) normalised and negated if it points away from the        */
+/*          sensor (dot with the ray direction > 0), NaN on a miss;          */
+/*   bary   float[total][2]: (u, v) with hit = (1-u-v) v0 + u v1 + v v2,     */
+/*          the Moller-Trumbore coordinates of the nearest hit, NaN;         */
+/*   point  float[total][3]: hit point in the sensor frame, t times the      */
+/*          ray's local direction (x forward), NaN;                          */
+/*   vert   int32[total][3]: global vertex ids (vertices numbered over all   */
+/*          rc_mesh_add calls in call order) of v0 v1 v2, -1; a per-vertex   */
+/*          annotation a gives the hit's value (1-u-v) a[i0] + u a[i1] +     */
+/*          v a[i2].                                                         */
+/*   shadow uint8[total]: 1 when the hit is hidden from the stereo pair's    */
+/*          second camera, else 0 (misses and sensors without a second       */
+/*          camera: 0).  The segment from the FP32 hit point p to the second */
+/*          centre c2 (pose applied to `stereo`, the vertex transform's fma  */
+/*          order) is tested against every triangle of the environment:      */
+/*          hidden iff one meets p + s (c2 - p) at s in [2^-13, 1] (the lower */
+/*          bound keeps the surface around p from shadowing itself).         */
+/* normal, bary, point, vert and shadow need the tri output (RC_E_INVALID). */
 /* The nearest hit is the smallest t in [near_, far_] over every triangle of */
 /* the ray's environment (two-sided; equal t resolved by the lower triangle  */
 /* id).  Every mode computes bit-identical outputs:                          */
@@ -201,6 +231,11 @@ typedef struct {
     int32_t *seg;
     int32_t *tri;
     float *hit_xyz;
+    float *normal;
+    float *bary;
+    float *point;
+    int32_t *vert;
+    uint8_t *shadow;
 } rc_outputs;
 
 rc_status rc_render(rc_context *ctx, const rc_outputs *out, int32_t mode, void *stream);

@@ -115,6 +115,8 @@ BuildView Scene::view() const
     v.env_nodes = env_nodes.as<int32_t>();
     v.env_micro = env_micro.as<int32_t>();
     v.micro = micro.as<int4>();
+    v.level_nodes = level_nodes.as<int32_t>();
+    v.level_off = level_off.as<int32_t>();
     v.env_mask = nullptr;
     return v;
 }
@@ -128,6 +130,8 @@ SceneView Scene::sview() const
     s.recs = recs.as<TriRec>();
     s.tri_seg = tri_seg.as<int32_t>();
     s.world = world.as<float>();
+    s.tri_src = tri_src.as<int2>();
+    s.proto_tri = proto_tri.as<int32_t>();
     s.n_envs = n_envs;
     return s;
 }
@@ -382,7 +386,8 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
         int64_t t = 0;
         for (int64_t i = inst_offsets[e]; i < inst_offsets[e + 1]; ++i)
             t += c->meshes[inst_mesh[i]].n_tris;
-        RC_CHECK(t < (1 << 27), "environment %d has %lld triangles (limit 2^27)", e, (long long)t);
+        RC_CHECK(t <= kMaxEnvTris, "environment %d has %lld triangles (limit %lld)", e, (long long)t,
+                 (long long)kMaxEnvTris);
         sc->env_tri_off[e + 1] = sc->env_tri_off[e] + t;
     }
     const int64_t N = sc->env_tri_off[n_envs];
@@ -429,6 +434,8 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->env_nodes, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->env_micro, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->micro, 16 * N));
+    RC_TRY(c->pool.alloc(sc->level_nodes, 4 * (size_t)(node_base(N, n_envs) + 16)));
+    RC_TRY(c->pool.alloc(sc->level_off, 4 * (size_t)n_envs * (kLevels + 1)));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);
@@ -444,9 +451,14 @@ rc_status rc_sensor_add(rc_context *c, const rc_sensor_desc *d, int32_t *sensor_
     RC_CHECK((int64_t)d->width * d->height < (1ll << 31), "sensor too large");
     RC_CHECK(isfinite(d->near_) && isfinite(d->far_) && d->near_ >= 0.f && d->near_ <= d->far_,
              "need 0 <= near <= far (finite)");
+    for (int k = 0; k < 3; ++k)
+        RC_CHECK(isfinite(d->stereo[k]), "stereo baseline not finite");
     ModelHost h{};
     SensorModel &m = h.m;
     m.kind = d->kind;
+    m.stereo = d->stereo[0] != 0.f || d->stereo[1] != 0.f || d->stereo[2] != 0.f;
+    for (int k = 0; k < 3; ++k)
+        m.sb[k] = d->stereo[k];
     m.W = d->width;
     m.H = d->height;
     m.tw_shift = 3;
@@ -661,7 +673,9 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
     Sensors &se = *c->sensors;
     const SceneView sv = sc.sview();
     const SensorView ev = se.view();
-    const OutView ov{out->depth, out->seg, out->tri, out->hit_xyz, nullptr, nullptr};
+    const OutView ov = out_view(*out);
+    const bool extras = out->normal || out->bary || out->point || out->vert;
+    RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
     switch (mode) {
     case RC_RENDER_PLAIN:
         for (int64_t s = 0; s < se.n_si; ++s)
@@ -677,6 +691,10 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
         RC_HIP(launch_render_brute(sv, ev, ov, se.n_items, st));
         break;
     }
+    if (extras)
+        RC_HIP(launch_hit_extras(sv, ev, ov, se.n_items, st));
+    if (out->shadow)
+        RC_HIP(launch_stereo_shadow(sv, ev, ov, se.n_items, st));
     return RC_OK;
 }
 
@@ -687,7 +705,7 @@ rc_status rc_render_stats(rc_context *c, void *stream, int64_t *counters)
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
     Sensors &se = *c->sensors;
-    const OutView ov{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const OutView ov{};
     RC_HIP(launch_fill_u32(se.counters.as<unsigned int>(), 8, 0u, st));
     RC_HIP(launch_render_stats(c->scene->sview(), se.view(), ov, se.n_items, se.counters.as<unsigned long long>(),
                                st));

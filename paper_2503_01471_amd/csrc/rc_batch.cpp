@@ -88,7 +88,9 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
         DBuf depth, seg;
         RC_TRY(c->pool.alloc(depth, 4 * (size_t)se.total_rays));
         RC_TRY(c->pool.alloc(seg, 4 * (size_t)se.total_rays));
-        const OutView ov{depth.as<float>(), seg.as<int32_t>(), nullptr, nullptr, nullptr, nullptr};
+        OutView ov;
+        ov.depth = depth.as<float>();
+        ov.seg = seg.as<int32_t>();
         hipEvent_t e0, e1;
         RC_HIP(hipEventCreate(&e0));
         RC_HIP(hipEventCreate(&e1));
@@ -167,6 +169,8 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
     Sensors &se = *c->sensors;
     RC_CHECK(sc.n_inst == 0 || d_vel, "d_vel is NULL");
     RC_CHECK(std::isfinite(dt), "dt not finite");
+    const bool extras = out->normal || out->bary || out->point || out->vert;
+    RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
     RC_TRY(set_device(c));
     auto g = new rc_graph;
     g->ctx = c;
@@ -186,7 +190,7 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
         return hip_fail(e, "step graph setup");
     }
     const BuildView v = sc.view();
-    const OutView ov{out->depth, out->seg, out->tri, out->hit_xyz, nullptr, nullptr};
+    const OutView ov = out_view(*out);
     hipStream_t cs = g->capture;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -198,6 +202,10 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
             k = launch_refit(v, cs);
         if (k == hipSuccess)
             k = launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk), c->batched_grid(), cs);
+        if (k == hipSuccess && extras)
+            k = launch_hit_extras(sc.sview(), se.view(), ov, se.n_items, cs);
+        if (k == hipSuccess && out->shadow)
+            k = launch_stereo_shadow(sc.sview(), se.view(), ov, se.n_items, cs);
         if (k == hipSuccess)
             k = launch_bump(g->step.as<int32_t>(), cs);
         e = hipStreamEndCapture(cs, &g->graph);

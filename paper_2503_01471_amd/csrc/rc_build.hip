@@ -719,7 +719,8 @@ __global__ __launch_bounds__(256) void k_gather(BuildView v)
 
 // ---------------------------------------------------------------------------
 // K7: refit.  One workgroup per environment walks its nodes level by level,
-// deepest first (a node's depth is stored in ch.w by the builder): each node
+// deepest first (the build groups node slots by depth, see k_level_order):
+// each node
 // takes the bounds of its leaf children from the records and of its internal
 // children from their (already refitted) two child boxes.  All traffic stays
 // inside one workgroup, so a barrier between levels is the only
@@ -762,20 +763,65 @@ __device__ __forceinline__ void node_box(const Node &c, float b[6])
 
 constexpr int kRefitBlock = 256;
 
+// K5d: group each environment's node slots by depth (counting sort in LDS;
+// order within a level is irrelevant to the refit), so the refit's level
+// passes touch only their own nodes.  Holes (depth -1) are left out.
+__global__ __launch_bounds__(kRefitBlock) void k_level_order(BuildView v)
+{
+    const int e = blockIdx.x;
+    if (masked_out(v, e))
+        return;
+    __shared__ int cnt[kLevels], pos[kLevels + 1];
+    const int64_t base = node_base(v.env_tri_off[e], e);
+    const int nn = v.env_nodes[e];
+    const Node *nodes = v.nodes + base;
+    for (int d = threadIdx.x; d < kLevels; d += kRefitBlock)
+        cnt[d] = 0;
+    __syncthreads();
+    for (int m = threadIdx.x; m < nn; m += kRefitBlock) {
+        const int d = nodes[m].ch.w;
+        if (d >= 0 && d < kLevels)
+            atomicAdd(&cnt[d], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int d = 0; d < kLevels; ++d) {
+            pos[d] = acc;
+            acc += cnt[d];
+        }
+        pos[kLevels] = acc;
+    }
+    __syncthreads();
+    int32_t *off = v.level_off + (int64_t)e * (kLevels + 1);
+    for (int d = threadIdx.x; d <= kLevels; d += kRefitBlock)
+        off[d] = pos[d];
+    __syncthreads();
+    int32_t *out = v.level_nodes + base;
+    for (int m = threadIdx.x; m < nn; m += kRefitBlock) {
+        const int d = nodes[m].ch.w;
+        if (d >= 0 && d < kLevels)
+            out[atomicAdd(&pos[d], 1)] = m;
+    }
+}
+
 __global__ __launch_bounds__(kRefitBlock) void k_refit(BuildView v)
 {
     const int e = blockIdx.x;
     if (masked_out(v, e))
         return;
-    const int64_t base = v.env_tri_off[e];
-    const int nn = v.env_nodes[e];
-    Node *nodes = v.nodes + node_base(base, e);
-    const TriRec *recs = v.recs + base;
+    const int64_t base = node_base(v.env_tri_off[e], e);
+    Node *nodes = v.nodes + base;
+    const int32_t *order = v.level_nodes + base;
+    const int32_t *off = v.level_off + (int64_t)e * (kLevels + 1);
+    const TriRec *recs = v.recs + v.env_tri_off[e];
     for (int level = kMaxNodeDepth; level >= 0; --level) {
-        for (int m = threadIdx.x; m < nn; m += kRefitBlock) {
+        const int a = off[level], b = off[level + 1];
+        if (a == b)
+            continue;  // uniform: every thread reads the same offsets
+        for (int i = a + threadIdx.x; i < b; i += kRefitBlock) {
+            const int m = order[i];
             const int4 ch = nodes[m].ch;
-            if (ch.w != level)
-                continue;
             float b0[6], b1[6];
             if (ch.x < 0)
                 leaf_box(recs, ch.x, b0);
@@ -846,6 +892,9 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
     if ((err = hipGetLastError()) != hipSuccess)
         return err;
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(k_level_order, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
     return hipGetLastError();
 }
 

@@ -14,12 +14,21 @@ namespace rc {
 // env_tri_off[e]); < 0 leaf ~(first << 3 | (count - 1)) over the
 // environment's leaf-ordered triangle records.
 // ---------------------------------------------------------------------------
+// The depth bound sizes the per-lane traversal stack in LDS, and that stack
+// is what limits how many render waves a CU holds: 22 keeps six waves per
+// SIMD resident (24 KB of stack per 256-thread block) and still admits
+// 2^25 triangles per environment.
 #ifndef RC_MAX_NODE_DEPTH
-#define RC_MAX_NODE_DEPTH 30
+#define RC_MAX_NODE_DEPTH 22
 #endif
 constexpr int kLeafMax = 4;                        // triangles per leaf (<= 8 by the encoding)
 constexpr int kMaxNodeDepth = RC_MAX_NODE_DEPTH;   // internal-node depth bound enforced by the builder
 constexpr int kStack = RC_MAX_NODE_DEPTH + 2;      // traversal stack entries (> kMaxNodeDepth)
+// Largest environment the bound admits: a balanced tree over this many
+// triangles has its deepest internal node at depth kMaxNodeDepth.
+constexpr int64_t kMaxEnvTris = (int64_t)kLeafMax << (kMaxNodeDepth + 1);
+constexpr int kLevels = kMaxNodeDepth + 1;  // internal-node depths 0 .. kMaxNodeDepth
+static_assert(kMaxEnvTris <= (int64_t(1) << 28), "leaf references hold 28-bit record offsets");
 #ifndef RC_BINS
 #define RC_BINS 16
 #endif
@@ -62,6 +71,8 @@ struct SensorModel {
     float hw, hh;     // W/2, H/2
     float tn, tf;     // near, far
     int64_t table_off;  // float3 entries into the direction table (lidar/table)
+    float sb[3];      // stereo pair's second centre in the sensor frame
+    int32_t stereo;   // nonzero when sb is set
 };
 
 // ---------------------------------------------------------------------------
@@ -74,6 +85,8 @@ struct SceneView {
     const TriRec *recs;          // [N] leaf order
     const int32_t *tri_seg;      // [N] global original order
     const float *world;          // [N][9] original order (reference path)
+    const int2 *tri_src;         // [N] (instance, global prototype triangle)
+    const int32_t *proto_tri;    // prototype triangles (global vertex ids)
     int32_t n_envs;
 };
 
@@ -91,12 +104,17 @@ struct SensorView {
 // the tables are set, one buffer per sensor instance (requests of a served
 // batch write into their own buffers).
 struct OutView {
-    float *depth;
-    int32_t *seg;
-    int32_t *tri;
-    float *hit;
-    float *const *depth_tab;
-    int32_t *const *seg_tab;
+    float *depth = nullptr;
+    int32_t *seg = nullptr;
+    int32_t *tri = nullptr;
+    float *hit = nullptr;
+    float *normal = nullptr;  // [ray][3]
+    float *bary = nullptr;    // [ray][2]
+    float *point = nullptr;   // [ray][3] sensor frame
+    int32_t *vert = nullptr;  // [ray][3]
+    uint8_t *shadow = nullptr;  // [ray] hidden from the second camera
+    float *const *depth_tab = nullptr;  // per sensor instance (served batches)
+    int32_t *const *seg_tab = nullptr;
 };
 
 struct BuildView {
@@ -118,6 +136,8 @@ struct BuildView {
     int32_t *env_nodes;          // [E] node slots per environment
     int32_t *env_micro;          // [E] deferred small ranges per environment
     int4 *micro;                 // [N] deferred ranges (node, begin, end, depth)
+    int32_t *level_nodes;        // node slots of env e grouped by depth (same base as nodes)
+    int32_t *level_off;          // [E][kLevels + 1] depth d of env e = level_nodes[off[d] .. off[d+1])
     const uint8_t *env_mask;     // [E] environments to process (nullptr: all)
 };
 
@@ -152,6 +172,13 @@ struct QueueView {
 hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const QueueView &q,
                                  int grid, hipStream_t st);
 int batched_blocks_per_cu();
+// Normals, barycentrics, sensor-frame points and vertex ids of rendered rays
+// (needs o.tri from a preceding render of the same rays).
+hipError_t launch_hit_extras(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                             hipStream_t st);
+// Stereo shadows of rendered rays (needs o.tri from a preceding render).
+hipError_t launch_stereo_shadow(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                                hipStream_t st);
 hipError_t launch_render_brute(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
                                hipStream_t st);
 hipError_t launch_render_stats(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,

@@ -26,11 +26,12 @@ constexpr float kU = 0x1p-24f;              // unit roundoff
 constexpr float kErr = 0x1p-17f;            // triple-product error factor (>= 48 u)
 constexpr float kBoxGrow = 1.0f + 0x1p-20f;  // >= 1 + 4 gamma_3 (robust slab test)
 constexpr int kBlock = 256;
-#ifdef RC_MIN_WAVES
-#define RC_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(RC_MIN_WAVES, 8)))
-#else
-#define RC_WAVES_PER_EU
+// Render kernels are latency bound at low occupancy: ask for at least six
+// waves per SIMD (80 VGPRs), which the LDS stack also admits.
+#ifndef RC_MIN_WAVES
+#define RC_MIN_WAVES 6
 #endif
+#define RC_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(RC_MIN_WAVES, 8)))
 
 struct Ray {
     float ox, oy, oz;
@@ -52,9 +53,9 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // Ray of (row, col) of sensor instance s.  Local direction: pinhole
 // (1, -(col+1/2-W/2) s, -(row+1/2-H/2) s); lidar / table from the FP32
 // direction table.  World direction i = fma(P_i0, dx, fma(P_i1, dy, P_i2 dz)).
-__device__ __forceinline__ void gen_ray(const SensorView &se, const Tile &t, int row, int col, Ray &r)
+__device__ __forceinline__ void local_dir(const SensorView &se, const Tile &t, int row, int col, float &lx, float &ly,
+                                          float &lz)
 {
-    float lx, ly, lz;
     if (t.kind == 0) {
         lx = 1.0f;
         ly = -((((float)col + 0.5f) - t.hw) * t.scale);
@@ -65,6 +66,12 @@ __device__ __forceinline__ void gen_ray(const SensorView &se, const Tile &t, int
         ly = d[1];
         lz = d[2];
     }
+}
+
+__device__ __forceinline__ void gen_ray(const SensorView &se, const Tile &t, int row, int col, Ray &r)
+{
+    float lx, ly, lz;
+    local_dir(se, t, row, col, lx, ly, lz);
     const float *P = se.pose + 12 * (int64_t)t.s;
     r.ox = P[3];
     r.oy = P[7];
@@ -339,15 +346,18 @@ __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ 
     }
 }
 
-// Final outputs of one ray from the winner (FP64 t, hit = o + t d).
-__device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc, const Ray &r, int env,
-                                          const TriRec *__restrict__ recs, Best &b, int s, int64_t ray_base,
-                                          int64_t r_local)
+// Final outputs of one ray from the winner (FP64 t, re-evaluated if the
+// winner was accepted in FP32; hit = o + t d).
+__device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc, const SensorView &se, const Tile &tl,
+                                          int row, int col, const Ray &r, const TriRec *__restrict__ recs, Best &b)
 {
+    const int env = tl.env;
+    const int64_t r_local = (int64_t)row * tl.W + col;
     float depth = -1.0f, hx = __builtin_nanf(""), hy = hx, hz = hx;
     int seg = -1, tri = -1;
+    double t = 0.0;
     if (b.pos >= 0) {
-        double t = b.t64;
+        t = b.t64;
         if (!b.have64) {
             t = 0.5 * ((double)b.lo + (double)b.hi);
             if (recs) {
@@ -365,15 +375,15 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
         seg = sc.tri_seg[sc.env_tri_off[env] + b.id];
     }
     if (o.depth_tab) {  // per-request buffers (served batches)
-        float *dp = o.depth_tab[s];
-        int32_t *sp = o.seg_tab[s];
+        float *dp = o.depth_tab[tl.s];
+        int32_t *sp = o.seg_tab[tl.s];
         if (dp)
             dp[r_local] = depth;
         if (sp)
             sp[r_local] = seg;
         return;
     }
-    const int64_t idx = ray_base + r_local;
+    const int64_t idx = tl.ray_base + r_local;
     if (o.depth)
         o.depth[idx] = depth;
     if (o.seg)
@@ -409,7 +419,7 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     const int root = sc.env_root[t.env];
     if (root != kEmptyRoot)
         traverse<STATS>(r, nodes, recs, root, stk, b, st);
-    write_out(o, sc, r, t.env, recs, b, t.s, t.ray_base, (int64_t)row * t.W + col);
+    write_out(o, sc, se, t, row, col, r, recs, b);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; map them so that each XCD walks
@@ -557,7 +567,216 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
         }
     }
     (void)st;
-    write_out(o, sc, r, t.env, nullptr, b, t.s, t.ray_base, (int64_t)row * t.W + col);
+    write_out(o, sc, se, t, row, col, r, nullptr, b);
+}
+
+// Further data types of the nearest hit: unit normal facing the sensor,
+// barycentric (u, v), sensor-frame point t * local direction, global vertex
+// ids; FP64 from the winner's FP32 world vertices (g: global original-order
+// triangle index, -1 on a miss).
+__device__ __forceinline__ void write_extras(const OutView &o, const SceneView &sc, int64_t g, int64_t idx, float ox,
+                                             float oy, float oz, float dxf, float dyf, float dzf, float lx, float ly,
+                                             float lz, double t, bool t_ok)
+{
+    if (g < 0) {
+        const float nan = __builtin_nanf("");
+        for (int k = 0; k < 3; ++k) {
+            if (o.normal)
+                o.normal[3 * idx + k] = nan;
+            if (o.point)
+                o.point[3 * idx + k] = nan;
+            if (o.vert)
+                o.vert[3 * idx + k] = -1;
+            if (o.bary && k < 2)
+                o.bary[2 * idx + k] = nan;
+        }
+        return;
+    }
+    const float *w = sc.world + 9 * g;
+    const double ax = w[0], ay = w[1], az = w[2];
+    const double e1x = (double)w[3] - ax, e1y = (double)w[4] - ay, e1z = (double)w[5] - az;
+    const double e2x = (double)w[6] - ax, e2y = (double)w[7] - ay, e2z = (double)w[8] - az;
+    const double dx = dxf, dy = dyf, dz = dzf;
+    if (o.normal) {
+        double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+        const double len = sqrt(nx * nx + ny * ny + nz * nz);
+        if (nx * dx + ny * dy + nz * dz > 0.0) {
+            nx = -nx;
+            ny = -ny;
+            nz = -nz;
+        }
+        o.normal[3 * idx + 0] = (float)(nx / len);
+        o.normal[3 * idx + 1] = (float)(ny / len);
+        o.normal[3 * idx + 2] = (float)(nz / len);
+    }
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const double det = e1x * px + e1y * py + e1z * pz;
+    const double Tx = (double)ox - ax, Ty = (double)oy - ay, Tz = (double)oz - az;
+    const double qx = Ty * e1z - Tz * e1y, qy = Tz * e1x - Tx * e1z, qz = Tx * e1y - Ty * e1x;
+    if (o.bary) {
+        o.bary[2 * idx + 0] = (float)((Tx * px + Ty * py + Tz * pz) / det);
+        o.bary[2 * idx + 1] = (float)((dx * qx + dy * qy + dz * qz) / det);
+    }
+    if (!t_ok)  // the certified winner always passes the FP64 test; plane t otherwise
+        t = (e2x * qx + e2y * qy + e2z * qz) / det;
+    if (o.point) {
+        o.point[3 * idx + 0] = (float)(t * (double)lx);
+        o.point[3 * idx + 1] = (float)(t * (double)ly);
+        o.point[3 * idx + 2] = (float)(t * (double)lz);
+    }
+    if (o.vert) {
+        const int2 src = sc.tri_src[g];
+        for (int k = 0; k < 3; ++k)
+            o.vert[3 * idx + k] = sc.proto_tri[3 * (int64_t)src.y + k];
+    }
+}
+
+// Second pass for the further data types: one wavefront per 64-ray tile
+// reads the winner's id from the tri output, re-evaluates the winner's FP64
+// t exactly as the render did (the same Moller-Trumbore on the same FP32
+// values) and writes the requested buffers.  Kept apart from the traversal
+// kernels so that they carry none of its registers.
+__global__ __launch_bounds__(kBlock) void k_hit_extras(SceneView sc, SensorView se, OutView o, int64_t n_items)
+{
+    const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    if (k >= n_items)
+        return;
+    const int2 item = se.items[k];
+    const Tile t = load_tile(se, item);
+    const int lane = threadIdx.x & 63;
+    const int ty = item.y / t.tiles_x, tx = item.y - ty * t.tiles_x;
+    const int tw = 1 << t.tw_shift;
+    const int row = ty * (64 >> t.tw_shift) + (lane >> t.tw_shift), col = tx * tw + (lane & (tw - 1));
+    if (row >= t.H || col >= t.W)
+        return;
+    Ray r;
+    gen_ray(se, t, row, col, r);
+    float lx, ly, lz;
+    local_dir(se, t, row, col, lx, ly, lz);
+    const int64_t idx = t.ray_base + (int64_t)row * t.W + col;
+    const int id = o.tri[idx];
+    int64_t g = -1;
+    double tt = 0.0;
+    bool ok = false;
+    if (id >= 0) {
+        g = sc.env_tri_off[t.env] + id;
+        const float *w = sc.world + 9 * g;
+        ok = mt64(r, make_float4(w[0], w[1], w[2], w[3]), make_float4(w[4], w[5], w[6], w[7]),
+                  make_float4(w[8], 0.f, 0.f, 0.f), tt);
+    }
+    write_extras(o, sc, g, idx, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, lx, ly, lz, tt, ok);
+}
+
+
+// ---------------------------------------------------------------------------
+// Stereo shadows: the segment from each hit point back to the stereo pair's
+// second camera.  Any-hit traversal (stops at the first triangle that meets
+// the segment), with the same conservative boxes and certified FP32 decisions
+// resolved in FP64 as the nearest-hit search, so the answer is the exact one
+// up to FP64 rounding.
+// ---------------------------------------------------------------------------
+constexpr float kShadowS0 = 0x1p-13f;  // lower end of the segment parameter
+
+__device__ __forceinline__ bool any_hit(const Ray &r, const Node *__restrict__ nodes, const TriRec *__restrict__ recs,
+                                        int root, int *stk)
+{
+    int sp = 0;
+    int ref = root;
+    while (true) {
+        if (ref >= 0) {
+            const Node *n = nodes + ref;
+            const float4 a = n->xy0, c = n->xy1, z = n->z01;
+            const int4 ch = n->ch;
+            float t0, t1;
+            const bool h0 = slab(r, a.x, a.y, a.z, a.w, z.x, z.y, r.tf, t0);
+            const bool h1 = slab(r, c.x, c.y, c.z, c.w, z.z, z.w, r.tf, t1);
+            if (h0 && h1) {
+                stk[sp * kBlock] = ch.y;
+                ++sp;
+                ref = ch.x;
+                continue;
+            }
+            if (h0 || h1) {
+                ref = h0 ? ch.x : ch.y;
+                continue;
+            }
+        } else {
+            const int code = ~ref;
+            const int first = code >> 3, cnt = (code & 7) + 1;
+            for (int k = 0; k < cnt; ++k) {
+                const TriRec T = recs[first + k];
+                float tt, et;
+                const int d = mt32(r, T.a, T.b, T.c, r.tf, tt, et);
+                if (d == kAccept)
+                    return true;
+                double t64;
+                if (d == kUnsure && mt64(r, T.a, T.b, T.c, t64))
+                    return true;
+            }
+        }
+        if (sp == 0)
+            return false;
+        --sp;
+        ref = stk[sp * kBlock];
+    }
+}
+
+// One wavefront per 64-ray tile: the hit point p = o + t d (FP64 t of the
+// winner read from the tri output, rounded as the hit output is), the second
+// centre c2 = pose applied to the baseline (FP32, the transform's fma order),
+// the segment p + s (c2 - p), s in [kShadowS0, 1].
+__global__ __launch_bounds__(kBlock) void k_stereo_shadow(SceneView sc, SensorView se, OutView o, int64_t n_items)
+{
+    __shared__ int s_stack[kStack * kBlock];
+    const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    if (k >= n_items)
+        return;
+    const int2 item = se.items[k];
+    const Tile t = load_tile(se, item);
+    const int lane = threadIdx.x & 63;
+    const int ty = item.y / t.tiles_x, tx = item.y - ty * t.tiles_x;
+    const int tw = 1 << t.tw_shift;
+    const int row = ty * (64 >> t.tw_shift) + (lane >> t.tw_shift), col = tx * tw + (lane & (tw - 1));
+    if (row >= t.H || col >= t.W)
+        return;
+    const int64_t idx = t.ray_base + (int64_t)row * t.W + col;
+    const SensorModel &M = se.models[se.si_model[t.s]];
+    const int id = o.tri[idx];
+    uint8_t hidden = 0;
+    const int root = sc.env_root[t.env];
+    if (M.stereo && id >= 0 && root != kEmptyRoot) {
+        Ray r;
+        gen_ray(se, t, row, col, r);
+        const int64_t base = sc.env_tri_off[t.env];
+        const float *w = sc.world + 9 * (base + id);
+        const float4 A = make_float4(w[0], w[1], w[2], w[3]), B = make_float4(w[4], w[5], w[6], w[7]),
+                     C = make_float4(w[8], 0.f, 0.f, 0.f);
+        double tt;
+        if (!mt64(r, A, B, C, tt))
+            tt = 0.5 * ((double)r.tn + (double)r.tf);  // unreachable for a certified winner
+        const float px = (float)((double)r.ox + tt * (double)r.dx);
+        const float py = (float)((double)r.oy + tt * (double)r.dy);
+        const float pz = (float)((double)r.oz + tt * (double)r.dz);
+        const float *P = se.pose + 12 * (int64_t)t.s;
+        const float cx = fmaf(P[0], M.sb[0], fmaf(P[1], M.sb[1], fmaf(P[2], M.sb[2], P[3])));
+        const float cy = fmaf(P[4], M.sb[0], fmaf(P[5], M.sb[1], fmaf(P[6], M.sb[2], P[7])));
+        const float cz = fmaf(P[8], M.sb[0], fmaf(P[9], M.sb[1], fmaf(P[10], M.sb[2], P[11])));
+        Ray s;
+        s.ox = px;
+        s.oy = py;
+        s.oz = pz;
+        s.dx = cx - px;
+        s.dy = cy - py;
+        s.dz = cz - pz;
+        s.ix = 1.0f / s.dx;
+        s.iy = 1.0f / s.dy;
+        s.iz = 1.0f / s.dz;
+        s.knd = kErr * fmaxf(fmaxf(fabsf(s.dx), fabsf(s.dy)), fabsf(s.dz));
+        s.tn = kShadowS0;
+        s.tf = 1.0f;
+        hidden = any_hit(s, sc.nodes + node_base(base, t.env), sc.recs + base, root, s_stack + threadIdx.x) ? 1 : 0;
+    }
+    o.shadow[idx] = hidden;
 }
 
 __global__ __launch_bounds__(256) void k_debug_rays(SensorView se, int32_t s, int64_t n,
@@ -617,6 +836,26 @@ hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, cons
     if (err != hipSuccess)
         return err;
     hipLaunchKernelGGL(k_render_batched, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_hit_extras(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                             hipStream_t st)
+{
+    if (n_items == 0 || !(o.normal || o.bary || o.point || o.vert))
+        return hipSuccess;
+    hipLaunchKernelGGL(k_hit_extras, dim3((unsigned)((n_items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
+                       st, sc, se, o, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_stereo_shadow(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,
+                                hipStream_t st)
+{
+    if (n_items == 0 || !o.shadow)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_stereo_shadow, dim3((unsigned)((n_items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock),
+                       0, st, sc, se, o, n_items);
     return hipGetLastError();
 }
 

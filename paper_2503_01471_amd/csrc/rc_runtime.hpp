@@ -74,6 +74,7 @@ struct Scene {
     std::vector<int64_t> inst_offsets;
     DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
     DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, env_micro, micro;
+    DBuf level_nodes, level_off;
     bool poses_set = false;
     bool built = false;
     BuildView view() const;
@@ -95,6 +96,22 @@ struct Sensors {
     SensorView view() const;
     QueueView queue(int chunk) const;
 };
+
+// Kernel view of caller output buffers.
+inline OutView out_view(const rc_outputs &o)
+{
+    OutView v;
+    v.depth = o.depth;
+    v.seg = o.seg;
+    v.tri = o.tri;
+    v.hit = o.hit_xyz;
+    v.normal = o.normal;
+    v.bary = o.bary;
+    v.point = o.point;
+    v.vert = o.vert;
+    v.shadow = o.shadow;
+    return v;
+}
 
 // Launch choices of the batched form (set by rc_autotune).
 struct Tuning {

@@ -216,7 +216,9 @@ rc_status launch(rc_server *sv, Slot &sl)
     ev.ray_off = sl.ray_off.as<int64_t>();
     ev.pose = sl.pose.as<float>();
     ev.items = sl.items.as<int2>();
-    const OutView ov{nullptr, nullptr, nullptr, nullptr, sl.dtab.as<float *>(), sl.stab.as<int32_t *>()};
+    OutView ov;
+    ov.depth_tab = sl.dtab.as<float *>();
+    ov.seg_tab = sl.stab.as<int32_t *>();
     if (sv->mode == RC_SERVE_BATCHED) {
         QueueView qv;
         qv.items = ev.items;

@@ -42,11 +42,23 @@ class RCError(RuntimeError):
 class rc_sensor_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32), ("hfov", C.c_float),
                 ("vmin", C.c_float), ("vmax", C.c_float), ("hmin", C.c_float), ("hmax", C.c_float),
-                ("near_", C.c_float), ("far_", C.c_float), ("dir_table", C.c_void_p)]
+                ("near_", C.c_float), ("far_", C.c_float), ("dir_table", C.c_void_p), ("stereo", C.c_float * 3)]
 
 
 class rc_outputs(C.Structure):
-    _fields_ = [("depth", C.c_void_p), ("seg", C.c_void_p), ("tri", C.c_void_p), ("hit_xyz", C.c_void_p)]
+    _fields_ = [("depth", C.c_void_p), ("seg", C.c_void_p), ("tri", C.c_void_p), ("hit_xyz", C.c_void_p),
+                ("normal", C.c_void_p), ("bary", C.c_void_p), ("point", C.c_void_p), ("vert", C.c_void_p),
+                ("shadow", C.c_void_p)]
+
+
+def _outputs(total_rays, depth=None, seg=None, tri=None, hit_xyz=None, normal=None, bary=None, point=None,
+             vert=None, shadow=None) -> rc_outputs:
+    def opt(t, dt, k, what):
+        return None if t is None else _dev(t, dt, k * total_rays, what)
+    return rc_outputs(opt(depth, "float32", 1, "depth"), opt(seg, "int32", 1, "seg"), opt(tri, "int32", 1, "tri"),
+                      opt(hit_xyz, "float32", 3, "hit_xyz"), opt(normal, "float32", 3, "normal"),
+                      opt(bary, "float32", 2, "bary"), opt(point, "float32", 3, "point"),
+                      opt(vert, "int32", 3, "vert"), opt(shadow, "uint8", 1, "shadow"))
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -210,10 +222,10 @@ def rc_scene_load(ctx, inst_offsets, inst_mesh, inst_seg, inst_dynamic=None) -> 
 
 
 def rc_sensor_add(ctx, kind, width, height, hfov=0.0, vmin=0.0, vmax=0.0, hmin=0.0, hmax=0.0, near=0.0,
-                  far=0.0, dir_table=None) -> int:
+                  far=0.0, dir_table=None, stereo=(0.0, 0.0, 0.0)) -> int:
     tab = None if dir_table is None else _host(dir_table, np.float32)
     d = rc_sensor_desc(kind, width, height, hfov, vmin, vmax, hmin, hmax, near, far,
-                       None if tab is None else tab.ctypes.data)
+                       None if tab is None else tab.ctypes.data, (C.c_float * 3)(*[float(x) for x in stereo]))
     sid = C.c_int32()
     _check(lib().rc_sensor_add(ctx, C.byref(d), C.byref(sid)))
     return sid.value
@@ -265,12 +277,8 @@ def rc_refit(ctx, stream=None, env_mask=None) -> None:
 
 
 def rc_render(ctx, depth=None, seg=None, tri=None, hit_xyz=None, mode: int = RC_RENDER_FLAT, stream=None,
-              total_rays: int = 0) -> None:
-    out = rc_outputs(
-        None if depth is None else _dev(depth, "float32", total_rays, "depth"),
-        None if seg is None else _dev(seg, "int32", total_rays, "seg"),
-        None if tri is None else _dev(tri, "int32", total_rays, "tri"),
-        None if hit_xyz is None else _dev(hit_xyz, "float32", 3 * total_rays, "hit_xyz"))
+              total_rays: int = 0, normal=None, bary=None, point=None, vert=None, shadow=None) -> None:
+    out = _outputs(total_rays, depth, seg, tri, hit_xyz, normal, bary, point, vert, shadow)
     _check(lib().rc_render(ctx, C.byref(out), mode, _stream(stream)))
 
 
@@ -320,12 +328,9 @@ def rc_tuning_set(ctx, tile_cols: int = 8, chunk: int = 4, cost_order: int = 1) 
     _check(lib().rc_tuning_set(ctx, _ptr(ch)))
 
 
-def rc_step_graph_create(ctx, d_vel, dt: float, depth=None, seg=None, tri=None, hit_xyz=None, total_rays: int = 0):
-    out = rc_outputs(
-        None if depth is None else _dev(depth, "float32", total_rays, "depth"),
-        None if seg is None else _dev(seg, "int32", total_rays, "seg"),
-        None if tri is None else _dev(tri, "int32", total_rays, "tri"),
-        None if hit_xyz is None else _dev(hit_xyz, "float32", 3 * total_rays, "hit_xyz"))
+def rc_step_graph_create(ctx, d_vel, dt: float, depth=None, seg=None, tri=None, hit_xyz=None, total_rays: int = 0,
+                         normal=None, bary=None, point=None, vert=None, shadow=None):
+    out = _outputs(total_rays, depth, seg, tri, hit_xyz, normal, bary, point, vert, shadow)
     g = C.c_void_p()
     _check(lib().rc_step_graph_create(ctx, C.byref(out), _dev(d_vel, "float32", 0, "d_vel"), dt, C.byref(g)))
     return g.value

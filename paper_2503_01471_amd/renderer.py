@@ -26,7 +26,7 @@ class Renderer:
         rc.rc_scene_load(self.ctx, scene.inst_offsets, scene.inst_mesh, scene.inst_seg, scene.inst_dynamic)
         for desc in scene.sensors:
             rc.rc_sensor_add(self.ctx, desc.kind, desc.width, desc.height, desc.hfov, desc.vmin, desc.vmax,
-                             desc.hmin, desc.hmax, desc.near, desc.far, desc.dir_table)
+                             desc.hmin, desc.hmax, desc.near, desc.far, desc.dir_table, getattr(desc, "stereo", (0, 0, 0)))
         rc.rc_sensors_attach(self.ctx, scene.sens_offsets, scene.sensor_ids)
         self.n_si = len(scene.sensor_ids)
         self.ray_offsets, self.total_rays = rc.rc_ray_layout(self.ctx, self.n_si)
@@ -70,21 +70,24 @@ class Renderer:
         rc.rc_set_sensor_poses(self.ctx, T, stream)
 
     # -- outputs -------------------------------------------------------------
-    def alloc(self, depth=True, seg=True, tri=False, hit=False):
+    def alloc(self, depth=True, seg=True, tri=False, hit=False, normal=False, bary=False, point=False, vert=False,
+              shadow=False):
         n = self.total_rays
         d = self.device
-        return dict(
-            depth=torch.empty(n, dtype=torch.float32, device=d) if depth else None,
-            seg=torch.empty(n, dtype=torch.int32, device=d) if seg else None,
-            tri=torch.empty(n, dtype=torch.int32, device=d) if tri else None,
-            hit_xyz=torch.empty(n, 3, dtype=torch.float32, device=d) if hit else None,
-        )
+
+        def mk(flag, shape, dt):
+            return torch.empty(shape, dtype=dt, device=d) if flag else None
+        return dict(depth=mk(depth, n, torch.float32), seg=mk(seg, n, torch.int32), tri=mk(tri, n, torch.int32),
+                    hit_xyz=mk(hit, (n, 3), torch.float32), normal=mk(normal, (n, 3), torch.float32),
+                    bary=mk(bary, (n, 2), torch.float32), point=mk(point, (n, 3), torch.float32),
+                    vert=mk(vert, (n, 3), torch.int32), shadow=mk(shadow, n, torch.uint8))
 
     def render(self, out=None, mode: int = rc.RC_RENDER_FLAT, stream=None, **which):
         if out is None:
             out = self.alloc(**which) if which else self.alloc(depth=True, seg=True, tri=True, hit=True)
         rc.rc_render(self.ctx, out.get("depth"), out.get("seg"), out.get("tri"), out.get("hit_xyz"), mode, stream,
-                     self.total_rays)
+                     self.total_rays, normal=out.get("normal"), bary=out.get("bary"), point=out.get("point"),
+                     vert=out.get("vert"), shadow=out.get("shadow"))
         return out
 
     def stats(self):

@@ -64,3 +64,52 @@ def assert_contract(rep: dict) -> None:
     if "max_hit_err_ulps" in rep:
         assert rep["max_hit_err_ulps"] <= 4.0, rep
         assert rep["miss_hit_not_nan"] == 0, rep
+
+
+# Further data types of a hit: both sides evaluate the same FP64 expressions on
+# identical FP32 vertices and rays and differ only in operation order (a few
+# FP64 ulps), so after the single rounding to FP32 they agree to within one
+# FP32 ulp: 2^-22 absolute for unit-range quantities (normal components, u, v),
+# 2^-21 relative for sensor-frame points.
+TOL_UNIT = 2.0 ** -22
+TOL_POINT_REL = 2.0 ** -21
+
+
+def compare_extras(gpu: dict, ora: "O.Render") -> dict:
+    """Normals, barycentrics, sensor-frame points and vertex ids on every ray
+    where GPU and oracle picked the same triangle (all robust hits), plus the
+    miss sentinels on every ray both call a miss."""
+    tri = np.asarray(gpu["tri"])
+    same = (tri == ora.tri) & (tri >= 0)
+    miss = (tri < 0) & (ora.tri < 0)
+    rep = dict(compared=int(same.sum()))
+    robust = (ora.cls & O.BORDER_MASK) == 0
+    rep["robust_hits_not_compared"] = int(np.sum(robust & (ora.tri >= 0) & ~same))
+    if gpu.get("normal") is not None:
+        e = np.abs(gpu["normal"][same].astype(np.float64) - ora.normal[same])
+        rep["normal_max_abs"] = float(e.max()) if e.size else 0.0
+        rep["normal_bad"] = int(np.sum(~(e <= TOL_UNIT).all(1)))
+        rep["normal_miss_bad"] = int(np.sum(~np.isnan(gpu["normal"][miss]).all(1)))
+    if gpu.get("bary") is not None:
+        e = np.abs(gpu["bary"][same].astype(np.float64) - ora.bary[same])
+        rep["bary_max_abs"] = float(e.max()) if e.size else 0.0
+        rep["bary_bad"] = int(np.sum(~(e <= TOL_UNIT).all(1)))
+        rep["bary_miss_bad"] = int(np.sum(~np.isnan(gpu["bary"][miss]).all(1)))
+    if gpu.get("point") is not None:
+        g, o = gpu["point"][same].astype(np.float64), ora.point[same].astype(np.float64)
+        scale = np.maximum(np.abs(o).max(1, initial=0.0), 1e-30)
+        e = np.abs(g - o).max(1, initial=0.0) / scale
+        rep["point_max_rel"] = float(e.max()) if e.size else 0.0
+        rep["point_bad"] = int(np.sum(~(e <= TOL_POINT_REL)))
+        rep["point_miss_bad"] = int(np.sum(~np.isnan(gpu["point"][miss]).all(1)))
+    if gpu.get("vert") is not None:
+        rep["vert_bad"] = int(np.sum(np.any(gpu["vert"][same] != ora.vert[same], 1)))
+        rep["vert_miss_bad"] = int(np.sum(np.any(gpu["vert"][miss] != -1, 1)))
+    return rep
+
+
+def assert_extras(rep: dict) -> None:
+    assert rep["robust_hits_not_compared"] == 0, rep
+    for k, v in rep.items():
+        if k.endswith("_bad"):
+            assert v == 0, (k, rep)

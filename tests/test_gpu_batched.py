@@ -75,9 +75,10 @@ def test_step_graph_replays_match_eager():
     R = _R(scene)
     n = R.total_rays
     gout = dict(depth=torch.empty(n, device="cuda"), seg=torch.empty(n, dtype=torch.int32, device="cuda"),
-                tri=torch.empty(n, dtype=torch.int32, device="cuda"))
+                tri=torch.empty(n, dtype=torch.int32, device="cuda"), normal=torch.empty(n, 3, device="cuda"),
+                point=torch.empty(n, 3, device="cuda"))
     g = rc.rc_step_graph_create(R.ctx, R.inst_vel, float(scene.dt), depth=gout["depth"], seg=gout["seg"],
-                                tri=gout["tri"], total_rays=n)
+                                tri=gout["tri"], total_rays=n, normal=gout["normal"], point=gout["point"])
     rc.rc_graph_set_step(g, 1)
     for step in range(1, 6):
         _say(f"graph replay step {step}")
@@ -87,10 +88,10 @@ def test_step_graph_replays_match_eager():
         # eager reference for the same step (also exercises eager work between replays)
         R.move(step)
         R.refit()
-        ref = _host(R.render(mode=rc.RC_RENDER_BATCHED, depth=True, seg=True, tri=True))
+        ref = _host(R.render(mode=rc.RC_RENDER_BATCHED, depth=True, seg=True, tri=True, normal=True, point=True))
         torch.cuda.synchronize()
-        for k in ("depth", "seg", "tri"):
-            assert np.array_equal(got[k], ref[k]), (step, k)
+        for k in ("depth", "seg", "tri", "normal", "point"):
+            assert np.array_equal(got[k], ref[k], equal_nan=True), (step, k)
         if step == 3:
             w = O.world(scene, O.moved_poses(scene, step))
             rep = parity.compare(got, O.render(scene, w))
