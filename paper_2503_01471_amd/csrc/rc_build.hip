@@ -364,40 +364,50 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                     }
                 }
                 __syncthreads();
-                // evaluate 3 x (kBins-1) split planes, one per lane
+                // evaluate the 3 x (kBins-1) split planes, plane index pl = lane,
+                // lane + 64, ...; each lane keeps its cheapest (lowest index on ties)
                 float cost = INFINITY;
-                int nl = 0;
+                int nl = 0, bw = lane;
                 WaveBox bl{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
                 WaveBox br = bl;
-                if (lane < 3 * (kBins - 1)) {
-                    const int a = lane / (kBins - 1), k = lane % (kBins - 1);
-                    if (scale[a] != 0.f) {
-                        int nr = 0;
-                        for (int j = 0; j < kBins; ++j) {
-                            const int q = a * kBins + j;
-                            const int c = S.cnt[q];
-                            if (c == 0)
-                                continue;
-                            WaveBox &B = j <= k ? bl : br;
-                            B.lx = fminf(B.lx, o2f(S.lo[3 * q]));
-                            B.ly = fminf(B.ly, o2f(S.lo[3 * q + 1]));
-                            B.lz = fminf(B.lz, o2f(S.lo[3 * q + 2]));
-                            B.hx = fmaxf(B.hx, o2f(S.hi[3 * q]));
-                            B.hy = fmaxf(B.hy, o2f(S.hi[3 * q + 1]));
-                            B.hz = fmaxf(B.hz, o2f(S.hi[3 * q + 2]));
-                            if (j <= k)
-                                nl += c;
-                            else
-                                nr += c;
+                for (int pl = lane; pl < 3 * (kBins - 1); pl += 64) {
+                    const int a = pl / (kBins - 1), k = pl % (kBins - 1);
+                    if (scale[a] == 0.f)
+                        continue;
+                    WaveBox cl{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+                    WaveBox cr = cl;
+                    int ml = 0, mr = 0;
+                    for (int j = 0; j < kBins; ++j) {
+                        const int q = a * kBins + j;
+                        const int c = S.cnt[q];
+                        if (c == 0)
+                            continue;
+                        WaveBox &B = j <= k ? cl : cr;
+                        B.lx = fminf(B.lx, o2f(S.lo[3 * q]));
+                        B.ly = fminf(B.ly, o2f(S.lo[3 * q + 1]));
+                        B.lz = fminf(B.lz, o2f(S.lo[3 * q + 2]));
+                        B.hx = fmaxf(B.hx, o2f(S.hi[3 * q]));
+                        B.hy = fmaxf(B.hy, o2f(S.hi[3 * q + 1]));
+                        B.hz = fmaxf(B.hz, o2f(S.hi[3 * q + 2]));
+                        if (j <= k)
+                            ml += c;
+                        else
+                            mr += c;
+                    }
+                    if (ml > 0 && mr > 0) {
+                        const float c = half_area(cl.lx, cl.ly, cl.lz, cl.hx, cl.hy, cl.hz) * (float)ml +
+                                        half_area(cr.lx, cr.ly, cr.lz, cr.hx, cr.hy, cr.hz) * (float)mr;
+                        if (c < cost) {
+                            cost = c;
+                            nl = ml;
+                            bw = pl;
+                            bl = cl;
+                            br = cr;
                         }
-                        if (nl > 0 && nr > 0)
-                            cost = half_area(bl.lx, bl.ly, bl.lz, bl.hx, bl.hy, bl.hz) * (float)nl +
-                                   half_area(br.lx, br.ly, br.lz, br.hx, br.hy, br.hz) * (float)nr;
                     }
                 }
-                // argmin over lanes, ties to the lower lane
+                // argmin over lanes, ties to the lower plane index
                 float bc = cost;
-                int bw = lane;
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
                     const float oc = __shfl_xor(bc, o, 64);
@@ -410,11 +420,12 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                 if (bc < INFINITY) {
                     best_axis = bw / (kBins - 1);
                     best_k = bw % (kBins - 1);
-                    const int nL = __shfl(nl, bw, 64);
-                    L = WaveBox{__shfl(bl.lx, bw, 64), __shfl(bl.ly, bw, 64), __shfl(bl.lz, bw, 64),
-                                __shfl(bl.hx, bw, 64), __shfl(bl.hy, bw, 64), __shfl(bl.hz, bw, 64)};
-                    R = WaveBox{__shfl(br.lx, bw, 64), __shfl(br.ly, bw, 64), __shfl(br.lz, bw, 64),
-                                __shfl(br.hx, bw, 64), __shfl(br.hy, bw, 64), __shfl(br.hz, bw, 64)};
+                    const int src = bw & 63;  // the lane that evaluated plane bw
+                    const int nL = __shfl(nl, src, 64);
+                    L = WaveBox{__shfl(bl.lx, src, 64), __shfl(bl.ly, src, 64), __shfl(bl.lz, src, 64),
+                                __shfl(bl.hx, src, 64), __shfl(bl.hy, src, 64), __shfl(bl.hz, src, 64)};
+                    R = WaveBox{__shfl(br.lx, src, 64), __shfl(br.ly, src, 64), __shfl(br.lz, src, 64),
+                                __shfl(br.hx, src, 64), __shfl(br.hy, src, 64), __shfl(br.hz, src, 64)};
                     mid = b + nL;
                     // stable partition, then copy back
                     int lc = 0, rc = 0;
