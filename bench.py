@@ -86,7 +86,7 @@ def cpu_baseline(cfg, seconds):
     O.render(sc, nthreads=cores)
     dt = time.perf_counter() - t0
     if cfg != 1:
-        n_env = max(1, min(64, int(seconds / max(dt, 1e-3))))
+        n_env = max(1, min(512, int(seconds / max(dt, 1e-3))))
         sc = S.make(cfg, env_ids=list(range(n_env)))
         t0 = time.perf_counter()
         O.render(sc, nthreads=cores)
