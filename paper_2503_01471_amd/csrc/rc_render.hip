@@ -419,7 +419,13 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     const int root = sc.env_root[t.env];
     if (root != kEmptyRoot)
         traverse<STATS>(r, nodes, recs, root, stk, b, st);
-    write_out(o, sc, se, t, row, col, r, recs, b);
+    // The output position is recomputed here from the lane: the empty asm
+    // hides that it equals the one above, so the compiler does not keep
+    // address arithmetic alive (spilled) across the traversal.
+    int lane2 = lane;
+    asm volatile("" : "+v"(lane2));
+    const int row2 = ty * (64 >> t.tw_shift) + (lane2 >> t.tw_shift), col2 = tx * tw + (lane2 & (tw - 1));
+    write_out(o, sc, se, t, row2, col2, r, recs, b);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; map them so that each XCD walks
