@@ -82,6 +82,7 @@ def cpu_baseline(cfg, seconds):
     cores = len(os.sched_getaffinity(0))
     n_env = 1
     sc = S.make(cfg, env_ids=[0]) if cfg != 1 else S.make_cfg1()
+    O.render(sc, nthreads=cores)  # warm: library load, first-touch allocations
     t0 = time.perf_counter()
     O.render(sc, nthreads=cores)
     dt = time.perf_counter() - t0
