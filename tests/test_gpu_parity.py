@@ -439,3 +439,10 @@ def _sampled(scene, mode, n_sample=12000, seed=0):
 def test_full_size_sampled(cfg, mode):
     scene = S.make(cfg)
     _sampled(scene, mode)
+
+
+def test_smoke_entry_point():
+    """The repository's smoke check runs as the harness runs it."""
+    _need_gpu()
+    import __graft_entry__ as g
+    g.smoke()
