@@ -115,6 +115,7 @@ BuildView Scene::view() const
     v.env_nodes = env_nodes.as<int32_t>();
     v.env_micro = env_micro.as<int32_t>();
     v.micro = micro.as<int4>();
+    v.micro_off = micro_off.as<int64_t>();
     v.level_nodes = level_nodes.as<int32_t>();
     v.level_off = level_off.as<int32_t>();
     v.env_mask = nullptr;
@@ -436,6 +437,7 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->micro, 16 * N));
     RC_TRY(c->pool.alloc(sc->level_nodes, 4 * (size_t)(node_base(N, n_envs) + 16)));
     RC_TRY(c->pool.alloc(sc->level_off, 4 * (size_t)n_envs * (kLevels + 1)));
+    RC_TRY(c->pool.alloc(sc->micro_off, 8 * ((size_t)n_envs + 1)));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);

@@ -530,181 +530,246 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 }
 
 // ---------------------------------------------------------------------------
-// K5b: ranges of 5..16 primitives deferred by k_build_sah, one per thread.
-// Full-sweep SAH over the three centroid axes with both sides limited to
-// `cap` primitives (8 for the top split, so each side is a leaf or one more
-// node with two leaves; 4 below).  Sorting is an odd-even transposition
-// network on (centroid, position), so the result is deterministic.  The
-// range's bounds live in this thread's LDS slice.
+// K5b: ranges of 5..16 primitives deferred by k_build_sah.  One 16-lane group
+// per range (four per wavefront), one primitive per lane.  Full-sweep SAH over
+// the three centroid axes with both sides limited to `cap` primitives (8 for
+// the top split, so each side is a leaf or one more node with two leaves; 4
+// below): per axis the group sorts (centroid, position) with a bitonic
+// network across its lanes, scans the sorted boxes from both ends and takes
+// the cheapest split (lowest axis, then fewest left primitives, on ties).
+// Centroids are compared through their ordered-integer image, a total order,
+// so the network is a permutation for any input.
 // ---------------------------------------------------------------------------
-constexpr int kMicroBlock = 64;
+constexpr int kMicroBlock = 256;
+constexpr int kGroup = 16;
 
-struct MicroShared {
-    float box[6][kMicro][kMicroBlock];
-    int pid[kMicro][kMicroBlock];
-};
+// Ascending (key, id) across the 16 lanes of a group (ids distinct).
+__device__ __forceinline__ void group_sort(int &key, int &id, int gl)
+{
+#pragma unroll
+    for (int k = 2; k <= kGroup; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int ok = __shfl_xor(key, j, kGroup);
+            const int oi = __shfl_xor(id, j, kGroup);
+            const bool other_less = ok < key || (ok == key && oi < id);
+            const bool take = (((gl & k) == 0) == ((gl & j) == 0)) ? other_less : !other_less;
+            if (take) {
+                key = ok;
+                id = oi;
+            }
+        }
+    }
+}
 
-template <int N>
-__device__ __forceinline__ int micro_split(const MicroShared &M, int t, int *slot_out, int first, int cnt, int cap,
+__device__ __forceinline__ WaveBox group_box_reduce(WaveBox b)
+{
+#pragma unroll
+    for (int d = 1; d < kGroup; d <<= 1) {
+        b.lx = fminf(b.lx, __shfl_xor(b.lx, d, kGroup));
+        b.ly = fminf(b.ly, __shfl_xor(b.ly, d, kGroup));
+        b.lz = fminf(b.lz, __shfl_xor(b.lz, d, kGroup));
+        b.hx = fmaxf(b.hx, __shfl_xor(b.hx, d, kGroup));
+        b.hy = fmaxf(b.hy, __shfl_xor(b.hy, d, kGroup));
+        b.hz = fmaxf(b.hz, __shfl_xor(b.hz, d, kGroup));
+    }
+    return b;
+}
+
+// Cross-lane read within the group.  Call it from every lane of the group
+// (never inside a per-lane condition): a lane that skips it cannot be read.
+__device__ __forceinline__ WaveBox box_shfl(const WaveBox &b, int src)
+{
+    return WaveBox{__shfl(b.lx, src, kGroup), __shfl(b.ly, src, kGroup), __shfl(b.lz, src, kGroup),
+                   __shfl(b.hx, src, kGroup), __shfl(b.hy, src, kGroup), __shfl(b.hz, src, kGroup)};
+}
+
+constexpr WaveBox kEmptyBox{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+
+// Split of the `cnt` primitives that lanes [first, first + cnt) hold (lane r
+// holds box `bx`; positions outside are ignored), both sides at most `cap`.
+// On return lane q holds in `order` the lane whose primitive comes q-th along
+// the chosen axis (q < cnt), and the function returns the left count.
+__device__ __forceinline__ int group_split(const WaveBox &bx, int gl, int first, int cnt, int cap, int &order,
                                            WaveBox &L, WaveBox &R)
 {
-    float key[N];
-    int os[N];  // (original position << 8) | slot
-    float best_cost = INFINITY;
-    int best_axis = 0, best_k = cnt / 2;
+    const bool mine = gl >= first && gl < first + cnt;
     const int kmin = cnt - cap > 1 ? cnt - cap : 1;
     const int kmax = cap < cnt - 1 ? cap : cnt - 1;
-#pragma unroll 1
-    for (int axis = 0; axis <= 3; ++axis) {
-        const int a = axis < 3 ? axis : best_axis;  // pass 3 re-sorts along the chosen axis
+    float best_c = INFINITY;
+    int best_k = cnt / 2, best_a = 0;  // no finite cost: middle split along the first axis
+    int orders[3];
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            if (k < cnt) {
-                const int q = slot_out[first + k];
-                key[k] = 0.5f * (M.box[a][q][t] + M.box[a + 3][q][t]);
-                os[k] = (k << 8) | q;
-            } else {
-                key[k] = INFINITY;
-                os[k] = ((N + k) << 8);
+    for (int a = 0; a < 3; ++a) {
+        const float c = a == 0 ? 0.5f * (bx.lx + bx.hx) : (a == 1 ? 0.5f * (bx.ly + bx.hy) : 0.5f * (bx.lz + bx.hz));
+        int key = mine ? f2o(c) : INT32_MAX;
+        int id = mine ? gl : kGroup + gl;
+        group_sort(key, id, gl);
+        orders[a] = id;
+        // boxes in sorted order; identity beyond the range (every lane takes
+        // part in the shuffle: its source may lie outside [0, cnt))
+        const WaveBox got = box_shfl(bx, id & (kGroup - 1));
+        const WaveBox s = gl < cnt ? got : kEmptyBox;
+        WaveBox pre = s, suf = s;
+#pragma unroll
+        for (int d = 1; d < kGroup; d <<= 1) {
+            const WaveBox u = box_shfl(pre, gl >= d ? gl - d : gl);
+            if (gl >= d) {
+                pre.lx = fminf(pre.lx, u.lx);
+                pre.ly = fminf(pre.ly, u.ly);
+                pre.lz = fminf(pre.lz, u.lz);
+                pre.hx = fmaxf(pre.hx, u.hx);
+                pre.hy = fmaxf(pre.hy, u.hy);
+                pre.hz = fmaxf(pre.hz, u.hz);
+            }
+            const WaveBox w = box_shfl(suf, gl + d < kGroup ? gl + d : gl);
+            if (gl + d < kGroup) {
+                suf.lx = fminf(suf.lx, w.lx);
+                suf.ly = fminf(suf.ly, w.ly);
+                suf.lz = fminf(suf.lz, w.lz);
+                suf.hx = fmaxf(suf.hx, w.hx);
+                suf.hy = fmaxf(suf.hy, w.hy);
+                suf.hz = fmaxf(suf.hz, w.hz);
             }
         }
+        // lane r: split after k = r + 1 (left = sorted 0..r, right = r+1..cnt-1)
+        const WaveBox rs = box_shfl(suf, gl + 1 < kGroup ? gl + 1 : gl);
+        const int k = gl + 1;
+        float cost = INFINITY;
+        if (k >= kmin && k <= kmax && k < cnt)
+            cost = half_area(pre.lx, pre.ly, pre.lz, pre.hx, pre.hy, pre.hz) * (float)k +
+                   half_area(rs.lx, rs.ly, rs.lz, rs.hx, rs.hy, rs.hz) * (float)(cnt - k);
+        // cheapest over the group, fewest left primitives on ties
+        float bc = cost;
+        int bk = k;
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-#pragma unroll
-            for (int i = (r & 1); i + 1 < N; i += 2) {
-                const bool sw = key[i] > key[i + 1] || (key[i] == key[i + 1] && os[i] > os[i + 1]);
-                const float tk = sw ? key[i + 1] : key[i], uk = sw ? key[i] : key[i + 1];
-                const int to = sw ? os[i + 1] : os[i], uo = sw ? os[i] : os[i + 1];
-                key[i] = tk;
-                key[i + 1] = uk;
-                os[i] = to;
-                os[i + 1] = uo;
+        for (int d = 1; d < kGroup; d <<= 1) {
+            const float oc = __shfl_xor(bc, d, kGroup);
+            const int okk = __shfl_xor(bk, d, kGroup);
+            if (oc < bc || (oc == bc && okk < bk)) {
+                bc = oc;
+                bk = okk;
             }
         }
-        if (axis == 3)
-            break;
-        float ra[N];  // half area of the suffix [k, cnt)
-        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-#pragma unroll
-        for (int k = N - 1; k >= 1; --k) {
-            if (k < cnt) {
-                const int q = os[k] & 255;
-                lx = fminf(lx, M.box[0][q][t]);
-                ly = fminf(ly, M.box[1][q][t]);
-                lz = fminf(lz, M.box[2][q][t]);
-                hx = fmaxf(hx, M.box[3][q][t]);
-                hy = fmaxf(hy, M.box[4][q][t]);
-                hz = fmaxf(hz, M.box[5][q][t]);
-            }
-            ra[k] = half_area(lx, ly, lz, hx, hy, hz);
-        }
-        lx = ly = lz = INFINITY;
-        hx = hy = hz = -INFINITY;
-#pragma unroll
-        for (int k = 1; k < N; ++k) {
-            const int q = os[k - 1] & 255;
-            lx = fminf(lx, M.box[0][q][t]);
-            ly = fminf(ly, M.box[1][q][t]);
-            lz = fminf(lz, M.box[2][q][t]);
-            hx = fmaxf(hx, M.box[3][q][t]);
-            hy = fmaxf(hy, M.box[4][q][t]);
-            hz = fmaxf(hz, M.box[5][q][t]);
-            if (k >= kmin && k <= kmax && k < cnt) {
-                const float c = half_area(lx, ly, lz, hx, hy, hz) * (float)k + ra[k] * (float)(cnt - k);
-                if (c < best_cost) {
-                    best_cost = c;
-                    best_axis = axis;
-                    best_k = k;
-                }
-            }
+        if (bc < best_c) {
+            best_c = bc;
+            best_k = bk;
+            best_a = a;
         }
     }
-    L = WaveBox{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    R = L;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        if (k < cnt) {
-            const int q = os[k] & 255;
-            slot_out[first + k] = q;
-            WaveBox &B = k < best_k ? L : R;
-            B.lx = fminf(B.lx, M.box[0][q][t]);
-            B.ly = fminf(B.ly, M.box[1][q][t]);
-            B.lz = fminf(B.lz, M.box[2][q][t]);
-            B.hx = fmaxf(B.hx, M.box[3][q][t]);
-            B.hy = fmaxf(B.hy, M.box[4][q][t]);
-            B.hz = fmaxf(B.hz, M.box[5][q][t]);
-        }
-    }
+    order = best_a == 0 ? orders[0] : (best_a == 1 ? orders[1] : orders[2]);
+    // child boxes of the chosen split
+    const WaveBox got = box_shfl(bx, order & (kGroup - 1));
+    const WaveBox s = gl < cnt ? got : kEmptyBox;
+    L = group_box_reduce(gl < best_k ? s : kEmptyBox);
+    R = group_box_reduce(gl >= best_k && gl < cnt ? s : kEmptyBox);
     return best_k;
 }
 
 __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
 {
-    __shared__ MicroShared M;
-    const int t = threadIdx.x;
-    const int64_t g = (int64_t)blockIdx.x * kMicroBlock + t;
-    if (g >= v.n_tris)
-        return;
-    const int e = v.tri_env[g];
-    if (masked_out(v, e))
-        return;
-    const int64_t base = v.env_tri_off[e];
-    const int j = (int)(g - base);
-    if (j >= v.env_micro[e])
-        return;
-    const int4 task = v.micro[base + j];  // node, begin, end, depth
-    int32_t *prim = v.prim + base;
-    Node *nodes = v.nodes + node_base(base, e);
-    const int cnt = task.z - task.y;
-    int slot[kMicro];
-#pragma unroll
-    for (int k = 0; k < kMicro; ++k) {
-        if (k < cnt) {
-            const int p = prim[task.y + k];
-            const float4 lo = v.box_lo[base + p], hi = v.box_hi[base + p];
-            M.box[0][k][t] = lo.x;
-            M.box[1][k][t] = lo.y;
-            M.box[2][k][t] = lo.z;
-            M.box[3][k][t] = hi.x;
-            M.box[4][k][t] = hi.y;
-            M.box[5][k][t] = hi.z;
-            M.pid[k][t] = p;
+    const int gl = threadIdx.x & (kGroup - 1);
+    const int64_t n_groups = ((int64_t)gridDim.x * kMicroBlock) / kGroup;
+    const int64_t total = v.micro_off[v.n_envs];
+    for (int64_t T = ((int64_t)blockIdx.x * kMicroBlock + threadIdx.x) / kGroup; T < total; T += n_groups) {
+        // environment of task T: micro_off[e] <= T < micro_off[e + 1]
+        int lo = 0, hi = v.n_envs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (v.micro_off[mid] <= T)
+                lo = mid;
+            else
+                hi = mid;
         }
-        slot[k] = k;
-    }
-    WaveBox L, R;
-    // above 8 primitives each side may hold up to 8 (one more level); at most 8,
-    // both sides must be leaves (only one node id was reserved)
-    const int kb = micro_split<kMicro>(M, t, slot, 0, cnt, cnt > 2 * kLeafMax ? 2 * kLeafMax : kLeafMax, L, R);
-    write_boxes(nodes[task.x], L, R);
-    const int sub[2] = {0, kb}, sc[2] = {kb, cnt - kb};
-    int ref[2];
-    int next = task.x + 1;  // reserved ids (ranges above 8 only)
+        const int e = lo;
+        const int64_t base = v.env_tri_off[e];
+        const int4 task = v.micro[base + (T - v.micro_off[e])];  // node, begin, end, depth
+        int32_t *prim = v.prim + base;
+        Node *nodes = v.nodes + node_base(base, e);
+        const int cnt = task.z - task.y;
+        // lane r holds primitive r of the range
+        int pid = -1;
+        WaveBox bx = kEmptyBox;
+        if (gl < cnt) {
+            pid = prim[task.y + gl];
+            const float4 lo4 = v.box_lo[base + pid], hi4 = v.box_hi[base + pid];
+            bx = WaveBox{lo4.x, lo4.y, lo4.z, hi4.x, hi4.y, hi4.z};
+        }
+        // top split: above 8 primitives each side may hold up to 8 (one more
+        // level); at most 8, both sides must be leaves (only one id reserved)
+        int order;
+        WaveBox L, R;
+        const int kb = group_split(bx, gl, 0, cnt, cnt > 2 * kLeafMax ? 2 * kLeafMax : kLeafMax, order, L, R);
+        // lane r now takes the primitive of sorted position r
+        const int src = order & (kGroup - 1);
+        const WaveBox sb = box_shfl(bx, src);
+        const int spid = __shfl(pid, src, kGroup);
+        if (gl == 0)
+            write_boxes(nodes[task.x], L, R);
+        const int sub[2] = {0, kb}, sc[2] = {kb, cnt - kb};
+        int ref[2];
+        int next = task.x + 1;  // reserved ids (ranges above 8 only)
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-        if (sc[sd] <= kLeafMax) {
-            ref[sd] = leaf_ref(task.y + sub[sd], sc[sd]);
-        } else {
-            const int cid = next++;
-            ref[sd] = cid;
-            WaveBox L2, R2;
-            const int k2 = micro_split<2 * kLeafMax>(M, t, slot, sub[sd], sc[sd], kLeafMax, L2, R2);
-            Node &cn = nodes[cid];
-            write_boxes(cn, L2, R2);
-            cn.ch = make_int4(leaf_ref(task.y + sub[sd], k2), leaf_ref(task.y + sub[sd] + k2, sc[sd] - k2), task.x,
-                              task.w + 1);
+        for (int sd = 0; sd < 2; ++sd) {
+            if (sc[sd] <= kLeafMax) {
+                ref[sd] = leaf_ref(task.y + sub[sd], sc[sd]);
+                if (gl >= sub[sd] && gl < sub[sd] + sc[sd])
+                    prim[task.y + gl] = spid;
+            } else {
+                const int cid = next++;
+                ref[sd] = cid;
+                int ord2;
+                WaveBox L2, R2;
+                const int k2 = group_split(sb, gl, sub[sd], sc[sd], kLeafMax, ord2, L2, R2);
+                const int pid2 = __shfl(spid, ord2 & (kGroup - 1), kGroup);
+                if (gl < sc[sd])
+                    prim[task.y + sub[sd] + gl] = pid2;
+                if (gl == 0) {
+                    Node &cn = nodes[cid];
+                    write_boxes(cn, L2, R2);
+                    cn.ch = make_int4(leaf_ref(task.y + sub[sd], k2), leaf_ref(task.y + sub[sd] + k2, sc[sd] - k2),
+                                      task.x, task.w + 1);
+                }
+            }
+        }
+        if (gl == 0) {
+            // unused reserved ids: never referenced; a depth of -1 keeps refit away
+            if (cnt > 2 * kLeafMax)
+                for (int h = next; h < task.x + 3; ++h)
+                    nodes[h].ch = make_int4(0, 0, -1, -1);
+            nodes[task.x].ch.x = ref[0];
+            nodes[task.x].ch.y = ref[1];
         }
     }
-    // unused reserved ids: never referenced; a depth of -1 keeps refit away
-    if (cnt > 2 * kLeafMax)
-        for (int h = next; h < task.x + 3; ++h)
-            nodes[h].ch = make_int4(0, 0, -1, -1);
-    nodes[task.x].ch.x = ref[0];
-    nodes[task.x].ch.y = ref[1];
-#pragma unroll
-    for (int k = 0; k < kMicro; ++k)
-        if (k < cnt)
-            prim[task.y + k] = M.pid[slot[k]][t];
+}
+
+// K5a: where each environment's deferred ranges start in one list of all
+// tasks (exclusive scan of the per-environment counts; masked environments
+// count none); micro_off[n_envs] is the total.  One workgroup.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_micro_scan(BuildView v)
+{
+    __shared__ int64_t s[kScanBlock];
+    int64_t carry = 0;
+    for (int c0 = 0; c0 < v.n_envs; c0 += kScanBlock) {
+        const int e = c0 + threadIdx.x;
+        const int64_t x = (e < v.n_envs && !masked_out(v, e)) ? v.env_micro[e] : 0;
+        s[threadIdx.x] = x;
+        __syncthreads();
+        for (int d = 1; d < kScanBlock; d <<= 1) {
+            const int64_t y = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (e < v.n_envs)
+            v.micro_off[e] = carry + s[threadIdx.x] - x;
+        carry += s[kScanBlock - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        v.micro_off[v.n_envs] = carry;
 }
 
 // K5c: leaf-ordered records and the inverse permutation, one thread per triangle.
@@ -899,7 +964,13 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || v.n_tris == 0)
         return err;
-    hipLaunchKernelGGL(k_build_micro, dim3(blocks_for(v.n_tris, kMicroBlock)), dim3(kMicroBlock), 0, st, v);
+    hipLaunchKernelGGL(k_micro_scan, dim3(1), dim3(kScanBlock), 0, st, v);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    // persistent groups; every range holds >= 5 primitives, so there are at most n_tris / 5
+    const int64_t groups = v.n_tris / 5 + 1;
+    const int64_t blocks = (groups * kGroup + kMicroBlock - 1) / kMicroBlock;
+    hipLaunchKernelGGL(k_build_micro, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kMicroBlock), 0, st, v);
     if ((err = hipGetLastError()) != hipSuccess)
         return err;
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
