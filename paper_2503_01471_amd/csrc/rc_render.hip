@@ -124,6 +124,43 @@ __device__ __forceinline__ bool slab(const Ray &r, float lx, float hx, float ly,
     return tmin <= tmax * kBoxGrow;
 }
 
+// The same test when every lane of the wavefront has the same direction
+// octant (bit a of OCT: the inverse direction component a has its sign bit
+// set; OCT = kMixed selects the general test above).  Subtraction and
+// multiplication round monotonically, so for a non-negative inverse the low
+// plane's computed t never exceeds the high plane's: the min / max pairs of
+// the general test reduce to a choice by sign.  The one difference is a plane
+// through the origin on an axis the ray runs parallel to (0 * inf = NaN): this
+// form ignores that plane where the general one treats the box as missed.
+// Both are safe, because a stored box lies strictly outside its triangles'
+// bounds (one float step), so such a ray cannot reach a triangle inside it.
+constexpr int kMixed = 8;
+
+template <int OCT>
+__device__ __forceinline__ bool slab_oct(const Ray &r, float lx, float hx, float ly, float hy, float lz, float hz,
+                                         float tcap, float &tenter)
+{
+    if constexpr (OCT == kMixed) {
+        return slab(r, lx, hx, ly, hy, lz, hz, tcap, tenter);
+    } else {
+        const float nx = (OCT & 1) ? hx : lx, fx = (OCT & 1) ? lx : hx;
+        const float ny = (OCT & 2) ? hy : ly, fy = (OCT & 2) ? ly : hy;
+        const float nz = (OCT & 4) ? hz : lz, fz = (OCT & 4) ? lz : hz;
+        const float tmin = fmaxf(fmaxf((nx - r.ox) * r.ix, (ny - r.oy) * r.iy), fmaxf((nz - r.oz) * r.iz, r.tn));
+        const float tmax = fminf(fminf((fx - r.ox) * r.ix, (fy - r.oy) * r.iy), fminf((fz - r.oz) * r.iz, tcap));
+        tenter = tmin;
+        return tmin <= tmax * kBoxGrow;
+    }
+}
+
+// Octant shared by every active lane of the wavefront, else kMixed.
+__device__ __forceinline__ int wave_octant(const Ray &r)
+{
+    const int o = (signbit(r.ix) ? 1 : 0) | (signbit(r.iy) ? 2 : 0) | (signbit(r.iz) ? 4 : 0);
+    const int o0 = uniform(o);
+    return __all(o == o0) ? o0 : kMixed;
+}
+
 // ---------------------------------------------------------------------------
 // Moller-Trumbore with certified FP32 decisions.
 //   e1 = v1 - v0, e2 = v2 - v0, T = o - v0, p = d x e2, q = T x e1,
@@ -287,10 +324,49 @@ __device__ __forceinline__ void offer(const Ray &r, const TriRec *__restrict__ r
 // active lane holds a leaf or finishes); phase 2 tests the postponed leaves.
 constexpr int kDone = INT32_MIN;  // never a leaf reference
 
+// Phase 1 of a round: walk internal nodes until this lane holds a leaf (or
+// has finished) and every other active lane does too.
+template <bool STATS, int OCT>
+__device__ __forceinline__ void descend(const Ray &r, const Node *__restrict__ nodes, int *stk, float tcap, int &sp,
+                                        int &ref, int &leaf, Stats &st)
+{
+    while (ref >= 0) {
+        const Node *n = nodes + ref;
+        const float4 a = n->xy0, c = n->xy1, z = n->z01;
+        const int4 ch = n->ch;
+        // Issue all four loads of the node before the first use: left alone,
+        // the scheduler may start on the first box and send the last load
+        // after waiting for the others, a second memory round trip per node.
+        __builtin_amdgcn_sched_barrier(0);
+        float t0, t1;
+        const bool h0 = slab_oct<OCT>(r, a.x, a.y, a.z, a.w, z.x, z.y, tcap, t0);
+        const bool h1 = slab_oct<OCT>(r, c.x, c.y, c.z, c.w, z.z, z.w, tcap, t1);
+        if (STATS)
+            st.box += 2;
+        if (h0 && h1) {
+            const bool first0 = t0 <= t1;
+            stk[sp * kBlock] = first0 ? ch.y : ch.x;
+            ++sp;
+            ref = first0 ? ch.x : ch.y;
+        } else if (h0 || h1) {
+            ref = h0 ? ch.x : ch.y;
+        } else {
+            ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+        }
+        if (ref < 0 && ref != kDone && leaf == kDone) {
+            leaf = ref;
+            ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+        }
+        if (__all(leaf != kDone))
+            break;
+    }
+}
+
 template <bool STATS>
 __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ nodes,
                                          const TriRec *__restrict__ recs, int root, int *stk, Best &b, Stats &st)
 {
+    const int oct = wave_octant(r);
     int sp = 0;
     int ref = root;   // next node to visit (internal >= 0, leaf < 0) or kDone
     int leaf = kDone; // postponed leaf
@@ -299,31 +375,16 @@ __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ 
         ref = kDone;
     }
     while (true) {
-        while (ref >= 0) {
-            const Node *n = nodes + ref;
-            const float4 a = n->xy0, c = n->xy1, z = n->z01;
-            const int4 ch = n->ch;
-            float t0, t1;
-            const bool h0 = slab(r, a.x, a.y, a.z, a.w, z.x, z.y, b.hi, t0);
-            const bool h1 = slab(r, c.x, c.y, c.z, c.w, z.z, z.w, b.hi, t1);
-            if (STATS)
-                st.box += 2;
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                stk[sp * kBlock] = first0 ? ch.y : ch.x;
-                ++sp;
-                ref = first0 ? ch.x : ch.y;
-            } else if (h0 || h1) {
-                ref = h0 ? ch.x : ch.y;
-            } else {
-                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
-            }
-            if (ref < 0 && ref != kDone && leaf == kDone) {
-                leaf = ref;
-                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
-            }
-            if (__all(leaf != kDone))
-                break;
+        switch (oct) {
+        case 0: descend<STATS, 0>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 1: descend<STATS, 1>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 2: descend<STATS, 2>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 3: descend<STATS, 3>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 4: descend<STATS, 4>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 5: descend<STATS, 5>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 6: descend<STATS, 6>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 7: descend<STATS, 7>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        default: descend<STATS, kMixed>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
         }
         while (leaf != kDone) {
             const int code = ~leaf;
