@@ -3,9 +3,11 @@
 // Paper, Sec. III-D: every sub-mesh of environment i is moved by its own
 // transform and a BVH is computed over the transformed mesh; the paper
 // rebuilds it when static environments are randomised.  Here the build is a
-// binned surface-area-heuristic builder with one wavefront per environment
-// (all environments in one launch), plus a bottom-up refit on the fixed
-// topology for moving instances.
+// surface-area-heuristic builder with one wavefront per environment (all
+// environments in one launch): binned splits for large nodes, exact sweeps
+// over sorted centroids for nodes of at most kSmall primitives and, in a
+// second kernel, for the subtrees of 5..16 primitives; plus a bottom-up refit
+// on the fixed topology for moving instances.
 #include "rc_common.hpp"
 
 namespace rc {
@@ -136,10 +138,11 @@ __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 }
 
 // ---------------------------------------------------------------------------
-// K5: binned SAH build, one wavefront (64 lanes) per environment.
-// Tasks are processed depth first (left child next), node ids are assigned
-// when a task is popped, so the left child of node i is node i+1.  Splits are
-// stable partitions of the primitive list, so the build is deterministic.
+// K5: SAH build, one wavefront (64 lanes) per environment.
+// Tasks are processed depth first (left child next) and node ids are assigned
+// when a task is popped.  Nodes above kSmall primitives take the cheapest of
+// 3 x (kBins - 1) binned planes and split by a stable partition; smaller ones
+// take the exact sweep below.  Every step is deterministic.
 // A node whose subtree could exceed kMaxNodeDepth is split at the index median
 // (balanced), which bounds the traversal stack.
 // Once a task holds at most kSmall primitives its whole subtree is built from
@@ -191,6 +194,187 @@ __device__ __forceinline__ void write_boxes(Node &nd, const WaveBox &L, const Wa
     nd.xy0 = make_float4(expand_lo(L.lx), expand_hi(L.hx), expand_lo(L.ly), expand_hi(L.hy));
     nd.xy1 = make_float4(expand_lo(R.lx), expand_hi(R.hx), expand_lo(R.ly), expand_hi(R.hy));
     nd.z01 = make_float4(expand_lo(L.lz), expand_hi(L.hz), expand_lo(R.lz), expand_hi(R.hz));
+}
+
+// ---------------------------------------------------------------------------
+// Exact SAH sweep for a task of at most kSmall primitives held in LDS (local
+// mode).  Per axis the wavefront sorts (centroid, slot) keys with a bitonic
+// network (kSweepE keys per lane, key h of lane l at index 64 h + l).  Slots
+// are numbered in the order the primitives had when the subtree entered LDS,
+// which is ascending triangle id (every earlier split is a stable partition of
+// the identity order), so equal centroids fall in id order.  Then both ends
+// are scanned for the union boxes, every split position is costed, and the
+// cheapest wins (lowest axis, then fewest left primitives, on ties).
+// ---------------------------------------------------------------------------
+constexpr int kSweepE = kSmall / 64;
+static_assert(kSmall % 64 == 0 && (kSweepE & (kSweepE - 1)) == 0, "kSmall must be 64 times a power of two");
+constexpr WaveBox kEmptyBox{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+constexpr uint64_t kNoKey = ~0ull;
+
+__device__ __forceinline__ WaveBox box_union(const WaveBox &a, const WaveBox &b)
+{
+    return WaveBox{fminf(a.lx, b.lx), fminf(a.ly, b.ly), fminf(a.lz, b.lz),
+                   fmaxf(a.hx, b.hx), fmaxf(a.hy, b.hy), fmaxf(a.hz, b.hz)};
+}
+
+// Whole-wavefront lane reads (call from every lane).
+__device__ __forceinline__ WaveBox box_up(const WaveBox &b, int d)
+{
+    return WaveBox{__shfl_up(b.lx, d, 64), __shfl_up(b.ly, d, 64), __shfl_up(b.lz, d, 64),
+                   __shfl_up(b.hx, d, 64), __shfl_up(b.hy, d, 64), __shfl_up(b.hz, d, 64)};
+}
+__device__ __forceinline__ WaveBox box_down(const WaveBox &b, int d)
+{
+    return WaveBox{__shfl_down(b.lx, d, 64), __shfl_down(b.ly, d, 64), __shfl_down(b.lz, d, 64),
+                   __shfl_down(b.hx, d, 64), __shfl_down(b.hy, d, 64), __shfl_down(b.hz, d, 64)};
+}
+__device__ __forceinline__ WaveBox box_bcast(const WaveBox &b, int src)
+{
+    return WaveBox{__shfl(b.lx, src, 64), __shfl(b.ly, src, 64), __shfl(b.lz, src, 64),
+                   __shfl(b.hx, src, 64), __shfl(b.hy, src, 64), __shfl(b.hz, src, 64)};
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort(uint64_t (&key)[E], int lane)
+{
+#pragma unroll
+    for (int k = 2; k <= 64 * E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {  // partner in the same lane
+#pragma unroll
+                for (int h = 0; h < E; ++h) {
+                    const int h2 = h ^ (j >> 6);
+                    if (h2 < h)
+                        continue;
+                    const bool up = ((64 * h + lane) & k) == 0;
+                    const uint64_t a = key[h], c = key[h2];
+                    const bool swap = up ? c < a : a < c;
+                    key[h] = swap ? c : a;
+                    key[h2] = swap ? a : c;
+                }
+            } else {
+#pragma unroll
+                for (int h = 0; h < E; ++h) {
+                    const uint64_t o = shfl_xor_u64(key[h], j);
+                    const int i = 64 * h + lane;
+                    const bool keep_min = ((i & k) == 0) == ((i & j) == 0);
+                    key[h] = keep_min == (o < key[h]) ? o : key[h];
+                }
+            }
+        }
+    }
+}
+
+// Split of the cnt primitives at list positions pb .. pb + cnt - 1 of S.perm.
+// Returns the left count (0 if no split has a finite cost) and, when it
+// splits, the child boxes; S.perm then holds the chosen axis order.  E keys
+// per lane (64 E >= cnt).
+template <int E>
+__device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L, WaveBox &R)
+{
+    int slot[E];
+#pragma unroll
+    for (int h = 0; h < E; ++h) {
+        const int p = 64 * h + lane;
+        slot[h] = p < cnt ? S.perm[pb + p] : -1;
+    }
+    float best_c = INFINITY;
+    int best_w = INT32_MAX;  // axis * 64 E + left count
+    WaveBox bl = kEmptyBox, br = kEmptyBox;
+    int sorted[3][E];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        uint64_t key[E];
+#pragma unroll
+        for (int h = 0; h < E; ++h) {
+            const int s = slot[h];
+            const float c = s >= 0 ? 0.5f * (S.box[a][s] + S.box[3 + a][s]) : 0.f;
+            key[h] = s >= 0 ? ((uint64_t)((uint32_t)f2o(c) ^ 0x80000000u) << 32) | (uint32_t)s : kNoKey;
+        }
+        wave_sort<E>(key, lane);
+        WaveBox bx[E];
+#pragma unroll
+        for (int h = 0; h < E; ++h) {
+            const int s = key[h] == kNoKey ? -1 : (int)(uint32_t)key[h];
+            sorted[a][h] = s;
+            bx[h] = s >= 0 ? WaveBox{S.box[0][s], S.box[1][s], S.box[2][s], S.box[3][s], S.box[4][s], S.box[5][s]}
+                           : kEmptyBox;
+        }
+        // P: union of positions 0..p; Q: union of positions p..end
+        WaveBox P[E], Q[E], qfirst[E + 1];
+        WaveBox carry = kEmptyBox;
+#pragma unroll
+        for (int h = 0; h < E; ++h) {
+            WaveBox x = bx[h];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1)
+                x = box_union(x, box_up(x, d));
+            P[h] = box_union(x, carry);
+            carry = box_bcast(P[h], 63);
+        }
+        carry = kEmptyBox;
+        qfirst[E] = kEmptyBox;
+#pragma unroll
+        for (int h = E - 1; h >= 0; --h) {
+            WaveBox x = bx[h];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1)
+                x = box_union(x, box_down(x, d));
+            Q[h] = box_union(x, carry);
+            carry = box_bcast(Q[h], 0);
+            qfirst[h] = carry;
+        }
+#pragma unroll
+        for (int h = 0; h < E; ++h) {
+            WaveBox qn = box_down(Q[h], 1);  // Q at position p + 1
+            if (lane == 63)
+                qn = qfirst[h + 1];
+            const int k = 64 * h + lane + 1;  // left = positions 0 .. k - 1
+            if (k < cnt) {
+                const float c = half_area(P[h].lx, P[h].ly, P[h].lz, P[h].hx, P[h].hy, P[h].hz) * (float)k +
+                                half_area(qn.lx, qn.ly, qn.lz, qn.hx, qn.hy, qn.hz) * (float)(cnt - k);
+                const int w = a * 64 * E + k;
+                if (c < best_c || (c == best_c && w < best_w)) {
+                    best_c = c;
+                    best_w = w;
+                    bl = P[h];
+                    br = qn;
+                }
+            }
+        }
+    }
+    float bc = best_c;
+    int bw = best_w;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float oc = __shfl_xor(bc, o, 64);
+        const int ow = __shfl_xor(bw, o, 64);
+        if (oc < bc || (oc == bc && ow < bw)) {
+            bc = oc;
+            bw = ow;
+        }
+    }
+    if (!(bc < INFINITY))
+        return 0;
+    const int a = bw / (64 * E), k = bw % (64 * E);
+    const int src = (k - 1) & 63;  // the lane that costed this split (its own best)
+    L = box_bcast(bl, src);
+    R = box_bcast(br, src);
+#pragma unroll
+    for (int h = 0; h < E; ++h) {
+        const int p = 64 * h + lane;
+        if (p < cnt)
+            S.perm[pb + p] = a == 0 ? sorted[0][h] : (a == 1 ? sorted[1][h] : sorted[2][h]);
+    }
+    return k;
 }
 
 __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
@@ -337,7 +521,14 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 
             int mid = -1, best_axis = -1, best_k = -1;
             WaveBox L{}, R{};
-            if (usable && !forced) {
+            if (local && !forced) {
+                __syncthreads();
+                const int k = cnt <= 64 ? sweep_split<1>(S, b - b0, cnt, lane, L, R)
+                                        : sweep_split<kSweepE>(S, b - b0, cnt, lane, L, R);
+                __syncthreads();
+                if (k > 0)
+                    mid = b + k;
+            } else if (usable && !forced) {
                 for (int j = lane; j < 3 * kBins; j += 64) {
                     S.cnt[j] = 0;
                     S.lo[3 * j] = S.lo[3 * j + 1] = S.lo[3 * j + 2] = f2o(INFINITY);
@@ -483,8 +674,8 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                     nd.ch.y = leaf_ref(mid, nr);
             }
             // Children of 5..kMicro primitives are deferred to k_build_micro
-            // (their node id is assigned now, plus two reserved ids for the
-            // second level of a range above 8); larger ones are pushed, right
+            // (their node id is assigned now, followed by c - 2 reserved ids
+            // for the rest of their subtree); larger ones are pushed, right
             // first so that the left child is popped next.
             const int cb[2] = {b, mid}, ce[2] = {mid, en};
             for (int sd = 1; sd >= 0; --sd) {
@@ -493,7 +684,7 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                     continue;
                 if (c <= kMicro) {
                     const int cid = n_nodes;
-                    n_nodes += c > 2 * kLeafMax ? 3 : 1;
+                    n_nodes += c - 1;  // the most internal nodes c primitives can need
                     if (lane == 0) {
                         if (sd == 0)
                             nodes[id].ch.x = cid;
@@ -531,14 +722,15 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 
 // ---------------------------------------------------------------------------
 // K5b: ranges of 5..16 primitives deferred by k_build_sah.  One 16-lane group
-// per range (four per wavefront), one primitive per lane.  Full-sweep SAH over
-// the three centroid axes with both sides limited to `cap` primitives (8 for
-// the top split, so each side is a leaf or one more node with two leaves; 4
-// below): per axis the group sorts (centroid, position) with a bitonic
+// per range (four per wavefront), one primitive per lane, builds the whole
+// subtree: every node takes the full-sweep SAH split over the three centroid
+// axes (per axis the group sorts (centroid, triangle id) with a bitonic
 // network across its lanes, scans the sorted boxes from both ends and takes
-// the cheapest split (lowest axis, then fewest left primitives, on ties).
-// Centroids are compared through their ordered-integer image, a total order,
-// so the network is a permutation for any input.
+// the cheapest split: lowest axis, then fewest left primitives, on ties), and
+// every side above kLeafMax primitives becomes a node of its own.  The only
+// limit on a split is the depth bound (micro_cap).  Centroids are compared
+// through their ordered-integer image, a total order, so the network is a
+// permutation for any input.
 // ---------------------------------------------------------------------------
 constexpr int kMicroBlock = 256;
 constexpr int kGroup = 16;
@@ -584,13 +776,11 @@ __device__ __forceinline__ WaveBox box_shfl(const WaveBox &b, int src)
                    __shfl(b.hx, src, kGroup), __shfl(b.hy, src, kGroup), __shfl(b.hz, src, kGroup)};
 }
 
-constexpr WaveBox kEmptyBox{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-
 // Split of the `cnt` primitives that lanes [first, first + cnt) hold (lane r
 // holds box `bx`; positions outside are ignored), both sides at most `cap`.
 // On return lane q holds in `order` the lane whose primitive comes q-th along
 // the chosen axis (q < cnt), and the function returns the left count.
-__device__ __forceinline__ int group_split(const WaveBox &bx, int gl, int first, int cnt, int cap, int &order,
+__device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, int first, int cnt, int cap, int &order,
                                            WaveBox &L, WaveBox &R)
 {
     const bool mine = gl >= first && gl < first + cnt;
@@ -603,7 +793,7 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int gl, int first,
     for (int a = 0; a < 3; ++a) {
         const float c = a == 0 ? 0.5f * (bx.lx + bx.hx) : (a == 1 ? 0.5f * (bx.ly + bx.hy) : 0.5f * (bx.lz + bx.hz));
         int key = mine ? f2o(c) : INT32_MAX;
-        int id = mine ? gl : kGroup + gl;
+        int id = mine ? (pid << 4) | gl : 0x7ffffff0 | gl;  // ties: lower triangle id first
         group_sort(key, id, gl);
         orders[a] = id;
         // boxes in sorted order; identity beyond the range (every lane takes
@@ -666,6 +856,15 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int gl, int first,
     return best_k;
 }
 
+// Largest side a micro split at depth dd may leave: a side of s > kLeafMax
+// primitives becomes a node at depth dd + 1 whose subtree needs
+// levels_needed(s) more levels, and internal nodes stay within kMaxNodeDepth.
+__device__ __forceinline__ int micro_cap(int dd)
+{
+    const int m = kMaxNodeDepth - dd;
+    return m >= 2 ? kGroup : (kLeafMax << (m < 0 ? 0 : m));
+}
+
 __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
 {
     const int gl = threadIdx.x & (kGroup - 1);
@@ -695,54 +894,78 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
             const float4 lo4 = v.box_lo[base + pid], hi4 = v.box_hi[base + pid];
             bx = WaveBox{lo4.x, lo4.y, lo4.z, hi4.x, hi4.y, hi4.z};
         }
-        // top split: above 8 primitives each side may hold up to 8 (one more
-        // level); at most 8, both sides must be leaves (only one id reserved)
-        int order;
-        WaveBox L, R;
-        const int kb = group_split(bx, gl, 0, cnt, cnt > 2 * kLeafMax ? 2 * kLeafMax : kLeafMax, order, L, R);
-        // lane r now takes the primitive of sorted position r
-        const int src = order & (kGroup - 1);
-        const WaveBox sb = box_shfl(bx, src);
-        const int spid = __shfl(pid, src, kGroup);
-        if (gl == 0)
-            write_boxes(nodes[task.x], L, R);
-        const int sub[2] = {0, kb}, sc[2] = {kb, cnt - kb};
-        int ref[2];
-        int next = task.x + 1;  // reserved ids (ranges above 8 only)
+        // Depth-first over the subtree's nodes.  Pending nodes form a stack
+        // held across the group, entry s in lane s: (first | count << 8, node
+        // id, depth); at most three ranges of five or more fit in sixteen.
+        int s_range = 0, s_id = 0, s_depth = 0, sp = 0;
+        int next = task.x + 1;  // next reserved node id
+        int f = 0, c = cnt, id = task.x, dd = task.w;
+        while (true) {
+            int order;
+            WaveBox L, R;
+            const int k = group_split(bx, pid, gl, f, c, micro_cap(dd), order, L, R);
+            // lanes f .. f + c - 1 take the chosen axis order
+            const int src = __shfl(order, (gl - f) & (kGroup - 1), kGroup) & (kGroup - 1);
+            const WaveBox nb = box_shfl(bx, src);
+            const int np = __shfl(pid, src, kGroup);
+            if (gl >= f && gl < f + c) {
+                bx = nb;
+                pid = np;
+            }
+            const int cf[2] = {f, f + k}, cc[2] = {k, c - k};
+            int ref[2];
 #pragma unroll
-        for (int sd = 0; sd < 2; ++sd) {
-            if (sc[sd] <= kLeafMax) {
-                ref[sd] = leaf_ref(task.y + sub[sd], sc[sd]);
-                if (gl >= sub[sd] && gl < sub[sd] + sc[sd])
-                    prim[task.y + gl] = spid;
-            } else {
-                const int cid = next++;
-                ref[sd] = cid;
-                int ord2;
-                WaveBox L2, R2;
-                const int k2 = group_split(sb, gl, sub[sd], sc[sd], kLeafMax, ord2, L2, R2);
-                const int pid2 = __shfl(spid, ord2 & (kGroup - 1), kGroup);
-                if (gl < sc[sd])
-                    prim[task.y + sub[sd] + gl] = pid2;
-                if (gl == 0) {
-                    Node &cn = nodes[cid];
-                    write_boxes(cn, L2, R2);
-                    cn.ch = make_int4(leaf_ref(task.y + sub[sd], k2), leaf_ref(task.y + sub[sd] + k2, sc[sd] - k2),
-                                      task.x, task.w + 1);
+            for (int sd = 0; sd < 2; ++sd) {
+                if (cc[sd] <= kLeafMax) {
+                    ref[sd] = leaf_ref(task.y + cf[sd], cc[sd]);
+                } else {
+                    ref[sd] = next++;
+                    if (gl == 0) {
+                        nodes[ref[sd]].ch.z = id;
+                        nodes[ref[sd]].ch.w = dd + 1;
+                    }
                 }
             }
+            if (gl == 0) {
+                write_boxes(nodes[id], L, R);
+                nodes[id].ch.x = ref[0];
+                nodes[id].ch.y = ref[1];
+            }
+            // right first, so that the left child is built next
+#pragma unroll
+            for (int sd = 1; sd >= 0; --sd) {
+                if (cc[sd] > kLeafMax) {
+                    if (gl == sp) {
+                        s_range = cf[sd] | (cc[sd] << 8);
+                        s_id = ref[sd];
+                        s_depth = dd + 1;
+                    }
+                    ++sp;
+                }
+            }
+            if (sp == 0)
+                break;
+            --sp;
+            const int t = __shfl(s_range, sp, kGroup);
+            id = __shfl(s_id, sp, kGroup);
+            dd = __shfl(s_depth, sp, kGroup);
+            f = t & 255;
+            c = t >> 8;
         }
+        if (gl < cnt)
+            prim[task.y + gl] = pid;
         if (gl == 0) {
             // unused reserved ids: never referenced; a depth of -1 keeps refit away
-            if (cnt > 2 * kLeafMax)
-                for (int h = next; h < task.x + 3; ++h)
-                    nodes[h].ch = make_int4(0, 0, -1, -1);
-            nodes[task.x].ch.x = ref[0];
-            nodes[task.x].ch.y = ref[1];
+            for (int h = next; h < task.x + cnt - 1; ++h) {
+                Node &u = nodes[h];
+                u.xy0 = u.xy1 = u.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
+                u.ch = make_int4(0, 0, -1, -1);
+            }
         }
     }
 }
 
+// ---------------------------------------------------------------------------
 // K5a: where each environment's deferred ranges start in one list of all
 // tasks (exclusive scan of the per-environment counts; masked environments
 // count none); micro_off[n_envs] is the total.  One workgroup.

@@ -30,7 +30,7 @@ constexpr int64_t kMaxEnvTris = (int64_t)kLeafMax << (kMaxNodeDepth + 1);
 constexpr int kLevels = kMaxNodeDepth + 1;  // internal-node depths 0 .. kMaxNodeDepth
 static_assert(kMaxEnvTris <= (int64_t(1) << 28), "leaf references hold 28-bit record offsets");
 #ifndef RC_BINS
-#define RC_BINS 16
+#define RC_BINS 32
 #endif
 constexpr int kBins = RC_BINS;     // SAH bins per axis
 constexpr int kEmptyRoot = INT32_MIN;
