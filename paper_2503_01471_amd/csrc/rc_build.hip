@@ -727,10 +727,12 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 // axes (per axis the group sorts (centroid, triangle id) with a bitonic
 // network across its lanes, scans the sorted boxes from both ends and takes
 // the cheapest split: lowest axis, then fewest left primitives, on ties), and
-// every side above kLeafMax primitives becomes a node of its own.  The only
-// limit on a split is the depth bound (micro_cap).  Centroids are compared
-// through their ordered-integer image, a total order, so the network is a
-// permutation for any input.
+// every side above kLeafMax primitives becomes a node of its own.  A side of
+// 2..kLeafMax primitives becomes a leaf unless splitting it is cheaper under
+// the SAH with a node visit costing one triangle test (n A > A + A_L n_L +
+// A_R n_R, half areas).  The only limit on a split is the depth bound
+// (micro_cap).  Centroids are compared through their ordered-integer
+// image, a total order, so the network is a permutation for any input.
 // ---------------------------------------------------------------------------
 constexpr int kMicroBlock = 256;
 constexpr int kGroup = 16;
@@ -865,6 +867,51 @@ __device__ __forceinline__ int micro_cap(int dd)
     return m >= 2 ? kGroup : (kLeafMax << (m < 0 ? 0 : m));
 }
 
+// SAH leaf test for the c <= kLeafMax primitives of lanes first .. first + c - 1
+// at depth dd (call from every lane of the group): true if they stay a leaf.
+// The split cost is the cheapest over every two-way partition of the c
+// primitives (a superset of the sweep's candidates): lane j costs the
+// partition whose left side is the bit set of j + 1 (primitive c - 1 always
+// right, so each partition once).
+__device__ __forceinline__ bool micro_leaf(const WaveBox &bx, int gl, int first, int c, int dd)
+{
+    static_assert(kLeafMax <= 5, "2^(kLeafMax-1) - 1 partitions must fit in the 16-lane group");
+    if (c <= 1 || dd >= kMaxNodeDepth)  // a split would put a node below the depth bound
+        return true;
+    WaveBox B[kLeafMax];
+    WaveBox U = kEmptyBox;
+#pragma unroll
+    for (int i = 0; i < kLeafMax; ++i) {
+        const WaveBox t = box_shfl(bx, (first + i) & (kGroup - 1));
+        B[i] = i < c ? t : kEmptyBox;
+        U = box_union(U, B[i]);
+    }
+    const int m = gl + 1;
+    float cost = INFINITY;
+    if (m < (1 << (c - 1))) {
+        WaveBox l = kEmptyBox, r = kEmptyBox;
+        int nl = 0;
+#pragma unroll
+        for (int i = 0; i < kLeafMax; ++i) {
+            if (i < c) {
+                if ((m >> i) & 1) {
+                    l = box_union(l, B[i]);
+                    ++nl;
+                } else {
+                    r = box_union(r, B[i]);
+                }
+            }
+        }
+        cost = half_area(l.lx, l.ly, l.lz, l.hx, l.hy, l.hz) * (float)nl +
+               half_area(r.lx, r.ly, r.lz, r.hx, r.hy, r.hz) * (float)(c - nl);
+    }
+#pragma unroll
+    for (int d = 1; d < kGroup; d <<= 1)
+        cost = fminf(cost, __shfl_xor(cost, d, kGroup));
+    const float a = half_area(U.lx, U.ly, U.lz, U.hx, U.hy, U.hz);
+    return !((float)c * a > a + cost);
+}
+
 __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
 {
     const int gl = threadIdx.x & (kGroup - 1);
@@ -916,7 +963,7 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
             int ref[2];
 #pragma unroll
             for (int sd = 0; sd < 2; ++sd) {
-                if (cc[sd] <= kLeafMax) {
+                if (cc[sd] <= kLeafMax && micro_leaf(bx, gl, cf[sd], cc[sd], dd + 1)) {
                     ref[sd] = leaf_ref(task.y + cf[sd], cc[sd]);
                 } else {
                     ref[sd] = next++;
@@ -934,7 +981,7 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
             // right first, so that the left child is built next
 #pragma unroll
             for (int sd = 1; sd >= 0; --sd) {
-                if (cc[sd] > kLeafMax) {
+                if (ref[sd] >= 0) {
                     if (gl == sp) {
                         s_range = cf[sd] | (cc[sd] << 8);
                         s_id = ref[sd];
