@@ -54,8 +54,8 @@ static_assert(sizeof(TriRec) == 48, "record is three 16-byte fetches");
 __host__ __device__ inline int leaf_ref(int first, int count) { return ~((first << 3) | (count - 1)); }
 
 // First node slot of environment e (tri_off = env_tri_off[e]).  Each
-// environment gets n + n/4 + 2 slots for n triangles: internal nodes (< n)
-// plus the unused ids the builder may reserve for small ranges (< n/9).
+// environment gets n + n/4 + 2 slots for n triangles; its internal nodes and
+// the unused ids the builder reserves for small ranges together stay below n.
 __host__ __device__ inline int64_t node_base(int64_t tri_off, int e) { return tri_off + (tri_off >> 2) + 2 * (int64_t)e; }
 
 // ---------------------------------------------------------------------------

@@ -153,6 +153,27 @@ __device__ __forceinline__ bool slab_oct(const Ray &r, float lx, float hx, float
     }
 }
 
+// Raw buffer view of one environment's nodes or triangle records: the
+// traversal's loads take a 32-bit byte offset per lane instead of 64-bit
+// address arithmetic, and the hardware checks the range (a load past the
+// view's size returns zeros).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // descriptor dword 3 for untyped loads (gfx9 family)
+
+__device__ __forceinline__ Rsrc buffer_view(const void *p, int64_t bytes)
+{
+    const uint32_t n = bytes < 0xffffffffll ? (uint32_t)bytes : 0xffffffffu;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, kRsrcWord3);
+}
+__device__ __forceinline__ float4 ldf4(Rsrc r, uint32_t off)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ int4 ldi4(Rsrc r, uint32_t off)
+{
+    return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 // Octant shared by every active lane of the wavefront, else kMixed.
 __device__ __forceinline__ int wave_octant(const Ray &r)
 {
@@ -327,13 +348,13 @@ constexpr int kDone = INT32_MIN;  // never a leaf reference
 // Phase 1 of a round: walk internal nodes until this lane holds a leaf (or
 // has finished) and every other active lane does too.
 template <bool STATS, int OCT>
-__device__ __forceinline__ void descend(const Ray &r, const Node *__restrict__ nodes, int *stk, float tcap, int &sp,
-                                        int &ref, int &leaf, Stats &st)
+__device__ __forceinline__ void descend(const Ray &r, Rsrc nodes, int *stk, float tcap, int &sp, int &ref, int &leaf,
+                                        Stats &st)
 {
     while (ref >= 0) {
-        const Node *n = nodes + ref;
-        const float4 a = n->xy0, c = n->xy1, z = n->z01;
-        const int4 ch = n->ch;
+        const uint32_t off = (uint32_t)ref * (uint32_t)sizeof(Node);
+        const float4 a = ldf4(nodes, off), c = ldf4(nodes, off + 16), z = ldf4(nodes, off + 32);
+        const int4 ch = ldi4(nodes, off + 48);
         // Issue all four loads of the node before the first use: left alone,
         // the scheduler may start on the first box and send the last load
         // after waiting for the others, a second memory round trip per node.
@@ -363,8 +384,8 @@ __device__ __forceinline__ void descend(const Ray &r, const Node *__restrict__ n
 }
 
 template <bool STATS>
-__device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ nodes,
-                                         const TriRec *__restrict__ recs, int root, int *stk, Best &b, Stats &st)
+__device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, const TriRec *__restrict__ recs, int root,
+                                         int *stk, Best &b, Stats &st)
 {
     const int oct = wave_octant(r);
     int sp = 0;
@@ -390,10 +411,11 @@ __device__ __forceinline__ void traverse(const Ray &r, const Node *__restrict__ 
             const int code = ~leaf;
             const int first = code >> 3, cnt = (code & 7) + 1;
             for (int k = 0; k < cnt; ++k) {
-                const TriRec T = recs[first + k];
+                const uint32_t off = (uint32_t)(first + k) * (uint32_t)sizeof(TriRec);
+                const float4 ta = ldf4(rv, off), tb = ldf4(rv, off + 16), tc = ldf4(rv, off + 32);
                 if (STATS)
                     ++st.tri;
-                offer<STATS>(r, recs, first + k, T.a, T.b, T.c, b, st);
+                offer<STATS>(r, recs, first + k, ta, tb, tc, b, st);
             }
             if (ref < 0 && ref != kDone) {
                 leaf = ref;
@@ -474,12 +496,14 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     Ray r;
     gen_ray(se, t, row, col, r);
     Best b{r.tf, r.tf, -1, -1, false, 0.0};
-    const int64_t base = sc.env_tri_off[t.env];
-    const Node *nodes = sc.nodes + node_base(base, t.env);
+    const int64_t base = sc.env_tri_off[t.env], end = sc.env_tri_off[t.env + 1];
+    const int64_t nb = node_base(base, t.env);
+    const Rsrc nodes = buffer_view(sc.nodes + nb, (node_base(end, t.env + 1) - nb) * (int64_t)sizeof(Node));
     const TriRec *recs = sc.recs + base;
+    const Rsrc rv = buffer_view(recs, (end - base) * (int64_t)sizeof(TriRec));
     const int root = sc.env_root[t.env];
     if (root != kEmptyRoot)
-        traverse<STATS>(r, nodes, recs, root, stk, b, st);
+        traverse<STATS>(r, nodes, rv, recs, root, stk, b, st);
     // The output position is recomputed here from the lane: the empty asm
     // hides that it equals the one above, so the compiler does not keep
     // address arithmetic alive (spilled) across the traversal.
