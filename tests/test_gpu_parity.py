@@ -376,6 +376,47 @@ def test_edge_cases():
     _check_scene(scene, bvh_envs=(1, 2, 4))
 
 
+def test_builder_degenerate_geometry():
+    """Inputs that drive the BVH builder's corner paths, each checked for a
+    valid BVH (exact expanded bounds, coverage, depth bound) and oracle
+    parity: 300 copies of one triangle (every centroid equal, so every split
+    cost ties and the depth bound forces median splits), slivers at
+    geometrically growing x (very uneven SAH splits), zero-area triangles
+    mixed with ordinary ones, and 17 / 129 triangles (one above the small-range
+    and local-sweep thresholds)."""
+    _need_gpu()
+    rng = np.random.default_rng(11)
+    v1 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    same = (v1, np.zeros((300, 3), np.int32) + np.array([0, 1, 2], np.int32))
+    xs = (1.35 ** np.arange(60)).astype(np.float32) * 0.01
+    sv = np.concatenate([np.stack([[x, -1, -1], [x, 1, -1], [x + 1e-3, 0, 1]]) for x in xs]).astype(np.float32)
+    slivers = (sv, np.arange(3 * len(xs), dtype=np.int32).reshape(-1, 3))
+    pts = rng.uniform(-1, 1, size=(90, 3)).astype(np.float32)
+    tris = np.concatenate([rng.integers(0, 90, size=(60, 3)),              # ordinary
+                           np.repeat(rng.integers(0, 90, size=(15, 1)), 3, 1),  # one point repeated
+                           np.stack([np.arange(15), np.arange(15) + 15, np.arange(15)], 1)])  # a repeated vertex
+    mixed = (pts, tris.astype(np.int32))
+
+    def soup(n):
+        c = rng.uniform(-2, 2, size=(n, 1, 3))
+        return ((c + rng.normal(scale=0.3, size=(n, 3, 3))).reshape(-1, 3).astype(np.float32),
+                np.arange(3 * n, dtype=np.int32).reshape(-1, 3))
+
+    sensors = [S.pinhole(24, 16, 90.0, 0.05, 400.0)]
+    I = lambda t: S.affine(np.eye(3), t)
+    z3 = (0.0, 0.0, 0.0)
+    front = S.sensor_pose(S.rot_zyx(0.0, 0.0), (-3.0, 0.2, 0.1))
+    along = S.sensor_pose(S.rot_zyx(0.0, 0.0), (-1.0, 0.05, 0.0))
+    above = S.sensor_pose(S.rot_zyx(0.0, 89 * S.DEG), (0.3, 0.25, 0.6))
+    envs = [([(0, 1, I(z3), 0, z3)], [(0, above)]),
+            ([(1, 2, I(z3), 0, z3)], [(0, along)]),
+            ([(2, 3, I(z3), 0, z3)], [(0, front)]),
+            ([(3, 4, I(z3), 0, z3)], [(0, front)]),
+            ([(4, 5, I(z3), 0, z3)], [(0, front)])]
+    scene = S.custom_scene([same, slivers, mixed, soup(17), soup(129)], envs, sensors)
+    _check_scene(scene, bvh_envs=(0, 1, 2, 3, 4))
+
+
 def test_api_errors():
     """Argument and state errors are reported as status codes before any work."""
     from paper_2503_01471_amd import rc
