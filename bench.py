@@ -164,6 +164,21 @@ def bench_step(args):
     ms_rebuild_step = timed(rebuild_step, max(2, args.steps // 2))
     log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, transform+refit {ms_refit:.3f} ms; reset: build "
         f"{ms_build:.3f} ms, step with rebuild {ms_rebuild_step:.3f} ms")
+    # the linear BVH builder (faster build, slower trees); the SAH trees are restored afterwards
+
+    def rebuild_step_lbvh():
+        rc.rc_set_sensor_poses(ctx, R.sensor_T)
+        rc.rc_set_instance_poses(ctx, R.inst_T)
+        rc.rc_build(ctx, rc.RC_BUILD_LBVH)
+        render()
+
+    ms_build_lbvh = timed(lambda: rc.rc_build(ctx, rc.RC_BUILD_LBVH), max(2, args.steps // 2))
+    ms_render_lbvh = timed(render, args.steps)
+    ms_rebuild_step_lbvh = timed(rebuild_step_lbvh, max(2, args.steps // 2))
+    rc.rc_build(ctx)
+    torch.cuda.synchronize()
+    log(f"lbvh: build {ms_build_lbvh:.3f} ms, render {ms_render_lbvh:.3f} ms, step with rebuild "
+        f"{ms_rebuild_step_lbvh:.3f} ms")
     # further data types from the same hits (Sec. III-D): normal, barycentrics, sensor-frame point and
     # vertex ids derived by a second pass from the winner ids; stereo shadows by segment tests
     xo = R.alloc(depth=True, seg=True, tri=True, normal=True, bary=True, point=True, vert=True, shadow=stereo)
@@ -237,7 +252,11 @@ def bench_step(args):
         "transform_refit_ms": ms_refit,
         "reset": {"sah_build_ms": ms_build, "step_with_rebuild_ms": ms_rebuild_step,
                   "step_with_rebuild_Mrays_s": rays / ms_rebuild_step / 1e3,
-                  "env_steps_per_s": n_envs / (ms_rebuild_step * 1e-3)},
+                  "env_steps_per_s": n_envs / (ms_rebuild_step * 1e-3),
+                  "lbvh": {"build_ms": ms_build_lbvh, "render_ms_on_lbvh_trees": ms_render_lbvh,
+                           "step_with_rebuild_ms": ms_rebuild_step_lbvh,
+                           "step_with_rebuild_Mrays_s": rays / ms_rebuild_step_lbvh / 1e3,
+                           "env_steps_per_s": n_envs / (ms_rebuild_step_lbvh * 1e-3)}},
         "plain": plain,
         "further_outputs": further,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,

@@ -167,10 +167,18 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /* ------------------------------------------------------------------------ */
 /* Acceleration structure (Sec. III-D: a BVH over the transformed mesh of    */
 /* each environment).  rc_build transforms every instance and builds one     */
-/* BVH per environment (builder RC_BUILD_SAH: binned surface-area           */
-/* heuristic, one wavefront per environment).  rc_refit re-transforms the    */
-/* dynamic instances and recomputes the bounds bottom-up on the fixed        */
-/* topology.  Both are asynchronous on `stream`.                             */
+/* BVH per environment with `builder`:                                       */
+/*   RC_BUILD_SAH   surface-area heuristic (binned splits for large nodes,   */
+/*                  exact sweeps below), one wavefront per environment; the  */
+/*                  faster trees to render.                                  */
+/*   RC_BUILD_LBVH  linear BVH (Morton order, radix tree as in Karras 2012),  */
+/*                  one workgroup per environment of 5..8192 triangles; the  */
+/*                  faster build.  Other environments, and any whose tree    */
+/*                  would exceed the depth bound, get the SAH build.         */
+/* Every builder gives the same render results (the nearest hit is exact).  */
+/* rc_refit re-transforms the dynamic instances and recomputes the bounds    */
+/* bottom-up on the fixed topology.  Both are asynchronous on `stream`.      */
+/* An unknown builder is RC_E_INVALID.                                       */
 /* d_env_mask: NULL (every environment) or a caller DEVICE uint8[n_envs],    */
 /* read on `stream`; environments whose byte is 0 are left exactly as they  */
 /* are (world triangles, BVH, records), so e.g. the environments reset by a  */
@@ -178,6 +186,7 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /* build first (RC_E_STATE).                                                 */
 /* ------------------------------------------------------------------------ */
 #define RC_BUILD_SAH 0
+#define RC_BUILD_LBVH 1
 rc_status rc_build(rc_context *ctx, const uint8_t *d_env_mask, int32_t builder, void *stream);
 rc_status rc_refit(rc_context *ctx, const uint8_t *d_env_mask, void *stream);
 

@@ -438,6 +438,7 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->level_nodes, 4 * (size_t)(node_base(N, n_envs) + 16)));
     RC_TRY(c->pool.alloc(sc->level_off, 4 * (size_t)n_envs * (kLevels + 1)));
     RC_TRY(c->pool.alloc(sc->micro_off, 8 * ((size_t)n_envs + 1)));
+    RC_TRY(c->pool.alloc(sc->sah_mask, (size_t)n_envs + 16));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);
@@ -621,7 +622,7 @@ rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, vo
 {
     RC_CHECK(c, "NULL context");
     RC_TRY(busy_check(c));
-    RC_CHECK(builder == RC_BUILD_SAH, "unknown builder %d", builder);
+    RC_CHECK(builder == RC_BUILD_SAH || builder == RC_BUILD_LBVH, "unknown builder %d", builder);
     if (!c->scene || !c->scene->poses_set)
         return fail(RC_E_STATE, "rc_build needs a scene and instance poses");
     Scene &sc = *c->scene;
@@ -632,7 +633,10 @@ rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, vo
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
     RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
-    RC_HIP(launch_build_sah(v, st));
+    if (builder == RC_BUILD_LBVH)
+        RC_HIP(launch_build_lbvh(v, sc.sah_mask.as<uint8_t>(), st));
+    else
+        RC_HIP(launch_build_sah(v, st));
     sc.built = true;
     return RC_OK;
 }

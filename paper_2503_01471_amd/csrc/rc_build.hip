@@ -1188,6 +1188,197 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(BuildView v)
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// ---------------------------------------------------------------------------
+// K6: linear BVH (builder RC_BUILD_LBVH), one workgroup per environment of
+// kLeafMax + 1 .. kLbvhMax triangles.  Centroids are quantised to 10 bits per
+// axis inside the environment's centroid bounds and bit-interleaved (Morton
+// order), and the (code, triangle id) keys are sorted in LDS.  Over the sorted
+// keys the radix tree of Karras (2012) has one internal node per adjacent key
+// pair: node i finds the far end of its key range and the position where the
+// range's highest differing bit changes, both by binary search on common
+// prefix lengths.  A range of at most kLeafMax keys is a leaf, node ids are
+// the radix-tree indices (those absorbed into leaves stay unused), and each
+// kept node's depth is the length of its parent chain.  Bounds are left to the
+// refit.  An environment outside that size range, or whose tree would be
+// deeper than kMaxNodeDepth, is flagged in sah_mask for the SAH kernels.
+// ---------------------------------------------------------------------------
+constexpr int kLbvhMax = 8192;  // 64 KB of sort keys + 16 KB of parent links in LDS (40 KB up to 4096)
+static_assert(kLbvhMax <= 32768, "parent links are 16-bit");
+
+__device__ __forceinline__ uint32_t spread3(uint32_t x)  // bit b of a 10-bit value -> bit 3b
+{
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t quant10(float c, float lo, float scale)
+{
+    const float q = (c - lo) * scale;
+    return q >= 1023.0f ? 1023u : (q > 0.0f ? (uint32_t)q : 0u);
+}
+
+// One instance per LDS footprint: environments of LO + 1 .. MAXN triangles,
+// NT threads (the larger footprint fits one workgroup per CU, so it takes
+// more threads).  The FIRST instance also settles every environment no
+// instance takes.
+template <int MAXN, int LO, bool FIRST, int NT>
+__global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
+{
+    static_assert(MAXN <= kLbvhMax, "above the LBVH size limit");
+    __shared__ uint64_t key[MAXN];
+    __shared__ short par[MAXN];  // parent of each kept node (-2: absorbed), fits 16 bits
+    __shared__ float red[6][NT / 64];
+    __shared__ int s_depth;
+    const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = v.env_tri_off[e];
+    const int n = (int)(v.env_tri_off[e + 1] - base);
+    const bool want = !masked_out(v, e);
+    if (!want || n <= LO || n > MAXN) {
+        const bool lbvh_any = want && n > kLeafMax && n <= kLbvhMax;
+        if (FIRST && tid == 0 && !lbvh_any)
+            sah_mask[e] = want ? 1 : 0;
+        return;
+    }
+    const float4 *blo = v.box_lo + base, *bhi = v.box_hi + base;
+    // centroid bounds
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = tid; i < n; i += NT) {
+        const float4 a = blo[i], b = bhi[i];
+        const float c[3] = {0.5f * (a.x + b.x), 0.5f * (a.y + b.y), 0.5f * (a.z + b.z)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], c[k]);
+            hi[k] = fmaxf(hi[k], c[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = wave_min(lo[k]);
+        hi[k] = wave_max(hi[k]);
+        if (lane == 0) {
+            red[k][wave] = lo[k];
+            red[3 + k][wave] = hi[k];
+        }
+    }
+    if (tid == 0)
+        s_depth = 0;
+    __syncthreads();
+    float scale[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float a = red[k][0], b = red[3 + k][0];
+        for (int w = 1; w < NT / 64; ++w) {
+            a = fminf(a, red[k][w]);
+            b = fmaxf(b, red[3 + k][w]);
+        }
+        lo[k] = a;
+        scale[k] = b > a ? 1024.0f / (b - a) : 0.0f;
+    }
+    // keys, padded to a power of two with the largest key
+    int P = 8;
+    while (P < n)
+        P <<= 1;
+    for (int i = tid; i < P; i += NT) {
+        uint64_t k64 = ~0ull;
+        if (i < n) {
+            const float4 a = blo[i], b = bhi[i];
+            const uint32_t code = (spread3(quant10(0.5f * (a.x + b.x), lo[0], scale[0])) << 2) |
+                                  (spread3(quant10(0.5f * (a.y + b.y), lo[1], scale[1])) << 1) |
+                                  spread3(quant10(0.5f * (a.z + b.z), lo[2], scale[2]));
+            k64 = ((uint64_t)code << 32) | (uint32_t)i;
+        }
+        key[i] = k64;
+        par[i] = 0;
+    }
+    __syncthreads();
+    // bitonic sort: pair (i, i + j), i with bit j clear, ascending where bit k of i is clear
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = tid; t < P / 2; t += NT) {
+                const int i = 2 * j * (t / j) + (t % j), m = i + j;
+                const bool up = (i & k) == 0;
+                const uint64_t a = key[i], b = key[m];
+                if (up ? b < a : a < b) {
+                    key[i] = b;
+                    key[m] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int32_t *prim = v.prim + base;
+    for (int i = tid; i < n; i += NT)
+        prim[i] = (int)(uint32_t)key[i];
+    // radix tree; delta = common prefix length of two keys, -1 outside the keys
+    Node *nodes = v.nodes + node_base(base, e);
+    auto delta = [&](int a, int b) -> int { return (b < 0 || b >= n) ? -1 : __clzll(key[a] ^ key[b]); };
+    for (int i = tid; i < n - 1; i += NT) {
+        const int d = delta(i, i + 1) > delta(i, i - 1) ? 1 : -1;
+        const int dmin = delta(i, i - d);
+        int lmax = 2;
+        while (delta(i, i + lmax * d) > dmin)
+            lmax <<= 1;
+        int l = 0;
+        for (int t = lmax >> 1; t > 0; t >>= 1)
+            if (delta(i, i + (l + t) * d) > dmin)
+                l += t;
+        const int j = i + l * d;
+        const int dnode = delta(i, j);
+        int s = 0, t = l;
+        do {
+            t = (t + 1) >> 1;
+            if (delta(i, i + (s + t) * d) > dnode)
+                s += t;
+        } while (t > 1);
+        const int g = i + s * d + (d < 0 ? -1 : 0);  // the left part ends at key g
+        const int first = i < j ? i : j, last = i < j ? j : i;
+        Node &nd = nodes[i];
+        if (last - first + 1 <= kLeafMax) {  // absorbed into its parent's leaf
+            nd.xy0 = nd.xy1 = nd.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
+            nd.ch = make_int4(0, 0, -1, -1);
+            par[i] = -2;  // no other thread writes par[i]: the parent links kept children only
+            continue;
+        }
+        const int nl = g - first + 1, nr = last - g;
+        nd.ch.x = nl > kLeafMax ? g : leaf_ref(first, nl);
+        nd.ch.y = nr > kLeafMax ? g + 1 : leaf_ref(g + 1, nr);
+        if (nl > kLeafMax)
+            par[g] = i;
+        if (nr > kLeafMax)
+            par[g + 1] = i;
+    }
+    __syncthreads();
+    // depths from the parent chains (node 0 is the root)
+    int dmax = 0;
+    for (int i = tid; i < n - 1; i += NT) {
+        if (par[i] == -2)
+            continue;  // unused id
+        int dep = 0;
+        for (int p = i; p > 0 && dep <= kLevels; p = par[p])
+            ++dep;
+        Node &nd = nodes[i];
+        nd.ch.z = i == 0 ? -1 : par[i];
+        nd.ch.w = dep;
+        dmax = dep > dmax ? dep : dmax;
+    }
+    atomicMax(&s_depth, dmax);
+    __syncthreads();
+    if (tid == 0) {
+        if (s_depth > kMaxNodeDepth) {  // too deep for the traversal stack: SAH instead
+            sah_mask[e] = 1;
+        } else {
+            sah_mask[e] = 0;
+            v.env_root[e] = 0;
+            v.env_nodes[e] = n - 1;
+            v.env_micro[e] = 0;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t n, bool to_recs, hipStream_t st)
@@ -1247,6 +1438,48 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
     if ((err = hipGetLastError()) != hipSuccess)
         return err;
     hipLaunchKernelGGL(k_level_order, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_lbvh(const BuildView &v, uint8_t *sah_mask, hipStream_t st)
+{
+    if (v.n_envs == 0)
+        return hipSuccess;
+    if (v.n_tris > 0) {
+        hipLaunchKernelGGL(k_bounds, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess)
+            return err;
+    }
+    hipLaunchKernelGGL((k_lbvh<kLbvhMax / 2, kLeafMax, true, 256>), dim3(v.n_envs), dim3(256), 0, st, v, sah_mask);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return err;
+    hipLaunchKernelGGL((k_lbvh<kLbvhMax, kLbvhMax / 2, false, 1024>), dim3(v.n_envs), dim3(1024), 0, st, v, sah_mask);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    // the SAH kernels build exactly the environments flagged above
+    BuildView vs = v;
+    vs.env_mask = sah_mask;
+    hipLaunchKernelGGL(k_build_sah, dim3(v.n_envs), dim3(64), 0, st, vs);
+    if ((err = hipGetLastError()) != hipSuccess || v.n_tris == 0)
+        return err;
+    hipLaunchKernelGGL(k_micro_scan, dim3(1), dim3(kScanBlock), 0, st, vs);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    const int64_t groups = v.n_tris / 5 + 1;
+    const int64_t blocks = (groups * kGroup + kMicroBlock - 1) / kMicroBlock;
+    hipLaunchKernelGGL(k_build_micro, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kMicroBlock), 0, st, vs);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    // every requested environment: records in leaf order, level lists, bounds
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(k_level_order, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(k_refit, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
     return hipGetLastError();
 }
 

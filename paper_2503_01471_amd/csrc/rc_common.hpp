@@ -154,6 +154,7 @@ hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const 
                        const int32_t *d_step, float dt, float *T, hipStream_t st);
 hipError_t launch_bump(int32_t *d_step, hipStream_t st);
 hipError_t launch_build_sah(const BuildView &v, hipStream_t st);
+hipError_t launch_build_lbvh(const BuildView &v, uint8_t *sah_mask, hipStream_t st);
 hipError_t launch_refit(const BuildView &v, hipStream_t st);
 
 hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const OutView &o, int64_t item_begin,

@@ -57,8 +57,8 @@ class Renderer:
             m[ids] = 1
         return m
 
-    def build(self, stream=None, envs=None):
-        rc.rc_build(self.ctx, rc.RC_BUILD_SAH, stream, env_mask=self._mask(envs))
+    def build(self, stream=None, envs=None, builder=rc.RC_BUILD_SAH):
+        rc.rc_build(self.ctx, builder, stream, env_mask=self._mask(envs))
 
     def refit(self, stream=None, envs=None):
         rc.rc_refit(self.ctx, stream, env_mask=self._mask(envs))
