@@ -268,8 +268,9 @@ def bench_step(args):
                      "byte_model": "canonical full-sweep SAH traversal: 32 B/box test + 40 B/tri test + 8 B out",
                      "l2_hit_rate": None if traffic is None else traffic.get("l2_hit_rate"),
                      "valu_issue_frac": None if traffic is None else traffic.get("issue", {}).get("valu_issue_frac"),
-                     "note": "B_alg bytes are mostly served from L2 / Infinity Cache; the measured binding resource "
-                             "is VALU issue (valu_issue_frac, from the committed SQ counter profile)"},
+                     "note": "B_alg bytes are mostly served from L2 / Infinity Cache; what binds is the dependent "
+                             "node and triangle fetch latency together with VALU issue (valu_issue_frac, from the "
+                             "committed SQ counter profile)"},
         "cpu_baseline": None,
     }
     R.close()
