@@ -608,7 +608,70 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                         bw = ow;
                     }
                 }
-                if (bc < INFINITY) {
+                // Cuts in the range's own order: it is ascending triangle id order (every
+                // split above local mode is a stable partition of the identity order), and
+                // mesh order is spatially coherent, so these cuts separate whole objects and
+                // clusters of equal centroids that no binned plane can split.  Forward pass:
+                // half-area of each prefix (kept in tmp, which the partition below reuses only
+                // afterwards); backward pass: suffix boxes and the cost of every cut.
+                float ic = INFINITY;
+                int ik = 0;
+                {
+                    float *parea = reinterpret_cast<float *>(tmp);
+                    WaveBox carry = kEmptyBox;
+                    for (int c0 = b; c0 < en; c0 += 64) {
+                        const int i = c0 + lane;
+                        WaveBox x = kEmptyBox;
+                        if (i < en)
+                            box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1)
+                            x = box_union(x, box_up(x, d));
+                        x = box_union(x, carry);
+                        if (i < en)
+                            parea[i] = half_area(x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+                        carry = box_bcast(x, 63);
+                    }
+                    __syncthreads();
+                    carry = kEmptyBox;  // union of the positions after the current chunk
+                    for (int c0 = b + ((cnt - 1) & ~63); c0 >= b; c0 -= 64) {
+                        const int i = c0 + lane;
+                        WaveBox x = kEmptyBox;
+                        if (i < en)
+                            box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1)
+                            x = box_union(x, box_down(x, d));
+                        const WaveBox suf = box_union(x, carry);  // positions i .. en - 1
+                        WaveBox rn = box_down(suf, 1);             // positions i + 1 .. en - 1
+                        if (lane == 63)
+                            rn = carry;
+                        if (i < en - 1) {
+                            const int k = i - b + 1;
+                            const float c = parea[i] * (float)k + half_area(rn.lx, rn.ly, rn.lz, rn.hx, rn.hy, rn.hz) * (float)(cnt - k);
+                            if (c < ic || (c == ic && k < ik)) {
+                                ic = c;
+                                ik = k;
+                            }
+                        }
+                        carry = box_bcast(suf, 0);
+                    }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        const float oc = __shfl_xor(ic, o, 64);
+                        const int ok = __shfl_xor(ik, o, 64);
+                        if (oc < ic || (oc == ic && ok < ik)) {
+                            ic = oc;
+                            ik = ok;
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (ic < bc) {  // cut in id order: both sides are already contiguous
+                    mid = b + ik;
+                    L = reduce_range(b, mid);
+                    R = reduce_range(mid, en);
+                } else if (bc < INFINITY) {
                     best_axis = bw / (kBins - 1);
                     best_k = bw % (kBins - 1);
                     const int src = bw & 63;  // the lane that evaluated plane bw
