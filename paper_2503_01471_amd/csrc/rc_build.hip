@@ -202,9 +202,10 @@ __device__ __forceinline__ void write_boxes(Node &nd, const WaveBox &L, const Wa
 // network (kSweepE keys per lane, key h of lane l at index 64 h + l).  Slots
 // are numbered in the order the primitives had when the subtree entered LDS,
 // which is ascending triangle id (every earlier split is a stable partition of
-// the identity order), so equal centroids fall in id order.  Then both ends
-// are scanned for the union boxes, every split position is costed, and the
-// cheapest wins (lowest axis, then fewest left primitives, on ties).
+// the identity order), so equal centroids fall in id order; a fourth order is
+// the slot order alone (mesh order).  Then both ends are scanned for the union
+// boxes, every split position is costed, and the cheapest wins (lowest order,
+// then fewest left primitives, on ties).
 // ---------------------------------------------------------------------------
 constexpr int kSweepE = kSmall / 64;
 static_assert(kSmall % 64 == 0 && (kSweepE & (kSweepE - 1)) == 0, "kSmall must be 64 times a power of two");
@@ -287,16 +288,17 @@ __device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L
         slot[h] = p < cnt ? S.perm[pb + p] : -1;
     }
     float best_c = INFINITY;
-    int best_w = INT32_MAX;  // axis * 64 E + left count
+    int best_w = INT32_MAX;  // order * 64 E + left count
     WaveBox bl = kEmptyBox, br = kEmptyBox;
-    int sorted[3][E];
+    int sorted[4][E];
+    // orders 0..2: centroid along x, y, z; order 3: slot (= triangle id) order alone
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 4; ++a) {
         uint64_t key[E];
 #pragma unroll
         for (int h = 0; h < E; ++h) {
             const int s = slot[h];
-            const float c = s >= 0 ? 0.5f * (S.box[a][s] + S.box[3 + a][s]) : 0.f;
+            const float c = (s >= 0 && a < 3) ? 0.5f * (S.box[a][s] + S.box[3 + a][s]) : 0.f;
             key[h] = s >= 0 ? ((uint64_t)((uint32_t)f2o(c) ^ 0x80000000u) << 32) | (uint32_t)s : kNoKey;
         }
         wave_sort<E>(key, lane);
@@ -372,7 +374,7 @@ __device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L
     for (int h = 0; h < E; ++h) {
         const int p = 64 * h + lane;
         if (p < cnt)
-            S.perm[pb + p] = a == 0 ? sorted[0][h] : (a == 1 ? sorted[1][h] : sorted[2][h]);
+            S.perm[pb + p] = a == 0 ? sorted[0][h] : (a == 1 ? sorted[1][h] : (a == 2 ? sorted[2][h] : sorted[3][h]));
     }
     return k;
 }
@@ -787,7 +789,8 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 // K5b: ranges of 5..16 primitives deferred by k_build_sah.  One 16-lane group
 // per range (four per wavefront), one primitive per lane, builds the whole
 // subtree: every node takes the full-sweep SAH split over the three centroid
-// axes (per axis the group sorts (centroid, triangle id) with a bitonic
+// axes and the triangle id order (per order the group sorts (centroid,
+// triangle id), the centroid left out for the id order, with a bitonic
 // network across its lanes, scans the sorted boxes from both ends and takes
 // the cheapest split: lowest axis, then fewest left primitives, on ties), and
 // every side above kLeafMax primitives becomes a node of its own.  A side of
@@ -853,10 +856,12 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
     const int kmax = cap < cnt - 1 ? cap : cnt - 1;
     float best_c = INFINITY;
     int best_k = cnt / 2, best_a = 0;  // no finite cost: middle split along the first axis
-    int orders[3];
+    int orders[4];
+    // orders 0..2: centroid along x, y, z; order 3: triangle id alone (mesh order)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float c = a == 0 ? 0.5f * (bx.lx + bx.hx) : (a == 1 ? 0.5f * (bx.ly + bx.hy) : 0.5f * (bx.lz + bx.hz));
+    for (int a = 0; a < 4; ++a) {
+        const float c = a == 0 ? 0.5f * (bx.lx + bx.hx)
+                               : (a == 1 ? 0.5f * (bx.ly + bx.hy) : (a == 2 ? 0.5f * (bx.lz + bx.hz) : 0.f));
         int key = mine ? f2o(c) : INT32_MAX;
         int id = mine ? (pid << 4) | gl : 0x7ffffff0 | gl;  // ties: lower triangle id first
         group_sort(key, id, gl);
@@ -912,7 +917,7 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
             best_a = a;
         }
     }
-    order = best_a == 0 ? orders[0] : (best_a == 1 ? orders[1] : orders[2]);
+    order = best_a == 0 ? orders[0] : (best_a == 1 ? orders[1] : (best_a == 2 ? orders[2] : orders[3]));
     // child boxes of the chosen split
     const WaveBox got = box_shfl(bx, order & (kGroup - 1));
     const WaveBox s = gl < cnt ? got : kEmptyBox;
