@@ -495,29 +495,50 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                 nodes[id].ch.z = parent;
                 nodes[id].ch.w = depth;
             }
-            // centroid bounds (centroid = midpoint of the primitive's box)
-            float cl0 = INFINITY, cl1 = INFINITY, cl2 = INFINITY, ch0 = -INFINITY, ch1 = -INFINITY, ch2 = -INFINITY;
-#pragma unroll 4
-            for (int i = b + lane; i < en; i += 64) {
-                float a0, a1, a2, c0, c1, c2;
-                box_at(i, a0, a1, a2, c0, c1, c2);
-                const float x = 0.5f * (a0 + c0), y = 0.5f * (a1 + c1), z = 0.5f * (a2 + c2);
-                cl0 = fminf(cl0, x);
-                cl1 = fminf(cl1, y);
-                cl2 = fminf(cl2, z);
-                ch0 = fmaxf(ch0, x);
-                ch1 = fmaxf(ch1, y);
-                ch2 = fmaxf(ch2, z);
-            }
-            const float cmin[3] = {wave_min(cl0), wave_min(cl1), wave_min(cl2)};
-            const float cmax[3] = {wave_max(ch0), wave_max(ch1), wave_max(ch2)};
-            float scale[3];
+            // Nodes above kSmall primitives, one pass: centroid bounds for the bins
+            // (centroid = midpoint of the primitive's box) and the half-area of every
+            // prefix of the range in its own order, for the cuts in that order (kept in
+            // tmp, which the partition below reuses only afterwards).  The range is in
+            // ascending triangle id order (every split above local mode is a stable
+            // partition of the identity order) and mesh order is spatially coherent,
+            // so those cuts separate whole objects and clusters of equal centroids
+            // that no binned plane can split.
+            float cmin[3] = {0.f, 0.f, 0.f}, scale[3] = {0.f, 0.f, 0.f};
             bool usable = false;
+            float *parea = reinterpret_cast<float *>(tmp);
+            if (!local) {
+                float cl0 = INFINITY, cl1 = INFINITY, cl2 = INFINITY, ch0 = -INFINITY, ch1 = -INFINITY, ch2 = -INFINITY;
+                WaveBox carry = kEmptyBox;
+                for (int c0 = b; c0 < en; c0 += 64) {
+                    const int i = c0 + lane;
+                    WaveBox x = kEmptyBox;
+                    if (i < en) {
+                        box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+                        const float cx = 0.5f * (x.lx + x.hx), cy = 0.5f * (x.ly + x.hy), cz = 0.5f * (x.lz + x.hz);
+                        cl0 = fminf(cl0, cx);
+                        cl1 = fminf(cl1, cy);
+                        cl2 = fminf(cl2, cz);
+                        ch0 = fmaxf(ch0, cx);
+                        ch1 = fmaxf(ch1, cy);
+                        ch2 = fmaxf(ch2, cz);
+                    }
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float ext = cmax[a] - cmin[a];
-                scale[a] = ext > 0.f ? (float)kBins / ext : 0.f;
-                usable |= ext > 0.f;
+                    for (int d = 1; d < 64; d <<= 1)
+                        x = box_union(x, box_up(x, d));
+                    x = box_union(x, carry);
+                    if (i < en)
+                        parea[i] = half_area(x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+                    carry = box_bcast(x, 63);
+                }
+                const float mn[3] = {wave_min(cl0), wave_min(cl1), wave_min(cl2)};
+                const float mx[3] = {wave_max(ch0), wave_max(ch1), wave_max(ch2)};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float ext = mx[a] - mn[a];
+                    cmin[a] = mn[a];
+                    scale[a] = ext > 0.f ? (float)kBins / ext : 0.f;
+                    usable |= ext > 0.f;
+                }
             }
             const bool forced = depth + levels_needed(cnt) - 1 >= kMaxNodeDepth;
 
@@ -536,24 +557,58 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                     S.lo[3 * j] = S.lo[3 * j + 1] = S.lo[3 * j + 2] = f2o(INFINITY);
                     S.hi[3 * j] = S.hi[3 * j + 1] = S.hi[3 * j + 2] = f2o(-INFINITY);
                 }
-                __syncthreads();
-#pragma unroll 4
-                for (int i = b + lane; i < en; i += 64) {
-                    float a0, a1, a2, c0, c1, c2;
-                    box_at(i, a0, a1, a2, c0, c1, c2);
-                    const float cc[3] = {0.5f * (a0 + c0), 0.5f * (a1 + c1), 0.5f * (a2 + c2)};
+                __syncthreads();  // bins cleared, prefix areas visible to every lane
+                // One pass, chunks from the end: binning (order-free) and, for the cuts in
+                // the range's own order, suffix boxes and the cost of every cut.
+                float ic = INFINITY;
+                int ik = 0;
+                {
+                    WaveBox carry = kEmptyBox;  // union of the positions after the current chunk
+                    for (int c0 = b + ((cnt - 1) & ~63); c0 >= b; c0 -= 64) {
+                        const int i = c0 + lane;
+                        WaveBox x = kEmptyBox;
+                        if (i < en) {
+                            box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+                            const float cc[3] = {0.5f * (x.lx + x.hx), 0.5f * (x.ly + x.hy), 0.5f * (x.lz + x.hz)};
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        if (scale[a] == 0.f)
-                            continue;
-                        const int j = a * kBins + bin_of(cc[a], cmin[a], scale[a]);
-                        atomicAdd(&S.cnt[j], 1);
-                        atomicMin(&S.lo[3 * j + 0], f2o(a0));
-                        atomicMin(&S.lo[3 * j + 1], f2o(a1));
-                        atomicMin(&S.lo[3 * j + 2], f2o(a2));
-                        atomicMax(&S.hi[3 * j + 0], f2o(c0));
-                        atomicMax(&S.hi[3 * j + 1], f2o(c1));
-                        atomicMax(&S.hi[3 * j + 2], f2o(c2));
+                            for (int a = 0; a < 3; ++a) {
+                                if (scale[a] == 0.f)
+                                    continue;
+                                const int j = a * kBins + bin_of(cc[a], cmin[a], scale[a]);
+                                atomicAdd(&S.cnt[j], 1);
+                                atomicMin(&S.lo[3 * j + 0], f2o(x.lx));
+                                atomicMin(&S.lo[3 * j + 1], f2o(x.ly));
+                                atomicMin(&S.lo[3 * j + 2], f2o(x.lz));
+                                atomicMax(&S.hi[3 * j + 0], f2o(x.hx));
+                                atomicMax(&S.hi[3 * j + 1], f2o(x.hy));
+                                atomicMax(&S.hi[3 * j + 2], f2o(x.hz));
+                            }
+                        }
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1)
+                            x = box_union(x, box_down(x, d));
+                        const WaveBox suf = box_union(x, carry);  // positions i .. en - 1
+                        WaveBox rn = box_down(suf, 1);             // positions i + 1 .. en - 1
+                        if (lane == 63)
+                            rn = carry;
+                        if (i < en - 1) {
+                            const int k = i - b + 1;
+                            const float c = parea[i] * (float)k + half_area(rn.lx, rn.ly, rn.lz, rn.hx, rn.hy, rn.hz) * (float)(cnt - k);
+                            if (c < ic || (c == ic && k < ik)) {
+                                ic = c;
+                                ik = k;
+                            }
+                        }
+                        carry = box_bcast(suf, 0);
+                    }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        const float oc = __shfl_xor(ic, o, 64);
+                        const int ok = __shfl_xor(ik, o, 64);
+                        if (oc < ic || (oc == ic && ok < ik)) {
+                            ic = oc;
+                            ik = ok;
+                        }
                     }
                 }
                 __syncthreads();
@@ -609,65 +664,6 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                         bc = oc;
                         bw = ow;
                     }
-                }
-                // Cuts in the range's own order: it is ascending triangle id order (every
-                // split above local mode is a stable partition of the identity order), and
-                // mesh order is spatially coherent, so these cuts separate whole objects and
-                // clusters of equal centroids that no binned plane can split.  Forward pass:
-                // half-area of each prefix (kept in tmp, which the partition below reuses only
-                // afterwards); backward pass: suffix boxes and the cost of every cut.
-                float ic = INFINITY;
-                int ik = 0;
-                {
-                    float *parea = reinterpret_cast<float *>(tmp);
-                    WaveBox carry = kEmptyBox;
-                    for (int c0 = b; c0 < en; c0 += 64) {
-                        const int i = c0 + lane;
-                        WaveBox x = kEmptyBox;
-                        if (i < en)
-                            box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-#pragma unroll
-                        for (int d = 1; d < 64; d <<= 1)
-                            x = box_union(x, box_up(x, d));
-                        x = box_union(x, carry);
-                        if (i < en)
-                            parea[i] = half_area(x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-                        carry = box_bcast(x, 63);
-                    }
-                    __syncthreads();
-                    carry = kEmptyBox;  // union of the positions after the current chunk
-                    for (int c0 = b + ((cnt - 1) & ~63); c0 >= b; c0 -= 64) {
-                        const int i = c0 + lane;
-                        WaveBox x = kEmptyBox;
-                        if (i < en)
-                            box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-#pragma unroll
-                        for (int d = 1; d < 64; d <<= 1)
-                            x = box_union(x, box_down(x, d));
-                        const WaveBox suf = box_union(x, carry);  // positions i .. en - 1
-                        WaveBox rn = box_down(suf, 1);             // positions i + 1 .. en - 1
-                        if (lane == 63)
-                            rn = carry;
-                        if (i < en - 1) {
-                            const int k = i - b + 1;
-                            const float c = parea[i] * (float)k + half_area(rn.lx, rn.ly, rn.lz, rn.hx, rn.hy, rn.hz) * (float)(cnt - k);
-                            if (c < ic || (c == ic && k < ik)) {
-                                ic = c;
-                                ik = k;
-                            }
-                        }
-                        carry = box_bcast(suf, 0);
-                    }
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const float oc = __shfl_xor(ic, o, 64);
-                        const int ok = __shfl_xor(ik, o, 64);
-                        if (oc < ic || (oc == ic && ok < ik)) {
-                            ic = oc;
-                            ik = ok;
-                        }
-                    }
-                    __syncthreads();
                 }
                 if (ic < bc) {  // cut in id order: both sides are already contiguous
                     mid = b + ik;
