@@ -481,6 +481,44 @@ def test_lbvh_builder():
         R.close()
 
 
+def test_lbvh_size_boundaries():
+    """Environments of 4, 5, 4096, 4097, 8192 and 8193 triangles: each is
+    decided by exactly one of the linear-BVH kernels (up to 4096, up to 8192)
+    or the SAH kernels (at most 4, above 8192); every BVH is valid and the
+    render equals the SAH build's bit for bit and the oracle."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    rng = np.random.default_rng(23)
+
+    def soup(n):
+        c = rng.uniform(-3, 3, size=(n, 1, 3))
+        return ((c + rng.normal(scale=0.15, size=(n, 3, 3))).reshape(-1, 3).astype(np.float32),
+                np.arange(3 * n, dtype=np.int32).reshape(-1, 3))
+
+    sizes = (4, 5, 4096, 4097, 8192, 8193)
+    I = S.affine(np.eye(3), (0.0, 0.0, 0.0))
+    z3 = (0.0, 0.0, 0.0)
+    cam = S.sensor_pose(S.rot_zyx(0.0, 0.0), (-6.0, 0.1, 0.2))
+    envs = [([(k, k + 1, I, 0, z3)], [(0, cam)]) for k in range(len(sizes))]
+    scene = S.custom_scene([soup(n) for n in sizes], envs, [S.pinhole(24, 16, 80.0, 0.05, 50.0)])
+    R = _renderer(scene)
+    ref = _host(R.render(mode=rc.RC_RENDER_FLAT))
+    R.build(builder=rc.RC_BUILD_LBVH)
+    w = O.world(scene)
+    assert np.array_equal(np.diff(w.env_off), sizes)
+    for e in range(scene.n_envs):
+        bvh = rc.rc_debug_bvh(R.ctx, e, int(w.env_off[e + 1] - w.env_off[e]))
+        errs = bvh_check.validate(bvh, w.tris[w.env_off[e]:w.env_off[e + 1]])
+        assert not errs, (e, errs[:5])
+    out = _host(R.render(mode=rc.RC_RENDER_FLAT))
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(out[k], ref[k]), k
+    rep = parity.compare(out, O.render(scene, w))
+    print(rep, flush=True)
+    parity.assert_contract(rep)
+    R.close()
+
+
 def test_api_errors():
     """Argument and state errors are reported as status codes before any work."""
     from paper_2503_01471_amd import rc
