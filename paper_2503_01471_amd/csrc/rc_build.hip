@@ -1092,7 +1092,7 @@ __global__ __launch_bounds__(kScanBlock) void k_micro_scan(BuildView v)
         s[threadIdx.x] = x;
         __syncthreads();
         for (int d = 1; d < kScanBlock; d <<= 1) {
-            const int64_t y = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+            const int64_t y = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
             __syncthreads();
             s[threadIdx.x] += y;
             __syncthreads();
