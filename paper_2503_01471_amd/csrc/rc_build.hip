@@ -785,8 +785,7 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
 // K5b: ranges of 5..16 primitives deferred by k_build_sah.  One 16-lane group
 // per range (four per wavefront), one primitive per lane, builds the whole
 // subtree: every node takes the full-sweep SAH split over the three centroid
-// axes and the triangle id order (per order the group sorts (centroid,
-// triangle id), the centroid left out for the id order, with a bitonic
+// axes (per axis the group sorts (centroid, triangle id) with a bitonic
 // network across its lanes, scans the sorted boxes from both ends and takes
 // the cheapest split: lowest axis, then fewest left primitives, on ties), and
 // every side above kLeafMax primitives becomes a node of its own.  A side of
@@ -852,12 +851,10 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
     const int kmax = cap < cnt - 1 ? cap : cnt - 1;
     float best_c = INFINITY;
     int best_k = cnt / 2, best_a = 0;  // no finite cost: middle split along the first axis
-    int orders[4];
-    // orders 0..2: centroid along x, y, z; order 3: triangle id alone (mesh order)
+    int orders[3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const float c = a == 0 ? 0.5f * (bx.lx + bx.hx)
-                               : (a == 1 ? 0.5f * (bx.ly + bx.hy) : (a == 2 ? 0.5f * (bx.lz + bx.hz) : 0.f));
+    for (int a = 0; a < 3; ++a) {
+        const float c = a == 0 ? 0.5f * (bx.lx + bx.hx) : (a == 1 ? 0.5f * (bx.ly + bx.hy) : 0.5f * (bx.lz + bx.hz));
         int key = mine ? f2o(c) : INT32_MAX;
         int id = mine ? (pid << 4) | gl : 0x7ffffff0 | gl;  // ties: lower triangle id first
         group_sort(key, id, gl);
@@ -913,7 +910,7 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
             best_a = a;
         }
     }
-    order = best_a == 0 ? orders[0] : (best_a == 1 ? orders[1] : (best_a == 2 ? orders[2] : orders[3]));
+    order = best_a == 0 ? orders[0] : (best_a == 1 ? orders[1] : orders[2]);
     // child boxes of the chosen split
     const WaveBox got = box_shfl(bx, order & (kGroup - 1));
     const WaveBox s = gl < cnt ? got : kEmptyBox;
