@@ -116,6 +116,8 @@ BuildView Scene::view() const
     v.env_micro = env_micro.as<int32_t>();
     v.micro = micro.as<int4>();
     v.micro_off = micro_off.as<int64_t>();
+    v.env_local = env_local.as<int32_t>();
+    v.local_off = local_off.as<int64_t>();
     v.level_nodes = level_nodes.as<int32_t>();
     v.level_off = level_off.as<int32_t>();
     v.env_mask = nullptr;
@@ -438,6 +440,8 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->level_nodes, 4 * (size_t)(node_base(N, n_envs) + 16)));
     RC_TRY(c->pool.alloc(sc->level_off, 4 * (size_t)n_envs * (kLevels + 1)));
     RC_TRY(c->pool.alloc(sc->micro_off, 8 * ((size_t)n_envs + 1)));
+    RC_TRY(c->pool.alloc(sc->env_local, 4 * (size_t)n_envs));
+    RC_TRY(c->pool.alloc(sc->local_off, 8 * ((size_t)n_envs + 1)));
     RC_TRY(c->pool.alloc(sc->sah_mask, (size_t)n_envs + 16));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();

@@ -141,13 +141,14 @@ __global__ __launch_bounds__(256) void k_bounds(BuildView v)
 // K5: SAH build, one wavefront (64 lanes) per environment.
 // Tasks are processed depth first (left child next) and node ids are assigned
 // when a task is popped.  Nodes above kSmall primitives take the cheapest of
-// 3 x (kBins - 1) binned planes and split by a stable partition; smaller ones
-// take the exact sweep below.  Every step is deterministic.
-// A node whose subtree could exceed kMaxNodeDepth is split at the index median
-// (balanced), which bounds the traversal stack.
-// Once a task holds at most kSmall primitives its whole subtree is built from
-// LDS: depth-first order guarantees that every task popped after it, until the
-// stack is back at its height, is one of its descendants.
+// 3 x (kBins - 1) binned planes and the cuts in triangle-id order, split by a
+// stable partition; a task of at most kSmall primitives is deferred whole to
+// k_build_local, which builds it from LDS with the exact sweep below.  Every
+// step is deterministic.  A node whose subtree could exceed kMaxNodeDepth is
+// split at the index median (balanced), which bounds the traversal stack.
+// Within a deferred subtree, depth-first order guarantees that every task
+// popped after its root, until the stack is empty again, is one of its
+// descendants.
 // ---------------------------------------------------------------------------
 constexpr int kTaskCap = kMaxNodeDepth + 4;
 #ifndef RC_SMALL
@@ -379,11 +380,15 @@ __device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L
     return k;
 }
 
-__global__ __launch_bounds__(64) void k_build_sah(BuildView v)
+// One SAH job for one wavefront.  JOB = false: environment e from its root;
+// every task of at most kSmall primitives is deferred whole to k_build_local
+// (its root id assigned and linked now, followed by cnt - 2 reserved ids, the
+// task stored at the end of the environment's range list).  JOB = true: one
+// such deferred subtree, built from LDS, its ranges of 5..kMicro primitives
+// appended to the environment's range list with an atomic counter.
+template <bool JOB>
+__device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int e, int4 job)
 {
-    const int e = blockIdx.x;
-    if (masked_out(v, e))
-        return;
     const int lane = threadIdx.x;
     const int64_t base = v.env_tri_off[e];
     const int n = (int)(v.env_tri_off[e + 1] - base);
@@ -392,23 +397,30 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
     Node *nodes = v.nodes + node_base(base, e);
     const float4 *blo = v.box_lo + base;
     const float4 *bhi = v.box_hi + base;
-    __shared__ BuildShared S;
-
-    for (int i = lane; i < n; i += 64)
-        prim[i] = i;
     int n_nodes = 0;
-    if (n == 0) {
-        if (lane == 0) {
-            v.env_root[e] = kEmptyRoot;
-            v.env_nodes[e] = 0;
-            v.env_micro[e] = 0;
+    if (!JOB) {
+        for (int i = lane; i < n; i += 64)
+            prim[i] = i;
+        if (n == 0) {
+            if (lane == 0) {
+                v.env_root[e] = kEmptyRoot;
+                v.env_nodes[e] = 0;
+                v.env_micro[e] = 0;
+                v.env_local[e] = 0;
+            }
+            return;
         }
-        return;
+        __syncthreads();
+    } else {
+        n_nodes = job.x;  // the subtree's root id (linked, parent and depth written)
     }
-    __syncthreads();
     bool local = false;
     int b0 = 0, cnt0 = 0, h0 = 0;
-    int nm = 0;  // deferred small ranges of this environment
+    int nm = 0;   // deferred small ranges (environment job)
+    int nlt = 0;  // deferred subtrees (environment job)
+    // Ranges from the start of the list, subtrees from its end: a range holds at
+    // least 5 primitives and a subtree (other than a root) at least kMicro + 1,
+    // so n/5 + n/(kMicro + 1) + 1 <= n entries never meet.
     int4 *micro = v.micro + base;
 
     // bounds of the primitive at list position i (global list or LDS copy)
@@ -447,16 +459,16 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
         return WaveBox{wave_min(lx), wave_min(ly), wave_min(lz), wave_max(hx), wave_max(hy), wave_max(hz)};
     };
 
-    if (n <= kLeafMax) {
+    if (!JOB && n <= kLeafMax) {
         if (lane == 0)
             v.env_root[e] = leaf_ref(0, n);
     } else {
         int sp = 0;
-        S.tp[0] = -1;
+        S.tp[0] = JOB ? -2 : -1;  // -2: the subtree's root, already linked
         S.ts[0] = 0;
-        S.tb[0] = 0;
-        S.te[0] = n;
-        S.td[0] = 0;
+        S.tb[0] = JOB ? job.y : 0;
+        S.te[0] = JOB ? job.z : n;
+        S.td[0] = JOB ? job.w : 0;
         sp = 1;
         __syncthreads();
         while (sp > 0) {
@@ -464,7 +476,24 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
             const int parent = S.tp[sp], side = S.ts[sp], b = S.tb[sp], en = S.te[sp], depth = S.td[sp];
             const int cnt = en - b;
             __syncthreads();
-            if (!local && cnt <= kSmall) {
+            if (!JOB && cnt <= kSmall) {
+                const int cid = n_nodes;
+                n_nodes += cnt - 1;  // the most internal nodes cnt primitives can need
+                if (lane == 0) {
+                    if (parent < 0)
+                        v.env_root[e] = cid;
+                    else if (side == 0)
+                        nodes[parent].ch.x = cid;
+                    else
+                        nodes[parent].ch.y = cid;
+                    nodes[cid].ch.z = parent;
+                    nodes[cid].ch.w = depth;
+                    micro[n - 1 - nlt] = make_int4(cid, b, en, depth);
+                }
+                ++nlt;
+                continue;
+            }
+            if (JOB && !local) {
                 // enter local mode: copy the task's primitives into LDS
                 b0 = b;
                 cnt0 = cnt;
@@ -485,7 +514,7 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                 __syncthreads();
             }
             const int id = n_nodes++;
-            if (lane == 0) {
+            if (lane == 0 && parent != -2) {
                 if (parent < 0)
                     v.env_root[e] = id;
                 else if (side == 0)
@@ -753,7 +782,7 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
                             nodes[id].ch.y = cid;
                         nodes[cid].ch.z = id;
                         nodes[cid].ch.w = depth + 1;
-                        micro[nm] = make_int4(cid, cb[sd], ce[sd], depth + 1);
+                        micro[JOB ? atomicAdd(&v.env_micro[e], 1) : nm] = make_int4(cid, cb[sd], ce[sd], depth + 1);
                     }
                     ++nm;
                 } else {
@@ -776,13 +805,57 @@ __global__ __launch_bounds__(64) void k_build_sah(BuildView v)
         }
     }
     if (lane == 0) {
-        v.env_nodes[e] = n_nodes;
-        v.env_micro[e] = nm;
+        if (!JOB) {
+            v.env_nodes[e] = n_nodes;
+            v.env_micro[e] = nm;
+            v.env_local[e] = nlt;
+        } else {
+            // unused reserved ids: never referenced; a depth of -1 keeps refit away
+            for (int h = n_nodes; h < job.x + (job.z - job.y) - 1; ++h) {
+                Node &u = nodes[h];
+                u.xy0 = u.xy1 = u.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
+                u.ch = make_int4(0, 0, -1, -1);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_build_sah(BuildView v)
+{
+    const int e = blockIdx.x;
+    if (masked_out(v, e))
+        return;
+    __shared__ BuildShared S;
+    sah_job<false>(v, S, e, make_int4(0, 0, 0, 0));
+}
+
+// K5a: the subtrees deferred by k_build_sah, one wavefront each (a persistent
+// grid over the list of all of them), so an environment's LDS-resident levels
+// are built in parallel instead of one after another.
+__global__ __launch_bounds__(64) void k_build_local(BuildView v)
+{
+    __shared__ BuildShared S;
+    const int64_t total = v.local_off[v.n_envs];
+    for (int64_t T = blockIdx.x; T < total; T += gridDim.x) {
+        // environment of task T: local_off[e] <= T < local_off[e + 1]
+        int lo = 0, hi = v.n_envs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (v.local_off[mid] <= T)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t base = v.env_tri_off[lo];
+        const int n = (int)(v.env_tri_off[lo + 1] - base);
+        const int4 job = v.micro[base + n - 1 - (T - v.local_off[lo])];
+        __syncthreads();  // the previous job's LDS is no longer read
+        sah_job<true>(v, S, lo, job);
     }
 }
 
 // ---------------------------------------------------------------------------
-// K5b: ranges of 5..16 primitives deferred by k_build_sah.  One 16-lane group
+// K5b: ranges of 5..16 primitives deferred by k_build_sah and k_build_local.  One 16-lane group
 // per range (four per wavefront), one primitive per lane, builds the whole
 // subtree: every node takes the full-sweep SAH split over the three centroid
 // axes (per axis the group sorts (centroid, triangle id) with a bitonic
@@ -1074,18 +1147,18 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
 }
 
 // ---------------------------------------------------------------------------
-// K5a: where each environment's deferred ranges start in one list of all
-// tasks (exclusive scan of the per-environment counts; masked environments
-// count none); micro_off[n_envs] is the total.  One workgroup.
+// Where each environment's deferred tasks start in one list of all of them
+// (exclusive scan of the per-environment counts; masked environments count
+// none); off[n_envs] is the total.  One workgroup.
 constexpr int kScanBlock = 1024;
 
-__global__ __launch_bounds__(kScanBlock) void k_micro_scan(BuildView v)
+__global__ __launch_bounds__(kScanBlock) void k_count_scan(BuildView v, const int32_t *count, int64_t *off)
 {
     __shared__ int64_t s[kScanBlock];
     int64_t carry = 0;
     for (int c0 = 0; c0 < v.n_envs; c0 += kScanBlock) {
         const int e = c0 + threadIdx.x;
-        const int64_t x = (e < v.n_envs && !masked_out(v, e)) ? v.env_micro[e] : 0;
+        const int64_t x = (e < v.n_envs && !masked_out(v, e)) ? count[e] : 0;
         s[threadIdx.x] = x;
         __syncthreads();
         for (int d = 1; d < kScanBlock; d <<= 1) {
@@ -1095,12 +1168,12 @@ __global__ __launch_bounds__(kScanBlock) void k_micro_scan(BuildView v)
             __syncthreads();
         }
         if (e < v.n_envs)
-            v.micro_off[e] = carry + s[threadIdx.x] - x;
+            off[e] = carry + s[threadIdx.x] - x;
         carry += s[kScanBlock - 1];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        v.micro_off[v.n_envs] = carry;
+        off[v.n_envs] = carry;
 }
 
 // K5c: leaf-ordered records and the inverse permutation, one thread per triangle.
@@ -1472,6 +1545,30 @@ hipError_t launch_bump(int32_t *d_step, hipStream_t st)
     return hipGetLastError();
 }
 
+// Subtrees of at most kSmall primitives (k_build_local, one wavefront each),
+// then the ranges of 5..kMicro primitives (k_build_micro), for the
+// environments the view admits.
+hipError_t launch_deferred(const BuildView &v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(kScanBlock), 0, st, v, (const int32_t *)v.env_local, v.local_off);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return err;
+    // persistent wavefronts; a deferred subtree holds > kMicro primitives (or is a whole environment)
+    const int64_t tasks = v.n_tris / (kMicro + 1) + v.n_envs;
+    hipLaunchKernelGGL(k_build_local, dim3((unsigned)(tasks < 8192 ? tasks : 8192)), dim3(64), 0, st, v);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(kScanBlock), 0, st, v, (const int32_t *)v.env_micro, v.micro_off);
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    // persistent groups; every range holds >= 5 primitives, so there are at most n_tris / 5
+    const int64_t groups = v.n_tris / 5 + 1;
+    const int64_t blocks = (groups * kGroup + kMicroBlock - 1) / kMicroBlock;
+    hipLaunchKernelGGL(k_build_micro, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kMicroBlock), 0, st, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
 {
     if (v.n_tris > 0) {
@@ -1486,14 +1583,7 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || v.n_tris == 0)
         return err;
-    hipLaunchKernelGGL(k_micro_scan, dim3(1), dim3(kScanBlock), 0, st, v);
-    if ((err = hipGetLastError()) != hipSuccess)
-        return err;
-    // persistent groups; every range holds >= 5 primitives, so there are at most n_tris / 5
-    const int64_t groups = v.n_tris / 5 + 1;
-    const int64_t blocks = (groups * kGroup + kMicroBlock - 1) / kMicroBlock;
-    hipLaunchKernelGGL(k_build_micro, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kMicroBlock), 0, st, v);
-    if ((err = hipGetLastError()) != hipSuccess)
+    if ((err = launch_deferred(v, st)) != hipSuccess)
         return err;
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
     if ((err = hipGetLastError()) != hipSuccess)
@@ -1525,13 +1615,7 @@ hipError_t launch_build_lbvh(const BuildView &v, uint8_t *sah_mask, hipStream_t 
     hipLaunchKernelGGL(k_build_sah, dim3(v.n_envs), dim3(64), 0, st, vs);
     if ((err = hipGetLastError()) != hipSuccess || v.n_tris == 0)
         return err;
-    hipLaunchKernelGGL(k_micro_scan, dim3(1), dim3(kScanBlock), 0, st, vs);
-    if ((err = hipGetLastError()) != hipSuccess)
-        return err;
-    const int64_t groups = v.n_tris / 5 + 1;
-    const int64_t blocks = (groups * kGroup + kMicroBlock - 1) / kMicroBlock;
-    hipLaunchKernelGGL(k_build_micro, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kMicroBlock), 0, st, vs);
-    if ((err = hipGetLastError()) != hipSuccess)
+    if ((err = launch_deferred(vs, st)) != hipSuccess)
         return err;
     // every requested environment: records in leaf order, level lists, bounds
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);

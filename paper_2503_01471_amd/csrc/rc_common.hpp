@@ -137,6 +137,8 @@ struct BuildView {
     int32_t *env_micro;          // [E] deferred small ranges per environment
     int4 *micro;                 // [N] deferred ranges (node, begin, end, depth)
     int64_t *micro_off;          // [E+1] start of env e's ranges in the list of all ranges
+    int32_t *env_local;          // [E] subtrees of at most kSmall primitives deferred per environment
+    int64_t *local_off;          // [E+1] start of env e's subtrees in the list of all subtrees
     int32_t *level_nodes;        // node slots of env e grouped by depth (same base as nodes)
     int32_t *level_off;          // [E][kLevels + 1] depth d of env e = level_nodes[off[d] .. off[d+1])
     const uint8_t *env_mask;     // [E] environments to process (nullptr: all)

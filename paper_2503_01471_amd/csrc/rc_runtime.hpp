@@ -74,7 +74,7 @@ struct Scene {
     std::vector<int64_t> inst_offsets;
     DBuf proto_xyz, proto_tri, d_env_tri_off, tri_env, tri_src, tri_seg, inst_T, inst_T0, inst_dyn, dyn_tris;
     DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, env_micro, micro;
-    DBuf level_nodes, level_off, micro_off;
+    DBuf level_nodes, level_off, micro_off, env_local, local_off;
     DBuf sah_mask;  // LBVH builds: environments left to the SAH kernels
     bool poses_set = false;
     bool built = false;
