@@ -41,20 +41,62 @@ __device__ __forceinline__ float expand_hi(float x)
     return __int_as_float(x > 0.f ? i + 1 : i - 1);
 }
 
-__device__ __forceinline__ float wave_min(float v)
+// DPP lane moves (gfx9 encodings): row_shr:n = 0x110 + n and row_shl:n =
+// 0x100 + n within rows of 16 lanes, wave_shr:1 = 0x138 and wave_shl:1 = 0x130
+// across the wavefront.  Lane i reads lane i - n (shr) or i + n (shl); a lane
+// whose source lies outside its row (or the wavefront) keeps `old`.  Every
+// cross-lane helper below is called from uniform control flow with all 64
+// lanes active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float old, float x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ float wave_max(float v)
+__device__ __forceinline__ float readlane_f(float x, int l)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
+template <bool MIN>
+__device__ __forceinline__ float mm(float a, float b) { return MIN ? fminf(a, b) : fmaxf(a, b); }
+
+// Inclusive in-row scan (Hillis-Steele over shifts 1, 2, 4, 8): lanes
+// 16 r .. i of the row (UP) or i .. 16 r + 15.
+template <bool MIN, bool UP>
+__device__ __forceinline__ float row_scan(float x)
+{
+    constexpr float id = MIN ? INFINITY : -INFINITY;
+    x = mm<MIN>(x, dpp_mov<UP ? 0x111 : 0x101>(id, x));
+    x = mm<MIN>(x, dpp_mov<UP ? 0x112 : 0x102>(id, x));
+    x = mm<MIN>(x, dpp_mov<UP ? 0x114 : 0x104>(id, x));
+    x = mm<MIN>(x, dpp_mov<UP ? 0x118 : 0x108>(id, x));
+    return x;
+}
+// Inclusive scan over the wavefront: lanes 0 .. i (UP) or i .. 63; the row
+// totals are combined through readlane.
+template <bool MIN, bool UP>
+__device__ __forceinline__ float lane_scan(float x, int row)
+{
+    constexpr float id = MIN ? INFINITY : -INFINITY;
+    x = row_scan<MIN, UP>(x);
+    if (UP) {
+        const float r0 = readlane_f(x, 15);
+        const float r1 = mm<MIN>(r0, readlane_f(x, 31));
+        const float r2 = mm<MIN>(r1, readlane_f(x, 47));
+        return mm<MIN>(x, row == 0 ? id : (row == 1 ? r0 : (row == 2 ? r1 : r2)));
+    }
+    const float r3 = readlane_f(x, 48);
+    const float r2 = mm<MIN>(r3, readlane_f(x, 32));
+    const float r1 = mm<MIN>(r2, readlane_f(x, 16));
+    return mm<MIN>(x, row == 3 ? id : (row == 2 ? r3 : (row == 1 ? r2 : r1)));
+}
+template <bool MIN>
+__device__ __forceinline__ float lane_reduce(float x)
+{
+    x = row_scan<MIN, true>(x);
+    return mm<MIN>(mm<MIN>(readlane_f(x, 15), readlane_f(x, 31)), mm<MIN>(readlane_f(x, 47), readlane_f(x, 63)));
+}
+__device__ __forceinline__ float wave_min(float v) { return lane_reduce<true>(v); }
+__device__ __forceinline__ float wave_max(float v) { return lane_reduce<false>(v); }
 
 // ---------------------------------------------------------------------------
 // K1: sub-mesh transform, one thread per world triangle.  Coordinate r of a
@@ -188,6 +230,8 @@ struct BuildShared {
     int id[kSmall];        // local mode: environment-local id by slot
     int perm[kSmall];      // local mode: slot at each position
     int perm2[kSmall];
+    int ord[4][kSmall];    // local mode: slots of each task in each sweep order
+    int side[kSmall];      // local mode: side of each slot in the current split
 };
 
 __device__ __forceinline__ void write_boxes(Node &nd, const WaveBox &L, const WaveBox &R)
@@ -199,14 +243,16 @@ __device__ __forceinline__ void write_boxes(Node &nd, const WaveBox &L, const Wa
 
 // ---------------------------------------------------------------------------
 // Exact SAH sweep for a task of at most kSmall primitives held in LDS (local
-// mode).  Per axis the wavefront sorts (centroid, slot) keys with a bitonic
-// network (kSweepE keys per lane, key h of lane l at index 64 h + l).  Slots
-// are numbered in the order the primitives had when the subtree entered LDS,
-// which is ascending triangle id (every earlier split is a stable partition of
-// the identity order), so equal centroids fall in id order; a fourth order is
-// the slot order alone (mesh order).  Then both ends are scanned for the union
-// boxes, every split position is costed, and the cheapest wins (lowest order,
-// then fewest left primitives, on ties).
+// mode).  Slots number the subtree's primitives in the order they had when it
+// entered LDS, which is ascending triangle id (every earlier split is a stable
+// partition of the identity order).  On entry the wavefront sorts the slots
+// once per centroid axis by (centroid, slot) with a bitonic network (kSweepE
+// keys per lane, key h of lane l at index 64 h + l); the fourth order is the
+// slot order itself (mesh order).  Every split then stable-partitions the four
+// lists, so each task finds its primitives sorted in every order (a subset of
+// a sorted list is sorted).  Per order the sweep scans the boxes from both
+// ends, costs every split position, and the cheapest wins (lowest order, then
+// fewest left primitives, on ties).
 // ---------------------------------------------------------------------------
 constexpr int kSweepE = kSmall / 64;
 static_assert(kSmall % 64 == 0 && (kSweepE & (kSweepE - 1)) == 0, "kSmall must be 64 times a power of two");
@@ -219,21 +265,26 @@ __device__ __forceinline__ WaveBox box_union(const WaveBox &a, const WaveBox &b)
                    fmaxf(a.hx, b.hx), fmaxf(a.hy, b.hy), fmaxf(a.hz, b.hz)};
 }
 
-// Whole-wavefront lane reads (call from every lane).
-__device__ __forceinline__ WaveBox box_up(const WaveBox &b, int d)
+// Inclusive union over lanes 0 .. i (UP) or i .. 63 (row = lane / 16).
+template <bool UP>
+__device__ __forceinline__ WaveBox box_scan(const WaveBox &b, int row)
 {
-    return WaveBox{__shfl_up(b.lx, d, 64), __shfl_up(b.ly, d, 64), __shfl_up(b.lz, d, 64),
-                   __shfl_up(b.hx, d, 64), __shfl_up(b.hy, d, 64), __shfl_up(b.hz, d, 64)};
+    return WaveBox{lane_scan<true, UP>(b.lx, row),  lane_scan<true, UP>(b.ly, row),  lane_scan<true, UP>(b.lz, row),
+                   lane_scan<false, UP>(b.hx, row), lane_scan<false, UP>(b.hy, row), lane_scan<false, UP>(b.hz, row)};
 }
-__device__ __forceinline__ WaveBox box_down(const WaveBox &b, int d)
+// Box of lane i - 1 (UP) or i + 1; the empty box at the end of the wavefront.
+template <bool UP>
+__device__ __forceinline__ WaveBox box_shift(const WaveBox &b)
 {
-    return WaveBox{__shfl_down(b.lx, d, 64), __shfl_down(b.ly, d, 64), __shfl_down(b.lz, d, 64),
-                   __shfl_down(b.hx, d, 64), __shfl_down(b.hy, d, 64), __shfl_down(b.hz, d, 64)};
+    constexpr int C = UP ? 0x138 : 0x130;
+    return WaveBox{dpp_mov<C>(INFINITY, b.lx),  dpp_mov<C>(INFINITY, b.ly),  dpp_mov<C>(INFINITY, b.lz),
+                   dpp_mov<C>(-INFINITY, b.hx), dpp_mov<C>(-INFINITY, b.hy), dpp_mov<C>(-INFINITY, b.hz)};
 }
-__device__ __forceinline__ WaveBox box_bcast(const WaveBox &b, int src)
+// Box of lane src (wave-uniform).
+__device__ __forceinline__ WaveBox box_lane(const WaveBox &b, int src)
 {
-    return WaveBox{__shfl(b.lx, src, 64), __shfl(b.ly, src, 64), __shfl(b.lz, src, 64),
-                   __shfl(b.hx, src, 64), __shfl(b.hy, src, 64), __shfl(b.hz, src, 64)};
+    return WaveBox{readlane_f(b.lx, src), readlane_f(b.ly, src), readlane_f(b.lz, src),
+                   readlane_f(b.hx, src), readlane_f(b.hy, src), readlane_f(b.hz, src)};
 }
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m)
@@ -275,81 +326,77 @@ __device__ __forceinline__ void wave_sort(uint64_t (&key)[E], int lane)
     }
 }
 
-// Split of the cnt primitives at list positions pb .. pb + cnt - 1 of S.perm.
-// Returns the left count (0 if no split has a finite cost) and, when it
-// splits, the child boxes; S.perm then holds the chosen axis order.  E keys
-// per lane (64 E >= cnt).
+// The three centroid orders of the cnt slots of a subtree entering LDS, and
+// the slot order; 64 E >= cnt.
 template <int E>
-__device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L, WaveBox &R)
+__device__ __forceinline__ void local_sort(BuildShared &S, int cnt, int lane)
 {
-    int slot[E];
 #pragma unroll
-    for (int h = 0; h < E; ++h) {
-        const int p = 64 * h + lane;
-        slot[h] = p < cnt ? S.perm[pb + p] : -1;
-    }
-    float best_c = INFINITY;
-    int best_w = INT32_MAX;  // order * 64 E + left count
-    WaveBox bl = kEmptyBox, br = kEmptyBox;
-    int sorted[4][E];
-    // orders 0..2: centroid along x, y, z; order 3: slot (= triangle id) order alone
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 3; ++a) {
         uint64_t key[E];
 #pragma unroll
         for (int h = 0; h < E; ++h) {
-            const int s = slot[h];
-            const float c = (s >= 0 && a < 3) ? 0.5f * (S.box[a][s] + S.box[3 + a][s]) : 0.f;
-            key[h] = s >= 0 ? ((uint64_t)((uint32_t)f2o(c) ^ 0x80000000u) << 32) | (uint32_t)s : kNoKey;
+            const int s = 64 * h + lane;
+            const float c = s < cnt ? 0.5f * (S.box[a][s] + S.box[3 + a][s]) : 0.f;
+            key[h] = s < cnt ? ((uint64_t)((uint32_t)f2o(c) ^ 0x80000000u) << 32) | (uint32_t)s : kNoKey;
         }
         wave_sort<E>(key, lane);
-        WaveBox bx[E];
 #pragma unroll
         for (int h = 0; h < E; ++h) {
-            const int s = key[h] == kNoKey ? -1 : (int)(uint32_t)key[h];
-            sorted[a][h] = s;
-            bx[h] = s >= 0 ? WaveBox{S.box[0][s], S.box[1][s], S.box[2][s], S.box[3][s], S.box[4][s], S.box[5][s]}
+            const int p = 64 * h + lane;
+            if (p < cnt)
+                S.ord[a][p] = (int)(uint32_t)key[h];
+        }
+    }
+    for (int p = lane; p < cnt; p += 64)
+        S.ord[3][p] = p;
+}
+
+// Split of the cnt primitives at positions pb .. pb + cnt - 1 of the sorted
+// lists.  Lane l holds positions E l .. E l + E - 1 (64 E >= cnt).  Returns
+// the left count (0 if no split has a finite cost) and, when it splits, the
+// child boxes; S.perm then holds the chosen order over the range.
+template <int E>
+__device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L, WaveBox &R)
+{
+    constexpr int W = kSmall + 1;  // candidate rank: order * W + left count
+    const int row = lane >> 4;
+    float best_c = INFINITY;
+    int best_w = INT32_MAX;
+    WaveBox bl = kEmptyBox, br = kEmptyBox;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        WaveBox lp[E], ls[E];  // unions of the lane's positions up to / from h
+#pragma unroll
+        for (int h = 0; h < E; ++h) {
+            const int p = E * lane + h;
+            const int s = p < cnt ? S.ord[a][pb + p] : -1;
+            lp[h] = s >= 0 ? WaveBox{S.box[0][s], S.box[1][s], S.box[2][s], S.box[3][s], S.box[4][s], S.box[5][s]}
                            : kEmptyBox;
         }
-        // P: union of positions 0..p; Q: union of positions p..end
-        WaveBox P[E], Q[E], qfirst[E + 1];
-        WaveBox carry = kEmptyBox;
+        ls[E - 1] = lp[E - 1];
+#pragma unroll
+        for (int h = E - 2; h >= 0; --h)
+            ls[h] = box_union(lp[h], ls[h + 1]);
+#pragma unroll
+        for (int h = 1; h < E; ++h)
+            lp[h] = box_union(lp[h - 1], lp[h]);
+        const WaveBox before = box_shift<true>(box_scan<true>(lp[E - 1], row));  // positions < E l
+        const WaveBox after = box_shift<false>(box_scan<false>(ls[0], row));     // positions >= E l + E
 #pragma unroll
         for (int h = 0; h < E; ++h) {
-            WaveBox x = bx[h];
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1)
-                x = box_union(x, box_up(x, d));
-            P[h] = box_union(x, carry);
-            carry = box_bcast(P[h], 63);
-        }
-        carry = kEmptyBox;
-        qfirst[E] = kEmptyBox;
-#pragma unroll
-        for (int h = E - 1; h >= 0; --h) {
-            WaveBox x = bx[h];
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1)
-                x = box_union(x, box_down(x, d));
-            Q[h] = box_union(x, carry);
-            carry = box_bcast(Q[h], 0);
-            qfirst[h] = carry;
-        }
-#pragma unroll
-        for (int h = 0; h < E; ++h) {
-            WaveBox qn = box_down(Q[h], 1);  // Q at position p + 1
-            if (lane == 63)
-                qn = qfirst[h + 1];
-            const int k = 64 * h + lane + 1;  // left = positions 0 .. k - 1
+            const int k = E * lane + h + 1;  // left = positions 0 .. k - 1
             if (k < cnt) {
-                const float c = half_area(P[h].lx, P[h].ly, P[h].lz, P[h].hx, P[h].hy, P[h].hz) * (float)k +
-                                half_area(qn.lx, qn.ly, qn.lz, qn.hx, qn.hy, qn.hz) * (float)(cnt - k);
-                const int w = a * 64 * E + k;
+                const WaveBox P = box_union(before, lp[h]);
+                const WaveBox Q = h + 1 < E ? box_union(ls[h + 1], after) : after;
+                const float c = half_area(P.lx, P.ly, P.lz, P.hx, P.hy, P.hz) * (float)k +
+                                half_area(Q.lx, Q.ly, Q.lz, Q.hx, Q.hy, Q.hz) * (float)(cnt - k);
+                const int w = a * W + k;
                 if (c < best_c || (c == best_c && w < best_w)) {
                     best_c = c;
                     best_w = w;
-                    bl = P[h];
-                    br = qn;
+                    bl = P;
+                    br = Q;
                 }
             }
         }
@@ -367,17 +414,49 @@ __device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L
     }
     if (!(bc < INFINITY))
         return 0;
-    const int a = bw / (64 * E), k = bw % (64 * E);
-    const int src = (k - 1) & 63;  // the lane that costed this split (its own best)
-    L = box_bcast(bl, src);
-    R = box_bcast(br, src);
-#pragma unroll
-    for (int h = 0; h < E; ++h) {
-        const int p = 64 * h + lane;
-        if (p < cnt)
-            S.perm[pb + p] = a == 0 ? sorted[0][h] : (a == 1 ? sorted[1][h] : (a == 2 ? sorted[2][h] : sorted[3][h]));
-    }
+    bw = __builtin_amdgcn_readfirstlane(bw);
+    const int a = bw / W, k = bw % W;
+    const int src = (k - 1) / E;  // the lane that costed this split (its own best)
+    L = box_lane(bl, src);
+    R = box_lane(br, src);
+    for (int p = lane; p < cnt; p += 64)
+        S.perm[pb + p] = S.ord[a][pb + p];
     return k;
+}
+
+// Local mode, after the task at positions pb .. pb + cnt - 1 has been split
+// into the first nl positions of S.perm and the rest: stable partition of the
+// four sorted lists by side.
+__device__ __forceinline__ void local_partition(BuildShared &S, int pb, int cnt, int nl, int lane)
+{
+    for (int p = lane; p < cnt; p += 64)
+        S.side[S.perm[pb + p]] = p < nl;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        int s[kSweepE];
+        bool left[kSweepE];
+#pragma unroll
+        for (int h = 0; h < kSweepE; ++h) {
+            const int p = 64 * h + lane;
+            s[h] = p < cnt ? S.ord[a][pb + p] : -1;
+            left[h] = s[h] >= 0 && S.side[s[h]] != 0;
+        }
+        __syncthreads();  // the whole list is read before any of it is rewritten
+        int lc = 0, rc = 0;
+#pragma unroll
+        for (int h = 0; h < kSweepE; ++h) {
+            const uint64_t m = __ballot(left[h]);
+            const int rank = __popcll(m & ((1ull << lane) - 1));  // left entries in lower lanes
+            const int nvalid = min(64, max(0, cnt - 64 * h));
+            if (s[h] >= 0)
+                S.ord[a][pb + (left[h] ? lc + rank : nl + rc + (lane - rank))] = s[h];
+            const int cl = __popcll(m);
+            lc += cl;
+            rc += nvalid - cl;
+        }
+    }
+    __syncthreads();
 }
 
 // One SAH job for one wavefront.  JOB = false: environment e from its root;
@@ -512,6 +591,11 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                 }
                 local = true;
                 __syncthreads();
+                if (cnt <= 64)
+                    local_sort<1>(S, cnt, lane);
+                else
+                    local_sort<kSweepE>(S, cnt, lane);
+                __syncthreads();
             }
             const int id = n_nodes++;
             if (lane == 0 && parent != -2) {
@@ -551,13 +635,10 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                         ch1 = fmaxf(ch1, cy);
                         ch2 = fmaxf(ch2, cz);
                     }
-#pragma unroll
-                    for (int d = 1; d < 64; d <<= 1)
-                        x = box_union(x, box_up(x, d));
-                    x = box_union(x, carry);
+                    x = box_union(box_scan<true>(x, lane >> 4), carry);
                     if (i < en)
                         parea[i] = half_area(x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-                    carry = box_bcast(x, 63);
+                    carry = box_lane(x, 63);
                 }
                 const float mn[3] = {wave_min(cl0), wave_min(cl1), wave_min(cl2)};
                 const float mx[3] = {wave_max(ch0), wave_max(ch1), wave_max(ch2)};
@@ -613,13 +694,9 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                                 atomicMax(&S.hi[3 * j + 2], f2o(x.hz));
                             }
                         }
-#pragma unroll
-                        for (int d = 1; d < 64; d <<= 1)
-                            x = box_union(x, box_down(x, d));
-                        const WaveBox suf = box_union(x, carry);  // positions i .. en - 1
-                        WaveBox rn = box_down(suf, 1);             // positions i + 1 .. en - 1
-                        if (lane == 63)
-                            rn = carry;
+                        x = box_scan<false>(x, lane >> 4);
+                        const WaveBox suf = box_union(x, carry);                    // positions i .. en - 1
+                        const WaveBox rn = box_union(box_shift<false>(x), carry);  // positions i + 1 .. en - 1
                         if (i < en - 1) {
                             const int k = i - b + 1;
                             const float c = parea[i] * (float)k + half_area(rn.lx, rn.ly, rn.lz, rn.hx, rn.hy, rn.hz) * (float)(cnt - k);
@@ -628,7 +705,7 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                                 ik = k;
                             }
                         }
-                        carry = box_bcast(suf, 0);
+                        carry = box_lane(suf, 0);
                     }
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
@@ -753,6 +830,8 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                 L = reduce_range(b, mid);
                 R = reduce_range(mid, en);
             }
+            if (local)
+                local_partition(S, b - b0, cnt, mid - b, lane);
             // write the node's child boxes (expanded outward by one step)
             const int nl = mid - b, nr = en - mid;
             if (lane == 0) {
