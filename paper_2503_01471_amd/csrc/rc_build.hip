@@ -950,37 +950,97 @@ __global__ __launch_bounds__(64) void k_build_local(BuildView v)
 constexpr int kMicroBlock = 256;
 constexpr int kGroup = 16;
 
-// Ascending (key, id) across the 16 lanes of a group (ids distinct).
-__device__ __forceinline__ void group_sort(int &key, int &id, int gl)
+// A group is one DPP row.  Value of lane gl ^ M of the row: quad_perm
+// [1,0,3,2] (M = 1) and [2,3,0,1] (M = 2), row_ror:8 (M = 8), and for M = 4
+// row_shl:4 or row_shr:4 by the lane's bit 2.
+template <int M>
+__device__ __forceinline__ int row_xor(int x, int gl)
 {
-#pragma unroll
-    for (int k = 2; k <= kGroup; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int ok = __shfl_xor(key, j, kGroup);
-            const int oi = __shfl_xor(id, j, kGroup);
-            const bool other_less = ok < key || (ok == key && oi < id);
-            const bool take = (((gl & k) == 0) == ((gl & j) == 0)) ? other_less : !other_less;
-            if (take) {
-                key = ok;
-                id = oi;
-            }
-        }
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8, "partner within the row");
+    if (M == 1)
+        return __builtin_amdgcn_update_dpp(x, x, 0xb1, 0xf, 0xf, false);
+    if (M == 2)
+        return __builtin_amdgcn_update_dpp(x, x, 0x4e, 0xf, 0xf, false);
+    if (M == 8)
+        return __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);
+    const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xf, 0xf, false);
+    const int dn = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false);
+    return (gl & 4) ? dn : up;
+}
+template <int M>
+__device__ __forceinline__ float row_xor_f(float x, int gl) { return __int_as_float(row_xor<M>(__float_as_int(x), gl)); }
+
+// Compare-exchange of the bitonic network: partner lane gl ^ j, block size k.
+template <int K, int J>
+__device__ __forceinline__ void group_cx(int &key, int &id, int gl)
+{
+    const int ok = row_xor<J>(key, gl);
+    const int oi = row_xor<J>(id, gl);
+    const bool other_less = ok < key || (ok == key && oi < id);
+    const bool take = (((gl & K) == 0) == ((gl & J) == 0)) ? other_less : !other_less;
+    if (take) {
+        key = ok;
+        id = oi;
     }
 }
 
-__device__ __forceinline__ WaveBox group_box_reduce(WaveBox b)
+// Ascending (key, id) across the 16 lanes of a group (ids distinct).
+__device__ __forceinline__ void group_sort(int &key, int &id, int gl)
 {
-#pragma unroll
-    for (int d = 1; d < kGroup; d <<= 1) {
-        b.lx = fminf(b.lx, __shfl_xor(b.lx, d, kGroup));
-        b.ly = fminf(b.ly, __shfl_xor(b.ly, d, kGroup));
-        b.lz = fminf(b.lz, __shfl_xor(b.lz, d, kGroup));
-        b.hx = fmaxf(b.hx, __shfl_xor(b.hx, d, kGroup));
-        b.hy = fmaxf(b.hy, __shfl_xor(b.hy, d, kGroup));
-        b.hz = fmaxf(b.hz, __shfl_xor(b.hz, d, kGroup));
+    group_cx<2, 1>(key, id, gl);
+    group_cx<4, 2>(key, id, gl);
+    group_cx<4, 1>(key, id, gl);
+    group_cx<8, 4>(key, id, gl);
+    group_cx<8, 2>(key, id, gl);
+    group_cx<8, 1>(key, id, gl);
+    group_cx<16, 8>(key, id, gl);
+    group_cx<16, 4>(key, id, gl);
+    group_cx<16, 2>(key, id, gl);
+    group_cx<16, 1>(key, id, gl);
+}
+
+// Minimum or maximum over the group: quad_perm [1,0,3,2], [2,3,0,1], then
+// row_half_mirror (lane j with 7 - j of its half) and row_mirror (j with 15 - j).
+template <bool MIN>
+__device__ __forceinline__ float group_reduce(float x)
+{
+    x = mm<MIN>(x, dpp_mov<0xb1>(x, x));
+    x = mm<MIN>(x, dpp_mov<0x4e>(x, x));
+    x = mm<MIN>(x, dpp_mov<0x141>(x, x));
+    return mm<MIN>(x, dpp_mov<0x140>(x, x));
+}
+
+__device__ __forceinline__ WaveBox group_box_reduce(const WaveBox &b)
+{
+    return WaveBox{group_reduce<true>(b.lx),  group_reduce<true>(b.ly),  group_reduce<true>(b.lz),
+                   group_reduce<false>(b.hx), group_reduce<false>(b.hy), group_reduce<false>(b.hz)};
+}
+
+// Inclusive union over lanes 0 .. gl (UP) or gl .. 15 of the group.
+template <bool UP>
+__device__ __forceinline__ WaveBox group_scan(const WaveBox &b)
+{
+    return WaveBox{row_scan<true, UP>(b.lx),  row_scan<true, UP>(b.ly),  row_scan<true, UP>(b.lz),
+                   row_scan<false, UP>(b.hx), row_scan<false, UP>(b.hy), row_scan<false, UP>(b.hz)};
+}
+
+// Box of lane gl + 1 of the group (row_shl:1); the empty box at lane 15.
+__device__ __forceinline__ WaveBox group_next(const WaveBox &b)
+{
+    return WaveBox{dpp_mov<0x101>(INFINITY, b.lx),  dpp_mov<0x101>(INFINITY, b.ly),  dpp_mov<0x101>(INFINITY, b.lz),
+                   dpp_mov<0x101>(-INFINITY, b.hx), dpp_mov<0x101>(-INFINITY, b.hy), dpp_mov<0x101>(-INFINITY, b.hz)};
+}
+
+// One step of the group's argmin of (cost, k): partner lane gl ^ M.
+template <int M>
+__device__ __forceinline__ void group_min_step(float &bc, int &bk, int gl)
+{
+    const float oc = row_xor_f<M>(bc, gl);
+    const int ok = row_xor<M>(bk, gl);
+    if (oc < bc || (oc == bc && ok < bk)) {
+        bc = oc;
+        bk = ok;
     }
-    return b;
 }
 
 // Cross-lane read within the group.  Call it from every lane of the group
@@ -1015,30 +1075,9 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
         // part in the shuffle: its source may lie outside [0, cnt))
         const WaveBox got = box_shfl(bx, id & (kGroup - 1));
         const WaveBox s = gl < cnt ? got : kEmptyBox;
-        WaveBox pre = s, suf = s;
-#pragma unroll
-        for (int d = 1; d < kGroup; d <<= 1) {
-            const WaveBox u = box_shfl(pre, gl >= d ? gl - d : gl);
-            if (gl >= d) {
-                pre.lx = fminf(pre.lx, u.lx);
-                pre.ly = fminf(pre.ly, u.ly);
-                pre.lz = fminf(pre.lz, u.lz);
-                pre.hx = fmaxf(pre.hx, u.hx);
-                pre.hy = fmaxf(pre.hy, u.hy);
-                pre.hz = fmaxf(pre.hz, u.hz);
-            }
-            const WaveBox w = box_shfl(suf, gl + d < kGroup ? gl + d : gl);
-            if (gl + d < kGroup) {
-                suf.lx = fminf(suf.lx, w.lx);
-                suf.ly = fminf(suf.ly, w.ly);
-                suf.lz = fminf(suf.lz, w.lz);
-                suf.hx = fmaxf(suf.hx, w.hx);
-                suf.hy = fmaxf(suf.hy, w.hy);
-                suf.hz = fmaxf(suf.hz, w.hz);
-            }
-        }
+        const WaveBox pre = group_scan<true>(s);
         // lane r: split after k = r + 1 (left = sorted 0..r, right = r+1..cnt-1)
-        const WaveBox rs = box_shfl(suf, gl + 1 < kGroup ? gl + 1 : gl);
+        const WaveBox rs = group_next(group_scan<false>(s));
         const int k = gl + 1;
         float cost = INFINITY;
         if (k >= kmin && k <= kmax && k < cnt)
@@ -1047,15 +1086,10 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
         // cheapest over the group, fewest left primitives on ties
         float bc = cost;
         int bk = k;
-#pragma unroll
-        for (int d = 1; d < kGroup; d <<= 1) {
-            const float oc = __shfl_xor(bc, d, kGroup);
-            const int okk = __shfl_xor(bk, d, kGroup);
-            if (oc < bc || (oc == bc && okk < bk)) {
-                bc = oc;
-                bk = okk;
-            }
-        }
+        group_min_step<1>(bc, bk, gl);
+        group_min_step<2>(bc, bk, gl);
+        group_min_step<4>(bc, bk, gl);
+        group_min_step<8>(bc, bk, gl);
         if (bc < best_c) {
             best_c = bc;
             best_k = bk;
@@ -1118,9 +1152,7 @@ __device__ __forceinline__ bool micro_leaf(const WaveBox &bx, int gl, int first,
         cost = half_area(l.lx, l.ly, l.lz, l.hx, l.hy, l.hz) * (float)nl +
                half_area(r.lx, r.ly, r.lz, r.hx, r.hy, r.hz) * (float)(c - nl);
     }
-#pragma unroll
-    for (int d = 1; d < kGroup; d <<= 1)
-        cost = fminf(cost, __shfl_xor(cost, d, kGroup));
+    cost = group_reduce<true>(cost);
     const float a = half_area(U.lx, U.ly, U.lz, U.hx, U.hy, U.hz);
     return !((float)c * a > a + cost);
 }
