@@ -198,6 +198,7 @@ constexpr int kTaskCap = kMaxNodeDepth + 4;
 #endif
 constexpr int kSmall = RC_SMALL;  // subtrees up to this size are built from LDS
 constexpr int kMicro = 16;    // ranges of 5..16 go to the per-thread builder
+constexpr int kU = 4;         // chunks of 64 primitives loaded together by the passes over large ranges
 
 struct WaveBox {
     float lx, ly, lz, hx, hy, hz;
@@ -229,7 +230,6 @@ struct BuildShared {
     float box[6][kSmall];  // local mode: primitive bounds by slot
     int id[kSmall];        // local mode: environment-local id by slot
     int perm[kSmall];      // local mode: slot at each position
-    int perm2[kSmall];
     int ord[4][kSmall];    // local mode: slots of each task in each sweep order
     int side[kSmall];      // local mode: side of each slot in the current split
 };
@@ -502,40 +502,47 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
     // so n/5 + n/(kMicro + 1) + 1 <= n entries never meet.
     int4 *micro = v.micro + base;
 
-    // bounds of the primitive at list position i (global list or LDS copy)
-    auto box_at = [&](int i, float &lx, float &ly, float &lz, float &hx, float &hy, float &hz) {
-        if (local) {
-            const int slot = S.perm[i - b0];
-            lx = S.box[0][slot];
-            ly = S.box[1][slot];
-            lz = S.box[2][slot];
-            hx = S.box[3][slot];
-            hy = S.box[4][slot];
-            hz = S.box[5][slot];
-        } else {
-            const int p = prim[i];
-            const float4 lo = blo[p], hi = bhi[p];
-            lx = lo.x;
-            ly = lo.y;
-            lz = lo.z;
-            hx = hi.x;
-            hy = hi.y;
-            hz = hi.z;
+    // bounds of the primitive at list position i of the LDS copy (local mode)
+    auto local_box = [&](int i) {
+        const int slot = S.perm[i - b0];
+        return WaveBox{S.box[0][slot], S.box[1][slot], S.box[2][slot], S.box[3][slot], S.box[4][slot], S.box[5][slot]};
+    };
+    // Boxes of the global list at positions c + lane, c = g0 + 64 u (g0 - 64 u
+    // when down), u < kU, and the primitives there (-1 and the empty box
+    // outside [rb, re)): the loads of kU chunks are issued together, so a
+    // pass over a large range waits for one round trip per kU chunks.
+    auto load_boxes = [&](int g0, bool down, int rb, int re, WaveBox(&xs)[kU], int(&ps)[kU]) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = (down ? g0 - 64 * u : g0 + 64 * u) + lane;
+            ps[u] = (i >= rb && i < re) ? prim[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            xs[u] = kEmptyBox;
+            if (ps[u] >= 0) {
+                const float4 lo = blo[ps[u]], hi = bhi[ps[u]];
+                xs[u] = WaveBox{lo.x, lo.y, lo.z, hi.x, hi.y, hi.z};
+            }
         }
     };
-    auto reduce_range = [&](int b, int en) {
-        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-        for (int i = b + lane; i < en; i += 64) {
-            float a0, a1, a2, c0, c1, c2;
-            box_at(i, a0, a1, a2, c0, c1, c2);
-            lx = fminf(lx, a0);
-            ly = fminf(ly, a1);
-            lz = fminf(lz, a2);
-            hx = fmaxf(hx, c0);
-            hy = fmaxf(hy, c1);
-            hz = fmaxf(hz, c2);
+    auto reduce_range = [&](int rb, int re) {
+        WaveBox acc = kEmptyBox;
+        if (local) {
+            for (int i = rb + lane; i < re; i += 64)
+                acc = box_union(acc, local_box(i));
+        } else {
+            for (int g0 = rb; g0 < re; g0 += 64 * kU) {
+                WaveBox xs[kU];
+                int ps[kU];
+                load_boxes(g0, false, rb, re, xs, ps);
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    acc = box_union(acc, xs[u]);
+            }
         }
-        return WaveBox{wave_min(lx), wave_min(ly), wave_min(lz), wave_max(hx), wave_max(hy), wave_max(hz)};
+        return WaveBox{wave_min(acc.lx), wave_min(acc.ly), wave_min(acc.lz),
+                       wave_max(acc.hx), wave_max(acc.hy), wave_max(acc.hz)};
     };
 
     if (!JOB && n <= kLeafMax) {
@@ -622,23 +629,28 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
             if (!local) {
                 float cl0 = INFINITY, cl1 = INFINITY, cl2 = INFINITY, ch0 = -INFINITY, ch1 = -INFINITY, ch2 = -INFINITY;
                 WaveBox carry = kEmptyBox;
-                for (int c0 = b; c0 < en; c0 += 64) {
-                    const int i = c0 + lane;
-                    WaveBox x = kEmptyBox;
-                    if (i < en) {
-                        box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-                        const float cx = 0.5f * (x.lx + x.hx), cy = 0.5f * (x.ly + x.hy), cz = 0.5f * (x.lz + x.hz);
-                        cl0 = fminf(cl0, cx);
-                        cl1 = fminf(cl1, cy);
-                        cl2 = fminf(cl2, cz);
-                        ch0 = fmaxf(ch0, cx);
-                        ch1 = fmaxf(ch1, cy);
-                        ch2 = fmaxf(ch2, cz);
+                for (int g0 = b; g0 < en; g0 += 64 * kU) {
+                    WaveBox xs[kU];
+                    int ps[kU];
+                    load_boxes(g0, false, b, en, xs, ps);
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        const int i = g0 + 64 * u + lane;
+                        WaveBox x = xs[u];
+                        if (i < en) {
+                            const float cx = 0.5f * (x.lx + x.hx), cy = 0.5f * (x.ly + x.hy), cz = 0.5f * (x.lz + x.hz);
+                            cl0 = fminf(cl0, cx);
+                            cl1 = fminf(cl1, cy);
+                            cl2 = fminf(cl2, cz);
+                            ch0 = fmaxf(ch0, cx);
+                            ch1 = fmaxf(ch1, cy);
+                            ch2 = fmaxf(ch2, cz);
+                        }
+                        x = box_union(box_scan<true>(x, lane >> 4), carry);
+                        if (i < en)
+                            parea[i] = half_area(x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
+                        carry = box_lane(x, 63);
                     }
-                    x = box_union(box_scan<true>(x, lane >> 4), carry);
-                    if (i < en)
-                        parea[i] = half_area(x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-                    carry = box_lane(x, 63);
                 }
                 const float mn[3] = {wave_min(cl0), wave_min(cl1), wave_min(cl2)};
                 const float mx[3] = {wave_max(ch0), wave_max(ch1), wave_max(ch2)};
@@ -674,38 +686,49 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                 int ik = 0;
                 {
                     WaveBox carry = kEmptyBox;  // union of the positions after the current chunk
-                    for (int c0 = b + ((cnt - 1) & ~63); c0 >= b; c0 -= 64) {
-                        const int i = c0 + lane;
-                        WaveBox x = kEmptyBox;
-                        if (i < en) {
-                            box_at(i, x.lx, x.ly, x.lz, x.hx, x.hy, x.hz);
-                            const float cc[3] = {0.5f * (x.lx + x.hx), 0.5f * (x.ly + x.hy), 0.5f * (x.lz + x.hz)};
+                    for (int g0 = b + ((cnt - 1) & ~63); g0 >= b; g0 -= 64 * kU) {
+                        WaveBox xs[kU];
+                        int ps[kU];
+                        float pa[kU];
 #pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                if (scale[a] == 0.f)
-                                    continue;
-                                const int j = a * kBins + bin_of(cc[a], cmin[a], scale[a]);
-                                atomicAdd(&S.cnt[j], 1);
-                                atomicMin(&S.lo[3 * j + 0], f2o(x.lx));
-                                atomicMin(&S.lo[3 * j + 1], f2o(x.ly));
-                                atomicMin(&S.lo[3 * j + 2], f2o(x.lz));
-                                atomicMax(&S.hi[3 * j + 0], f2o(x.hx));
-                                atomicMax(&S.hi[3 * j + 1], f2o(x.hy));
-                                atomicMax(&S.hi[3 * j + 2], f2o(x.hz));
-                            }
+                        for (int u = 0; u < kU; ++u) {
+                            const int i = g0 - 64 * u + lane;
+                            pa[u] = (i >= b && i < en - 1) ? parea[i] : 0.f;
                         }
-                        x = box_scan<false>(x, lane >> 4);
-                        const WaveBox suf = box_union(x, carry);                    // positions i .. en - 1
-                        const WaveBox rn = box_union(box_shift<false>(x), carry);  // positions i + 1 .. en - 1
-                        if (i < en - 1) {
-                            const int k = i - b + 1;
-                            const float c = parea[i] * (float)k + half_area(rn.lx, rn.ly, rn.lz, rn.hx, rn.hy, rn.hz) * (float)(cnt - k);
-                            if (c < ic || (c == ic && k < ik)) {
-                                ic = c;
-                                ik = k;
+                        load_boxes(g0, true, b, en, xs, ps);
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int i = g0 - 64 * u + lane;
+                            WaveBox x = xs[u];
+                            if (i >= b && i < en) {
+                                const float cc[3] = {0.5f * (x.lx + x.hx), 0.5f * (x.ly + x.hy), 0.5f * (x.lz + x.hz)};
+#pragma unroll
+                                for (int a = 0; a < 3; ++a) {
+                                    if (scale[a] == 0.f)
+                                        continue;
+                                    const int j = a * kBins + bin_of(cc[a], cmin[a], scale[a]);
+                                    atomicAdd(&S.cnt[j], 1);
+                                    atomicMin(&S.lo[3 * j + 0], f2o(x.lx));
+                                    atomicMin(&S.lo[3 * j + 1], f2o(x.ly));
+                                    atomicMin(&S.lo[3 * j + 2], f2o(x.lz));
+                                    atomicMax(&S.hi[3 * j + 0], f2o(x.hx));
+                                    atomicMax(&S.hi[3 * j + 1], f2o(x.hy));
+                                    atomicMax(&S.hi[3 * j + 2], f2o(x.hz));
+                                }
                             }
+                            x = box_scan<false>(x, lane >> 4);
+                            const WaveBox suf = box_union(x, carry);                    // positions i .. en - 1
+                            const WaveBox rn = box_union(box_shift<false>(x), carry);  // positions i + 1 .. en - 1
+                            if (i >= b && i < en - 1) {
+                                const int k = i - b + 1;
+                                const float c = pa[u] * (float)k + half_area(rn.lx, rn.ly, rn.lz, rn.hx, rn.hy, rn.hz) * (float)(cnt - k);
+                                if (c < ic || (c == ic && k < ik)) {
+                                    ic = c;
+                                    ik = k;
+                                }
+                            }
+                            carry = box_lane(suf, 0);
                         }
-                        carry = box_lane(suf, 0);
                     }
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
@@ -785,42 +808,51 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                     R = WaveBox{__shfl(br.lx, src, 64), __shfl(br.ly, src, 64), __shfl(br.lz, src, 64),
                                 __shfl(br.hx, src, 64), __shfl(br.hy, src, 64), __shfl(br.hz, src, 64)};
                     mid = b + nL;
-                    // stable partition, then copy back
+                    // stable partition into tmp, then copy back (global list only:
+                    // local mode always takes the sweep)
                     int lc = 0, rc = 0;
                     const float cm = cmin[best_axis], sc = scale[best_axis];
-                    for (int c0 = b; c0 < en; c0 += 64) {
-                        const int i = c0 + lane;
-                        const bool valid = i < en;
-                        float cc = 0.f;
-                        int item = 0;
-                        if (valid) {
-                            float a0, a1, a2, d0, d1, d2;
-                            box_at(i, a0, a1, a2, d0, d1, d2);
-                            cc = best_axis == 0 ? 0.5f * (a0 + d0) : (best_axis == 1 ? 0.5f * (a1 + d1) : 0.5f * (a2 + d2));
-                            item = local ? S.perm[i - b0] : prim[i];
+                    for (int g0 = b; g0 < en; g0 += 64 * kU) {
+                        WaveBox xs[kU];
+                        int ps[kU];
+                        load_boxes(g0, false, b, en, xs, ps);
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int c0 = g0 + 64 * u;
+                            if (c0 >= en)
+                                break;
+                            const int i = c0 + lane;
+                            const bool valid = i < en;
+                            const WaveBox &x = xs[u];
+                            const float cc = best_axis == 0 ? 0.5f * (x.lx + x.hx)
+                                                            : (best_axis == 1 ? 0.5f * (x.ly + x.hy) : 0.5f * (x.lz + x.hz));
+                            const bool left = valid && bin_of(cc, cm, sc) <= best_k;
+                            const uint64_t m = __ballot(left);
+                            const uint64_t below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
+                            const int rank = __popcll(below);
+                            const int nvalid = min(64, en - c0);
+                            const int dst = left ? b + lc + rank : mid + rc + (lane - rank);
+                            if (valid)
+                                tmp[dst] = ps[u];
+                            const int cl = __popcll(m);
+                            lc += cl;
+                            rc += nvalid - cl;
                         }
-                        const bool left = valid && bin_of(cc, cm, sc) <= best_k;
-                        const uint64_t m = __ballot(left);
-                        const uint64_t below = lane == 0 ? 0ull : (m & (~0ull >> (64 - lane)));
-                        const int rank = __popcll(below);
-                        const int nvalid = min(64, en - c0);
-                        const int dst = left ? b + lc + rank : mid + rc + (lane - rank);
-                        if (valid) {
-                            if (local)
-                                S.perm2[dst - b0] = item;
-                            else
-                                tmp[dst] = item;
-                        }
-                        const int cl = __popcll(m);
-                        lc += cl;
-                        rc += nvalid - cl;
                     }
                     __syncthreads();
-                    for (int i = b + lane; i < en; i += 64) {
-                        if (local)
-                            S.perm[i - b0] = S.perm2[i - b0];
-                        else
-                            prim[i] = tmp[i];
+                    for (int g0 = b; g0 < en; g0 += 64 * kU) {
+                        int t[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int i = g0 + 64 * u + lane;
+                            t[u] = i < en ? tmp[i] : 0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            const int i = g0 + 64 * u + lane;
+                            if (i < en)
+                                prim[i] = t[u];
+                        }
                     }
                     __syncthreads();
                 }
