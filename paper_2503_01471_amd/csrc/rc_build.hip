@@ -44,9 +44,11 @@ __device__ __forceinline__ float expand_hi(float x)
 // DPP lane moves (gfx9 encodings): row_shr:n = 0x110 + n and row_shl:n =
 // 0x100 + n within rows of 16 lanes, wave_shr:1 = 0x138 and wave_shl:1 = 0x130
 // across the wavefront.  Lane i reads lane i - n (shr) or i + n (shl); a lane
-// whose source lies outside its row (or the wavefront) keeps `old`.  Every
-// cross-lane helper below is called from uniform control flow with all 64
-// lanes active.
+// whose source lies outside its row (or the wavefront) keeps `old`.  The
+// wavefront helpers below (scans, reductions, readlane) are called from
+// uniform control flow with all 64 lanes active; the row helpers (row_scan,
+// row_xor and the 16-lane group operations built on them) read only their own
+// row and need its 16 lanes active.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float old, float x)
 {
@@ -89,6 +91,46 @@ __device__ __forceinline__ float lane_scan(float x, int row)
     const float r1 = mm<MIN>(r2, readlane_f(x, 16));
     return mm<MIN>(x, row == 3 ? id : (row == 2 ? r3 : (row == 1 ? r2 : r1)));
 }
+// Value of lane l ^ M within the lane's row of 16 (gl = l mod 16): quad_perm
+// [1,0,3,2] (M = 1) and [2,3,0,1] (M = 2), row_ror:8 (M = 8), and for M = 4
+// row_shl:4 or row_shr:4 by the lane's bit 2.
+template <int M>
+__device__ __forceinline__ int row_xor(int x, int gl)
+{
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8, "partner within the row");
+    if (M == 1)
+        return __builtin_amdgcn_update_dpp(x, x, 0xb1, 0xf, 0xf, false);
+    if (M == 2)
+        return __builtin_amdgcn_update_dpp(x, x, 0x4e, 0xf, 0xf, false);
+    if (M == 8)
+        return __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);
+    const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xf, 0xf, false);
+    const int dn = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false);
+    return (gl & 4) ? dn : up;
+}
+template <int M>
+__device__ __forceinline__ float row_xor_f(float x, int gl) { return __int_as_float(row_xor<M>(__float_as_int(x), gl)); }
+
+// Lexicographic minimum of (c, w) over the wavefront, left in every lane:
+// partners 1..8 through DPP, 16 and 32 through ds_bpermute.
+__device__ __forceinline__ void take_min(float &c, int &w, float oc, int ow)
+{
+    if (oc < c || (oc == c && ow < w)) {
+        c = oc;
+        w = ow;
+    }
+}
+__device__ __forceinline__ void wave_argmin(float &c, int &w, int lane)
+{
+    const int gl = lane & 15;
+    take_min(c, w, row_xor_f<1>(c, gl), row_xor<1>(w, gl));
+    take_min(c, w, row_xor_f<2>(c, gl), row_xor<2>(w, gl));
+    take_min(c, w, row_xor_f<4>(c, gl), row_xor<4>(w, gl));
+    take_min(c, w, row_xor_f<8>(c, gl), row_xor<8>(w, gl));
+    take_min(c, w, __shfl_xor(c, 16, 64), __shfl_xor(w, 16, 64));
+    take_min(c, w, __shfl_xor(c, 32, 64), __shfl_xor(w, 32, 64));
+}
+
 template <bool MIN>
 __device__ __forceinline__ float lane_reduce(float x)
 {
@@ -294,6 +336,28 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Partner j < 16 through DPP (j is a compile-time constant after unrolling).
+__device__ __forceinline__ uint64_t row_xor_u64(uint64_t x, int j, int lane)
+{
+    const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
+    const int gl = lane & 15;
+    int olo, ohi;
+    if (j == 1) {
+        olo = row_xor<1>(lo, gl);
+        ohi = row_xor<1>(hi, gl);
+    } else if (j == 2) {
+        olo = row_xor<2>(lo, gl);
+        ohi = row_xor<2>(hi, gl);
+    } else if (j == 4) {
+        olo = row_xor<4>(lo, gl);
+        ohi = row_xor<4>(hi, gl);
+    } else {
+        olo = row_xor<8>(lo, gl);
+        ohi = row_xor<8>(hi, gl);
+    }
+    return ((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo;
+}
+
 template <int E>
 __device__ __forceinline__ void wave_sort(uint64_t (&key)[E], int lane)
 {
@@ -316,7 +380,7 @@ __device__ __forceinline__ void wave_sort(uint64_t (&key)[E], int lane)
             } else {
 #pragma unroll
                 for (int h = 0; h < E; ++h) {
-                    const uint64_t o = shfl_xor_u64(key[h], j);
+                    const uint64_t o = j < 16 ? row_xor_u64(key[h], j, lane) : shfl_xor_u64(key[h], j);
                     const int i = 64 * h + lane;
                     const bool keep_min = ((i & k) == 0) == ((i & j) == 0);
                     key[h] = keep_min == (o < key[h]) ? o : key[h];
@@ -403,15 +467,7 @@ __device__ int sweep_split(BuildShared &S, int pb, int cnt, int lane, WaveBox &L
     }
     float bc = best_c;
     int bw = best_w;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const float oc = __shfl_xor(bc, o, 64);
-        const int ow = __shfl_xor(bw, o, 64);
-        if (oc < bc || (oc == bc && ow < bw)) {
-            bc = oc;
-            bw = ow;
-        }
-    }
+    wave_argmin(bc, bw, lane);
     if (!(bc < INFINITY))
         return 0;
     bw = __builtin_amdgcn_readfirstlane(bw);
@@ -730,15 +786,7 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                             carry = box_lane(suf, 0);
                         }
                     }
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const float oc = __shfl_xor(ic, o, 64);
-                        const int ok = __shfl_xor(ik, o, 64);
-                        if (oc < ic || (oc == ic && ok < ik)) {
-                            ic = oc;
-                            ik = ok;
-                        }
-                    }
+                    wave_argmin(ic, ik, lane);
                 }
                 __syncthreads();
                 // evaluate the 3 x (kBins-1) split planes, plane index pl = lane,
@@ -785,15 +833,7 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                 }
                 // argmin over lanes, ties to the lower plane index
                 float bc = cost;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const float oc = __shfl_xor(bc, o, 64);
-                    const int ow = __shfl_xor(bw, o, 64);
-                    if (oc < bc || (oc == bc && ow < bw)) {
-                        bc = oc;
-                        bw = ow;
-                    }
-                }
+                wave_argmin(bc, bw, lane);
                 if (ic < bc) {  // cut in id order: both sides are already contiguous
                     mid = b + ik;
                     L = reduce_range(b, mid);
@@ -801,12 +841,10 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                 } else if (bc < INFINITY) {
                     best_axis = bw / (kBins - 1);
                     best_k = bw % (kBins - 1);
-                    const int src = bw & 63;  // the lane that evaluated plane bw
-                    const int nL = __shfl(nl, src, 64);
-                    L = WaveBox{__shfl(bl.lx, src, 64), __shfl(bl.ly, src, 64), __shfl(bl.lz, src, 64),
-                                __shfl(bl.hx, src, 64), __shfl(bl.hy, src, 64), __shfl(bl.hz, src, 64)};
-                    R = WaveBox{__shfl(br.lx, src, 64), __shfl(br.ly, src, 64), __shfl(br.lz, src, 64),
-                                __shfl(br.hx, src, 64), __shfl(br.hy, src, 64), __shfl(br.hz, src, 64)};
+                    const int src = __builtin_amdgcn_readfirstlane(bw) & 63;  // the lane that evaluated plane bw
+                    const int nL = __builtin_amdgcn_readlane(nl, src);
+                    L = box_lane(bl, src);
+                    R = box_lane(br, src);
                     mid = b + nL;
                     // stable partition into tmp, then copy back (global list only:
                     // local mode always takes the sweep)
@@ -981,26 +1019,6 @@ __global__ __launch_bounds__(64) void k_build_local(BuildView v)
 // ---------------------------------------------------------------------------
 constexpr int kMicroBlock = 256;
 constexpr int kGroup = 16;
-
-// A group is one DPP row.  Value of lane gl ^ M of the row: quad_perm
-// [1,0,3,2] (M = 1) and [2,3,0,1] (M = 2), row_ror:8 (M = 8), and for M = 4
-// row_shl:4 or row_shr:4 by the lane's bit 2.
-template <int M>
-__device__ __forceinline__ int row_xor(int x, int gl)
-{
-    static_assert(M == 1 || M == 2 || M == 4 || M == 8, "partner within the row");
-    if (M == 1)
-        return __builtin_amdgcn_update_dpp(x, x, 0xb1, 0xf, 0xf, false);
-    if (M == 2)
-        return __builtin_amdgcn_update_dpp(x, x, 0x4e, 0xf, 0xf, false);
-    if (M == 8)
-        return __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);
-    const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xf, 0xf, false);
-    const int dn = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false);
-    return (gl & 4) ? dn : up;
-}
-template <int M>
-__device__ __forceinline__ float row_xor_f(float x, int gl) { return __int_as_float(row_xor<M>(__float_as_int(x), gl)); }
 
 // Compare-exchange of the bitonic network: partner lane gl ^ j, block size k.
 template <int K, int J>
