@@ -1373,7 +1373,28 @@ __device__ __forceinline__ void leaf_box(const TriRec *recs, int ref, float b[6]
     const int code = ~ref;
     const int first = code >> 3, cnt = (code & 7) + 1;
     float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-    for (int k = 0; k < cnt; ++k) {
+    // The first kLeafMax records are loaded together (a missing one re-reads
+    // the last record, which leaves the union unchanged): one memory round
+    // trip per leaf instead of one per triangle.
+    float4 ra[kLeafMax], rb[kLeafMax];
+    float rc[kLeafMax];
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) {
+        const TriRec *t = recs + first + (k < cnt ? k : cnt - 1);
+        ra[k] = t->a;
+        rb[k] = t->b;
+        rc[k] = t->c.x;
+    }
+#pragma unroll
+    for (int k = 0; k < kLeafMax; ++k) {
+        lx = fminf(lx, fminf(fminf(ra[k].x, ra[k].w), rb[k].z));
+        ly = fminf(ly, fminf(fminf(ra[k].y, rb[k].x), rb[k].w));
+        lz = fminf(lz, fminf(fminf(ra[k].z, rb[k].y), rc[k]));
+        hx = fmaxf(hx, fmaxf(fmaxf(ra[k].x, ra[k].w), rb[k].z));
+        hy = fmaxf(hy, fmaxf(fmaxf(ra[k].y, rb[k].x), rb[k].w));
+        hz = fmaxf(hz, fmaxf(fmaxf(ra[k].z, rb[k].y), rc[k]));
+    }
+    for (int k = kLeafMax; k < cnt; ++k) {  // larger leaves (the encoding admits 8)
         const TriRec r = recs[first + k];
         lx = fminf(lx, fminf(fminf(r.a.x, r.a.w), r.b.z));
         ly = fminf(ly, fminf(fminf(r.a.y, r.b.x), r.b.w));
