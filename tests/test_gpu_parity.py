@@ -335,16 +335,35 @@ def test_stereo_shadows():
 
 
 def test_deterministic():
+    """Two SAH builds of the same scene give byte-identical BVHs and renders.
+    The subtrees of at most 128 primitives and the 5-16 primitive ranges are
+    handed to their kernels through lists whose order depends on scheduling
+    (atomic appends); every task writes only the node ids reserved for it, so
+    the trees must not depend on that order.  A cfg3 slice defers about sixty
+    subtrees per environment, a cfg2 slice mixes small and large rooms."""
     from paper_2503_01471_amd import rc
     _need_gpu()
-    scene = S.make_cfg2(n_envs=4, W=160, H=90)
-    R = _renderer(scene)
-    a = _host(R.render(mode=rc.RC_RENDER_BATCHED))
-    R.build()
-    b = _host(R.render(mode=rc.RC_RENDER_BATCHED))
-    for k in ("depth", "seg", "tri"):
-        assert np.array_equal(a[k], b[k])
-    R.close()
+    for scene in (S.make_cfg2(n_envs=4, W=160, H=90), S.make_cfg3(n_envs=6, azimuths=64, channels=16)):
+        _say(f"determinism {scene.name}: envs={scene.n_envs}")
+        R = _renderer(scene)
+        off = R.env_tri_off
+
+        def trees():
+            return [rc.rc_debug_bvh(R.ctx, e, int(off[e + 1] - off[e])) for e in range(scene.n_envs)]
+
+        ta = trees()
+        a = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+        R.build()
+        torch.cuda.synchronize()
+        tb = trees()
+        b = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+        for x, y in zip(ta, tb):
+            assert x["n_nodes"] == y["n_nodes"] and x["root"] == y["root"]
+            for k in ("boxes", "children", "parent", "leaf_ids"):
+                assert np.array_equal(x[k], y[k]), k
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(a[k], b[k])
+        R.close()
 
 
 def test_edge_cases():
