@@ -111,6 +111,8 @@ BuildView Scene::view() const
     v.nodes = nodes.as<Node>();
     v.recs = recs.as<TriRec>();
     v.pos_of = pos_of.as<int32_t>();
+    v.leaf_src = leaf_src.as<int4>();
+    v.inst_dyn = inst_dyn.as<uint8_t>();
     v.env_root = env_root.as<int32_t>();
     v.env_nodes = env_nodes.as<int32_t>();
     v.env_micro = env_micro.as<int32_t>();
@@ -443,6 +445,7 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->env_local, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->local_off, 8 * ((size_t)n_envs + 1)));
     RC_TRY(c->pool.alloc(sc->sah_mask, (size_t)n_envs + 16));
+    RC_TRY(c->pool.alloc(sc->leaf_src, 16 * N));
     RC_HIP(hipStreamSynchronize(st));
     c->sensors.reset();
     c->scene = std::move(sc);
@@ -637,6 +640,8 @@ rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, vo
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
     RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
+    if (!d_env_mask)
+        sc.world_stale = false;
     if (builder == RC_BUILD_LBVH)
         RC_HIP(launch_build_lbvh(v, sc.sah_mask.as<uint8_t>(), st));
     else
@@ -656,8 +661,23 @@ rc_status rc_refit(rc_context *c, const uint8_t *d_env_mask, void *stream)
     hipStream_t st = pick(c, stream);
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
-    RC_HIP(launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, st));
+    if (sc.n_dyn > 0) {
+        RC_HIP(launch_transform_leaf(v, st));
+        sc.world_stale = true;
+    }
     RC_HIP(launch_refit(v, st));
+    return RC_OK;
+}
+
+// Brings the original-order world copy up to date (on stream st) if a
+// per-step transform left it stale.
+static rc_status fresh_world(rc_context *c, hipStream_t st)
+{
+    Scene &sc = *c->scene;
+    if (sc.world_stale) {
+        RC_HIP(launch_transform(sc.view(), nullptr, sc.n_tris, false, st));
+        sc.world_stale = false;
+    }
     return RC_OK;
 }
 
@@ -686,6 +706,8 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
     const OutView ov = out_view(*out);
     const bool extras = out->normal || out->bary || out->point || out->vert;
     RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
+    if (mode == RC_RENDER_BRUTE || extras || out->shadow)
+        RC_TRY(fresh_world(c, st));
     switch (mode) {
     case RC_RENDER_PLAIN:
         for (int64_t s = 0; s < se.n_si; ++s)
@@ -735,6 +757,7 @@ rc_status rc_debug_world(rc_context *c, float *tris9)
     if (!c->scene || !c->scene->built)
         return fail(RC_E_STATE, "no built scene");
     RC_TRY(set_device(c));
+    RC_TRY(fresh_world(c, c->stream));
     RC_HIP(hipStreamSynchronize(c->stream));
     RC_HIP(hipMemcpy(tris9, c->scene->world.p, 36 * c->scene->n_tris, hipMemcpyDeviceToHost));
     return RC_OK;

@@ -19,6 +19,7 @@ struct rc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     DBuf step;
+    bool world_kept = false;  // the graph refreshes the original-order world copy itself
 };
 
 namespace {
@@ -196,8 +197,13 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
     if (e == hipSuccess) {
         hipError_t k = launch_move(sc.n_inst, sc.inst_T0.as<float>(), d_vel, sc.inst_dyn.as<uint8_t>(), 0,
                                    g->step.as<int32_t>(), dt, sc.inst_T.as<float>(), cs);
-        if (k == hipSuccess)
-            k = launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, cs);
+        // With the further outputs or shadows in the graph (they read the
+        // original-order world copy) both copies are transformed; otherwise
+        // the leaf-ordered records only.
+        g->world_kept = extras || out->shadow;
+        if (k == hipSuccess && sc.n_dyn > 0)
+            k = g->world_kept ? launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, cs)
+                              : launch_transform_leaf(v, cs);
         if (k == hipSuccess)
             k = launch_refit(v, cs);
         if (k == hipSuccess)
@@ -238,6 +244,8 @@ rc_status rc_graph_launch(rc_graph *g, void *stream)
         return fail(RC_E_STATE, "the scene, sensors or tuning changed after the graph was captured");
     RC_TRY(set_device(g->ctx));
     RC_HIP(hipGraphLaunch(g->exec, stream ? (hipStream_t)stream : g->ctx->stream));
+    if (!g->world_kept && g->ctx->scene->n_dyn > 0)
+        g->ctx->scene->world_stale = true;
     return RC_OK;
 }
 

@@ -182,6 +182,39 @@ __global__ __launch_bounds__(256) void k_transform(BuildView v, const int32_t *_
     }
 }
 
+// K1b: the per-step form of K1 for a built scene: one thread per leaf-ordered
+// record, so reads and writes are coalesced; a record of a static instance is
+// left as it is.  Same arithmetic as K1, so the record is bit-identical to
+// the one K1 writes.  The original-order world copy is not updated (the
+// library refreshes it before a path that reads it).
+__global__ __launch_bounds__(256) void k_transform_leaf(BuildView v)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // a record stays inside its environment's range, so tri_env[p] is its environment
+    if (p >= v.n_tris || masked_out(v, v.tri_env[p]))
+        return;
+    const int4 src = v.leaf_src[p];
+    if (!v.inst_dyn[src.x])
+        return;
+    const float *A = v.inst_T + 12 * (int64_t)src.x;
+    float w[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int vi = v.proto_tri[3 * (int64_t)src.y + c];
+        const float x = v.proto_xyz[3 * (int64_t)vi + 0];
+        const float y = v.proto_xyz[3 * (int64_t)vi + 1];
+        const float z = v.proto_xyz[3 * (int64_t)vi + 2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            w[3 * c + r] = fmaf(A[4 * r + 0], x, fmaf(A[4 * r + 1], y, fmaf(A[4 * r + 2], z, A[4 * r + 3])));
+    }
+    TriRec rec;
+    rec.a = make_float4(w[0], w[1], w[2], w[3]);
+    rec.b = make_float4(w[4], w[5], w[6], w[7]);
+    rec.c = make_float4(w[8], __int_as_float(src.z), 0.f, 0.f);
+    v.recs[p] = rec;
+}
+
 // K8: constant-velocity motion of dynamic instances.
 // The step comes from d_step when it is set (a captured step graph advances
 // it on the device), else from the argument.
@@ -1356,6 +1389,8 @@ __global__ __launch_bounds__(256) void k_gather(BuildView v)
     rec.c = make_float4(w[8], __int_as_float(id), 0.f, 0.f);
     v.recs[g] = rec;
     v.pos_of[base + id] = i;
+    const int2 src = v.tri_src[base + id];
+    v.leaf_src[g] = make_int4(src.x, src.y, id, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1702,6 +1737,14 @@ hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t
     if (n == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_transform, dim3(blocks_for(n, 256)), dim3(256), 0, st, v, tri_list, n, (int)to_recs);
+    return hipGetLastError();
+}
+
+hipError_t launch_transform_leaf(const BuildView &v, hipStream_t st)
+{
+    if (v.n_tris == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_transform_leaf, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
     return hipGetLastError();
 }
 

@@ -132,6 +132,8 @@ struct BuildView {
     Node *nodes;                 // env e starts at node_base(env_tri_off[e], e)
     TriRec *recs;                // [N]
     int32_t *pos_of;             // [N] leaf position of env-local id
+    int4 *leaf_src;              // [N] leaf order: instance, prototype triangle, env-local id, 0
+    const uint8_t *inst_dyn;     // [I] dynamic flag per instance
     int32_t *env_root;           // [E]
     int32_t *env_nodes;          // [E] node slots per environment
     int32_t *env_micro;          // [E] deferred small ranges per environment
@@ -152,6 +154,9 @@ __host__ __device__ inline bool masked_out(const BuildView &v, int e) { return v
 // ---------------------------------------------------------------------------
 hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t n, bool to_recs,
                             hipStream_t st);
+// The dynamic instances' triangles straight into their leaf-ordered records
+// (the original-order world copy is not written).
+hipError_t launch_transform_leaf(const BuildView &v, hipStream_t st);
 hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step,
                        const int32_t *d_step, float dt, float *T, hipStream_t st);
 hipError_t launch_bump(int32_t *d_step, hipStream_t st);

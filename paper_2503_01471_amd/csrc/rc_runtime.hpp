@@ -76,8 +76,14 @@ struct Scene {
     DBuf world, box_lo, box_hi, prim, tmp, nodes, recs, pos_of, env_root, env_nodes, env_micro, micro;
     DBuf level_nodes, level_off, micro_off, env_local, local_off;
     DBuf sah_mask;  // LBVH builds: environments left to the SAH kernels
+    DBuf leaf_src;  // leaf order: instance, prototype triangle, env-local id, 0 (written by the build)
     bool poses_set = false;
     bool built = false;
+    // The per-step transform writes the leaf-ordered records only; the
+    // original-order world copy (read by the brute-force render, the further
+    // outputs, the stereo shadows and the debug readback) is then stale until
+    // refreshed by fresh_world().
+    bool world_stale = false;
     BuildView view() const;
     SceneView sview() const;
 };

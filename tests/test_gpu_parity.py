@@ -142,6 +142,56 @@ def test_cfg4_motion_refit_equals_rebuild():
     R.close()
 
 
+def test_motion_world_copy():
+    """The per-step transform updates only the leaf-ordered records and leaves
+    the original-order world copy stale; every path that reads that copy must
+    see the moved geometry.  After a move and refit: the brute-force render
+    (first reader) equals the batched render bit for bit, the further outputs
+    match the oracle at the moved poses, and the debug readback equals the
+    oracle's world.  The same after replays of a step graph captured without
+    further outputs (its transform also writes the records only)."""
+    from paper_2503_01471_amd import rc
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=5, env_ids=None)
+    R = _renderer(scene)
+    base = dict(depth=True, seg=True, tri=True, hit=True)
+    for step in (7, 60):
+        _say(f"world copy after move + refit, step {step}")
+        R.move(step)
+        R.refit()
+        brute = _host(R.render(mode=rc.RC_RENDER_BRUTE, **base))
+        batched = _host(R.render(mode=rc.RC_RENDER_BATCHED, **base))
+        for k in brute:
+            if brute[k] is not None:
+                assert np.array_equal(brute[k], batched[k], equal_nan=brute[k].dtype.kind == "f"), (step, k)
+        R.move(step + 1)
+        R.refit()
+        ext = _host(R.render(mode=rc.RC_RENDER_BATCHED, normal=True, bary=True, point=True, vert=True, **base))
+        w = O.world(scene, O.moved_poses(scene, step + 1))
+        rep = parity.compare_extras(ext, O.render(scene, w))
+        print(rep, flush=True)
+        parity.assert_extras(rep)
+        assert np.array_equal(rc.rc_debug_world(R.ctx, R.n_tris), w.tris), step
+    n = R.total_rays
+    gout = dict(depth=torch.empty(n, device="cuda"), seg=torch.empty(n, dtype=torch.int32, device="cuda"),
+                tri=torch.empty(n, dtype=torch.int32, device="cuda"))
+    g = rc.rc_step_graph_create(R.ctx, R.inst_vel, float(scene.dt), depth=gout["depth"], seg=gout["seg"],
+                                tri=gout["tri"], total_rays=n)
+    rc.rc_graph_set_step(g, 20)
+    for step in (20, 21):
+        _say(f"world copy after graph replay, step {step}")
+        rc.rc_graph_launch(g)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in gout.items()}
+        brute = _host(R.render(mode=rc.RC_RENDER_BRUTE, depth=True, seg=True, tri=True))
+        for k in got:
+            assert np.array_equal(got[k], brute[k], equal_nan=True), (step, k)
+        w = O.world(scene, O.moved_poses(scene, step))
+        assert np.array_equal(rc.rc_debug_world(R.ctx, R.n_tris), w.tris), step
+    rc.rc_graph_destroy(g)
+    R.close()
+
+
 def _mix_poses(scene, new, old, envs):
     """Instance poses: `new` for the instances of `envs`, `old` elsewhere."""
     T = np.array(old, np.float32, copy=True).reshape(-1, 12)
