@@ -3,11 +3,12 @@
 // Paper, Sec. III-D: every sub-mesh of environment i is moved by its own
 // transform and a BVH is computed over the transformed mesh; the paper
 // rebuilds it when static environments are randomised.  Here the build is a
-// surface-area-heuristic builder with one wavefront per environment (all
-// environments in one launch): binned splits for large nodes, exact sweeps
-// over sorted centroids for nodes of at most kSmall primitives and, in a
-// second kernel, for the subtrees of 5..16 primitives; plus a bottom-up refit
-// on the fixed topology for moving instances.
+// surface-area-heuristic builder over all environments at once: one wavefront
+// per environment takes the binned splits of the large nodes, then one
+// wavefront per subtree of at most kSmall primitives takes exact sweeps over
+// sorted centroids, and one 16-lane group per subtree of 5..16 primitives
+// finishes it; plus a bottom-up refit on the fixed topology for moving
+// instances.
 #include "rc_common.hpp"
 
 namespace rc {
