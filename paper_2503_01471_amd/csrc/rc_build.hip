@@ -1204,7 +1204,9 @@ __device__ __forceinline__ int micro_cap(int dd)
 // primitives (a superset of the sweep's candidates): lane j costs the
 // partition whose left side is the bit set of j + 1 (primitive c - 1 always
 // right, so each partition once).
-__device__ __forceinline__ bool micro_leaf(const WaveBox &bx, int gl, int first, int c, int dd)
+// gbox: the group's boxes in LDS, lane r's at gbox[r] (lo.x lo.y lo.z hi.x,
+// hi.y hi.z).
+__device__ __forceinline__ bool micro_leaf(const float4 (*gbox)[2], int gl, int first, int c, int dd)
 {
     static_assert(kLeafMax <= 5, "2^(kLeafMax-1) - 1 partitions must fit in the 16-lane group");
     if (c <= 1 || dd >= kMaxNodeDepth)  // a split would put a node below the depth bound
@@ -1213,8 +1215,11 @@ __device__ __forceinline__ bool micro_leaf(const WaveBox &bx, int gl, int first,
     WaveBox U = kEmptyBox;
 #pragma unroll
     for (int i = 0; i < kLeafMax; ++i) {
-        const WaveBox t = box_shfl(bx, (first + i) & (kGroup - 1));
-        B[i] = i < c ? t : kEmptyBox;
+        B[i] = kEmptyBox;
+        if (i < c) {  // group-uniform: every lane reads the same slot
+            const float4 a = gbox[first + i][0], b = gbox[first + i][1];
+            B[i] = WaveBox{a.x, a.y, a.z, a.w, b.x, b.y};
+        }
         U = box_union(U, B[i]);
     }
     const int m = gl + 1;
@@ -1243,6 +1248,9 @@ __device__ __forceinline__ bool micro_leaf(const WaveBox &bx, int gl, int first,
 
 __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
 {
+    // each lane's current box, for the leaf tests' reads of the group's boxes
+    __shared__ float4 sbox[kMicroBlock][2];
+    const float4(*gbox)[2] = sbox + (threadIdx.x & ~(kGroup - 1));
     const int gl = threadIdx.x & (kGroup - 1);
     const int64_t n_groups = ((int64_t)gridDim.x * kMicroBlock) / kGroup;
     const int64_t total = v.micro_off[v.n_envs];
@@ -1288,11 +1296,13 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
                 bx = nb;
                 pid = np;
             }
+            sbox[threadIdx.x][0] = make_float4(bx.lx, bx.ly, bx.lz, bx.hx);
+            sbox[threadIdx.x][1] = make_float4(bx.hy, bx.hz, 0.f, 0.f);
             const int cf[2] = {f, f + k}, cc[2] = {k, c - k};
             int ref[2];
 #pragma unroll
             for (int sd = 0; sd < 2; ++sd) {
-                if (cc[sd] <= kLeafMax && micro_leaf(bx, gl, cf[sd], cc[sd], dd + 1)) {
+                if (cc[sd] <= kLeafMax && micro_leaf(gbox, gl, cf[sd], cc[sd], dd + 1)) {
                     ref[sd] = leaf_ref(task.y + cf[sd], cc[sd]);
                 } else {
                     ref[sd] = next++;
