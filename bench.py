@@ -431,8 +431,8 @@ def main():
     ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); environments shard across GPUs "
-              "with no exchange, so a multi-GPU run is not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): environments shard across GPUs "
+              "with no exchange, so N GPUs run N independent copies of the one-GPU job.", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench needs a HIP device"
