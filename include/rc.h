@@ -178,6 +178,11 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /* Every builder gives the same render results (the nearest hit is exact).  */
 /* rc_refit re-transforms the dynamic instances and recomputes the bounds    */
 /* bottom-up on the fixed topology.  Both are asynchronous on `stream`.      */
+/* rc_refit (and a step graph without further outputs or shadows) updates   */
+/* the leaf-ordered triangle records the traversal reads; the library's     */
+/* original-order world copy is refreshed by the next call that reads it   */
+/* (RC_RENDER_BRUTE, the further outputs and shadows of rc_render,          */
+/* rc_debug_world), which first enqueues the transform on its own stream.   */
 /* An unknown builder is RC_E_INVALID.                                       */
 /* d_env_mask: NULL (every environment) or a caller DEVICE uint8[n_envs],    */
 /* read on `stream`; environments whose byte is 0 are left exactly as they  */
@@ -222,6 +227,8 @@ rc_status rc_refit(rc_context *ctx, const uint8_t *d_env_mask, void *stream);
 /*          hidden iff one meets p + s (c2 - p) at s in [2^-13, 1] (the lower */
 /*          bound keeps the surface around p from shadowing itself).         */
 /* normal, bary, point, vert and shadow need the tri output (RC_E_INVALID). */
+/* RC_RENDER_BRUTE, the further outputs and shadows read the world copy:     */
+/* after an rc_refit they first bring it up to date on `stream`.            */
 /* The nearest hit is the smallest t in [near_, far_] over every triangle of */
 /* the ray's environment (two-sided; equal t resolved by the lower triangle  */
 /* id).  Every mode computes bit-identical outputs:                          */
