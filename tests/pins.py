@@ -444,6 +444,59 @@ def pin_rays():
     return fails
 
 
+def pin_table_rays(seed=0):
+    """Direction-table sensors (user-defined projection models): each beam r
+    travels along R table[r] from the pose's origin.  Inside an axis-aligned
+    room (a scaled box whose corners are exact in FP32), the range of every
+    beam is the FP64 slab exit distance along that direction; from a pose
+    rotated about z only, over the ground plane, the range of a downward beam
+    is h / (-table_z), because such a pose leaves the z component unchanged."""
+    fails = []
+    rng = np.random.default_rng(seed)
+    W, H = 16, 12
+    dirs = rng.normal(size=(W * H, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    dirs = dirs.astype(np.float32)
+    sens = S.table_sensor(dirs, W, H, near=0.01, far=100.0)
+    L = np.array([7.0, 4.0, 3.0])
+    c = np.array([1.0, -2.0, 1.5])
+    lo, hi = c - L / 2, c + L / 2
+    room = S.affine(np.diag(L), c)
+    p = np.array([1.75, -1.25, 0.875])
+    for yaw, pitch, roll in ((0.3, 0.2, -0.1), (2.2, -0.4, 0.6), (0.0, 0.0, 0.0)):
+        sc = S.custom_scene([S.box_mesh()], [([(0, 0, room, 0, (0, 0, 0))],
+                                              [(0, S.sensor_pose(S.rot_zyx(yaw, pitch, roll), p))])], [sens])
+        r = O.render(sc, nthreads=1)
+        Rf = sc.sensor_T[0].reshape(3, 4)[:, :3].astype(np.float64)
+        dw = dirs.astype(np.float64) @ Rf.T
+        with np.errstate(divide="ignore"):
+            t_axis = np.where(dw > 0, (hi - p) / dw, np.where(dw < 0, (lo - p) / dw, np.inf))
+        t_exit = t_axis.min(1)
+        if np.any(r.tri < 0):
+            fails.append(f"table room: {np.sum(r.tri < 0)} beams escape a closed room")
+            continue
+        robust = (r.cls & O.BORDER_MASK) == 0
+        if robust.sum() < 0.8 * len(dirs):
+            fails.append("table room: too few robust beams")
+        err = np.abs(r.t[robust] - t_exit[robust]) / t_exit[robust]
+        if err.max() > 1e-5:
+            fails.append(f"table room: yaw {yaw} max rel range err {err.max():.3g}")
+    h = 1.5
+    for yaw in (0.0, 1.1, -2.5):
+        sc = _ground_scene(sens, S.sensor_pose(S.rot_zyx(yaw), (0.5, -0.75, h)))
+        r = O.render(sc, nthreads=1)
+        dz = dirs[:, 2].astype(np.float64)
+        down = dz < -1e-3
+        want = h / -dz[down]
+        ok = want <= sens.far
+        got = r.t[down][ok]
+        if np.any(np.abs(got - want[ok]) > 1e-6 * want[ok]):
+            fails.append(f"table ground: yaw {yaw} range differs from h / -d_z")
+        if np.any(r.tri[~down & (dz > 1e-3)] != -1):
+            fails.append(f"table ground: yaw {yaw} an upward beam hits the ground")
+    return fails
+
+
 # --------------------------------------------------------------------------
 # 4. classification
 # --------------------------------------------------------------------------
@@ -466,11 +519,29 @@ def pin_classifier():
                np.float32([[0, 0, 1]]), 0.1, 10.0)
     if r["cls"][0] != O.HIT | O.B_GAP or r["tri"][0] != 0:
         fails.append(f"classifier gap: {r['cls'][0]}")
-    # at the far limit
-    r = O.cast(_world_of([tri]), np.zeros(1, np.int32), np.float32([[0.5, 0.5, 0]]),
-               np.float32([[0, 0, 1]]), 0.1, 2.0000001)
-    if not r["cls"][0] & O.B_RANGE:
-        fails.append("classifier range")
+    # at the far limit and at the near limit (the triangle sits at t = 2)
+    for near, far, lim in ((0.1, 2.0000001, "far"), (1.9999999, 10.0, "near")):
+        r = O.cast(_world_of([tri]), np.zeros(1, np.int32), np.float32([[0.5, 0.5, 0]]),
+                   np.float32([[0, 0, 1]]), near, far)
+        if not r["cls"][0] & O.B_RANGE:
+            fails.append(f"classifier range ({lim} limit)")
+    # depth margin: the smallest of the relative gaps to the near limit, to the
+    # far limit and to the next candidate, each known here in closed form
+    for near, far, t2, want in ((1.8, 10.0, None, 0.1), (0.1, 2.2, None, 0.1),
+                                (0.1, 10.0, 2.3, 0.15), (1.9, 2.3, 2.25, 0.05)):
+        tris = [tri]
+        if t2 is not None:
+            second = tri.copy()
+            second[[2, 5, 8]] = t2
+            tris.append(second)
+        r = O.cast(_world_of(tris), np.zeros(1, np.int32), np.float32([[0.5, 0.5, 0]]),
+                   np.float32([[0, 0, 1]]), near, far)
+        f32 = lambda x: float(np.float32(x))
+        lim = [(2.0 - f32(near)) / 2.0, (f32(far) - 2.0) / 2.0]
+        if t2 is not None:
+            lim.append((f32(t2) - 2.0) / 2.0)
+        if r["tri"][0] != 0 or abs(r["md"][0] - min(lim)) > 1e-12 or abs(min(lim) - want) > 1e-6:
+            fails.append(f"classifier depth margin near {near} far {far}: {r['md'][0]} want {min(lim)}")
     # grazing incidence |cos| = 5e-4
     c = 5e-4
     d = np.float32([[math.sqrt(1 - c * c), 0, c]])
@@ -730,6 +801,6 @@ def pin_stereo_exact(seeds=range(40)):
 
 
 ALL_PINS = [pin_exact, pin_duplicate_tie, pin_ray_plane, pin_boxes, pin_tessellated,
-            pin_invariants, pin_transform, pin_motion, pin_rays, pin_classifier,
+            pin_invariants, pin_transform, pin_motion, pin_rays, pin_table_rays, pin_classifier,
             pin_normals, pin_barycentric, pin_point_cloud, pin_vertex_ids,
             pin_stereo_pillar, pin_stereo_zero_baseline, pin_stereo_exact]

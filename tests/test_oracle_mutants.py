@@ -53,6 +53,16 @@ MUTANTS = {
     "shadow_centre_transposed": ("fmaf(P[4 * k + 0], B[0], fmaf(P[4 * k + 1], B[1], fmaf(P[4 * k + 2], B[2], P[4 * k + 3])))",
                                  "fmaf(P[k], B[0], fmaf(P[4 + k], B[1], fmaf(P[8 + k], B[2], P[4 * k + 3])))"),
     "shadow_dir_reversed": ("D32[k] = c2 - p[3 * r + k];", "D32[k] = p[3 * r + k] - c2;"),
+    "table_xy_swapped": ("dl[0] = table[3 * r + 0];\n            dl[1] = table[3 * r + 1];",
+                         "dl[0] = table[3 * r + 1];\n            dl[1] = table[3 * r + 0];"),
+    "table_z_from_y": ("dl[2] = table[3 * r + 2];", "dl[2] = table[3 * r + 1];"),
+    "table_wrong_beam": ("dl[0] = table[3 * r + 0];", "dl[0] = table[3 * (r / 2) + 0];"),
+    "range_flag_near_dropped": ("if ((bt - tn) / bt <= MARGIN || (tf - bt) / bt <= MARGIN)",
+                                "if ((tf - bt) / bt <= MARGIN)"),
+    "depth_margin_near_dropped": ("double md = fmin((bt - tn) / bt, (tf - bt) / bt);",
+                                  "double md = (tf - bt) / bt;"),
+    "depth_margin_far_dropped": ("double md = fmin((bt - tn) / bt, (tf - bt) / bt);",
+                                 "double md = (bt - tn) / bt;"),
 }
 
 FAST_ARGS = {pins.pin_exact: dict(seeds=range(60))}
