@@ -126,6 +126,9 @@ BuildView Scene::view() const
     return v;
 }
 
+// Words of the per-environment stale flags (one byte per environment).
+static int64_t stale_words(int64_t n_envs) { return (n_envs + 3) / 4 + 1; }
+
 SceneView Scene::sview() const
 {
     SceneView s;
@@ -400,12 +403,14 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     std::vector<int32_t> tri_env(N), tri_seg(N), dyn;
     std::vector<int2> tri_src(N);
     std::vector<uint8_t> dynf(n_inst, 0);
+    std::vector<int32_t> inst_env(n_inst, 0);
     int64_t g = 0;
     for (int32_t e = 0; e < n_envs; ++e) {
         for (int64_t i = inst_offsets[e]; i < inst_offsets[e + 1]; ++i) {
             const Mesh &m = c->meshes[inst_mesh[i]];
             const bool d = inst_dynamic && inst_dynamic[i];
             dynf[i] = d;
+            inst_env[i] = e;
             for (int64_t k = 0; k < m.n_tris; ++k, ++g) {
                 tri_env[g] = e;
                 tri_seg[g] = inst_seg[i];
@@ -424,9 +429,13 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(upload(c, sc->tri_seg, tri_seg.data(), N, st));
     RC_TRY(upload(c, sc->tri_src, tri_src.data(), N, st));
     RC_TRY(upload(c, sc->inst_dyn, dynf.data(), n_inst, st));
+    RC_TRY(upload(c, sc->inst_env, inst_env.data(), n_inst, st));
     RC_TRY(upload(c, sc->dyn_tris, dyn.data(), dyn.size(), st));
     RC_TRY(c->pool.alloc(sc->inst_T, 48 * n_inst));
     RC_TRY(c->pool.alloc(sc->inst_T0, 48 * n_inst));
+    RC_TRY(c->pool.alloc(sc->inst_Tw, 48 * n_inst));
+    RC_TRY(c->pool.alloc(sc->stale_env, 4 * stale_words(n_envs)));
+    RC_HIP(launch_fill_u32(sc->stale_env.as<unsigned int>(), stale_words(n_envs), 0u, st));
     RC_TRY(c->pool.alloc(sc->world, 36 * N));
     RC_TRY(c->pool.alloc(sc->box_lo, 16 * N));
     RC_TRY(c->pool.alloc(sc->box_hi, 16 * N));
@@ -625,6 +634,15 @@ rc_status rc_move_instances(rc_context *c, const float *d_vel, int32_t step, flo
     return RC_OK;
 }
 
+// The world copy of every environment matches its records again.
+static rc_status world_fresh(Scene &sc, hipStream_t st)
+{
+    if (sc.world_stale)
+        RC_HIP(launch_fill_u32(sc.stale_env.as<unsigned int>(), stale_words(sc.n_envs), 0u, st));
+    sc.world_stale = sc.stale_all = false;
+    return RC_OK;
+}
+
 rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, void *stream)
 {
     RC_CHECK(c, "NULL context");
@@ -640,8 +658,11 @@ rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, vo
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
     RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
+    // the rebuilt environments' world triangles and records use these poses
+    RC_HIP(launch_pose_snapshot(sc.n_inst, sc.inst_env.as<int32_t>(), sc.inst_dyn.as<uint8_t>(), d_env_mask, false,
+                                sc.inst_T.as<float>(), sc.inst_Tw.as<float>(), nullptr, st));
     if (!d_env_mask)
-        sc.world_stale = false;
+        RC_TRY(world_fresh(sc, st));
     if (builder == RC_BUILD_LBVH)
         RC_HIP(launch_build_lbvh(v, sc.sah_mask.as<uint8_t>(), st));
     else
@@ -663,20 +684,31 @@ rc_status rc_refit(rc_context *c, const uint8_t *d_env_mask, void *stream)
     v.env_mask = d_env_mask;
     if (sc.n_dyn > 0) {
         RC_HIP(launch_transform_leaf(v, st));
+        // the poses of the moved records; a masked refit marks its environments
+        RC_HIP(launch_pose_snapshot(sc.n_inst, sc.inst_env.as<int32_t>(), sc.inst_dyn.as<uint8_t>(), d_env_mask,
+                                    true, sc.inst_T.as<float>(), sc.inst_Tw.as<float>(),
+                                    d_env_mask ? sc.stale_env.as<uint8_t>() : nullptr, st));
         sc.world_stale = true;
+        if (!d_env_mask)
+            sc.stale_all = true;
     }
     RC_HIP(launch_refit(v, st));
     return RC_OK;
 }
 
 // Brings the original-order world copy up to date (on stream st) if a
-// per-step transform left it stale.
+// per-step transform left it stale: the stale environments (all of them
+// after an unmasked refit or a step graph) are transformed with the poses
+// their records were made with.
 static rc_status fresh_world(rc_context *c, hipStream_t st)
 {
     Scene &sc = *c->scene;
     if (sc.world_stale) {
-        RC_HIP(launch_transform(sc.view(), nullptr, sc.n_tris, false, st));
-        sc.world_stale = false;
+        BuildView v = sc.view();
+        v.inst_T = sc.inst_Tw.as<float>();
+        v.env_mask = sc.stale_all ? nullptr : sc.stale_env.as<uint8_t>();
+        RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
+        RC_TRY(world_fresh(sc, st));
     }
     return RC_OK;
 }

@@ -204,6 +204,9 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
         if (k == hipSuccess && sc.n_dyn > 0)
             k = g->world_kept ? launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, cs)
                               : launch_transform_leaf(v, cs);
+        if (k == hipSuccess && sc.n_dyn > 0)
+            k = launch_pose_snapshot(sc.n_inst, sc.inst_env.as<int32_t>(), sc.inst_dyn.as<uint8_t>(), nullptr, true,
+                                     sc.inst_T.as<float>(), sc.inst_Tw.as<float>(), nullptr, cs);
         if (k == hipSuccess)
             k = launch_refit(v, cs);
         if (k == hipSuccess)
@@ -245,7 +248,7 @@ rc_status rc_graph_launch(rc_graph *g, void *stream)
     RC_TRY(set_device(g->ctx));
     RC_HIP(hipGraphLaunch(g->exec, stream ? (hipStream_t)stream : g->ctx->stream));
     if (!g->world_kept && g->ctx->scene->n_dyn > 0)
-        g->ctx->scene->world_stale = true;
+        g->ctx->scene->world_stale = g->ctx->scene->stale_all = true;
     return RC_OK;
 }
 

@@ -216,6 +216,30 @@ __global__ __launch_bounds__(256) void k_transform_leaf(BuildView v)
     v.recs[p] = rec;
 }
 
+// Pose record of the original-order world copy: copies the pose rows of the
+// instances whose triangles a build or refit just transformed (environments
+// in env_mask, dynamic instances only with dyn_only), so that a later refresh
+// of the world copy uses the poses its records were made with.  With
+// stale_env set, every environment touched is marked there.
+__global__ __launch_bounds__(256) void k_pose_snapshot(int64_t n, const int32_t *__restrict__ inst_env,
+                                                       const uint8_t *__restrict__ dyn,
+                                                       const uint8_t *__restrict__ env_mask, int dyn_only,
+                                                       const float *__restrict__ src, float *__restrict__ dst,
+                                                       uint8_t *__restrict__ stale_env)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int e = inst_env[i];
+    if ((env_mask && !env_mask[e]) || (dyn_only && !dyn[i]))
+        return;
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        dst[12 * i + k] = src[12 * i + k];
+    if (stale_env)
+        stale_env[e] = 1;  // every writer stores the same value
+}
+
 // K8: constant-velocity motion of dynamic instances.
 // The step comes from d_step when it is set (a captured step graph advances
 // it on the device), else from the argument.
@@ -1756,6 +1780,16 @@ hipError_t launch_transform_leaf(const BuildView &v, hipStream_t st)
     if (v.n_tris == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_transform_leaf, dim3(blocks_for(v.n_tris, 256)), dim3(256), 0, st, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_snapshot(int64_t n_inst, const int32_t *inst_env, const uint8_t *dyn, const uint8_t *env_mask,
+                                bool dyn_only, const float *src, float *dst, uint8_t *stale_env, hipStream_t st)
+{
+    if (n_inst == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_pose_snapshot, dim3(blocks_for(n_inst, 256)), dim3(256), 0, st, n_inst, inst_env, dyn,
+                       env_mask, (int)dyn_only, src, dst, stale_env);
     return hipGetLastError();
 }
 

@@ -115,6 +115,8 @@ struct OutView {
     uint8_t *shadow = nullptr;  // [ray] hidden from the second camera
     float *const *depth_tab = nullptr;  // per sensor instance (served batches)
     int32_t *const *seg_tab = nullptr;
+    int32_t *const *tri_tab = nullptr;
+    float *const *hit_tab = nullptr;    // [ray][3] per sensor instance
 };
 
 struct BuildView {
@@ -157,6 +159,11 @@ hipError_t launch_transform(const BuildView &v, const int32_t *tri_list, int64_t
 // The dynamic instances' triangles straight into their leaf-ordered records
 // (the original-order world copy is not written).
 hipError_t launch_transform_leaf(const BuildView &v, hipStream_t st);
+// Copies the pose rows of the instances of the environments in env_mask (all
+// when null; dynamic instances only with dyn_only) from src to dst, marking
+// each such environment in stale_env when it is set.
+hipError_t launch_pose_snapshot(int64_t n_inst, const int32_t *inst_env, const uint8_t *dyn, const uint8_t *env_mask,
+                                bool dyn_only, const float *src, float *dst, uint8_t *stale_env, hipStream_t st);
 hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step,
                        const int32_t *d_step, float dt, float *T, hipStream_t st);
 hipError_t launch_bump(int32_t *d_step, hipStream_t st);

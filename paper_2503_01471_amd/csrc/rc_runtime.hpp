@@ -82,8 +82,16 @@ struct Scene {
     // The per-step transform writes the leaf-ordered records only; the
     // original-order world copy (read by the brute-force render, the further
     // outputs, the stereo shadows and the debug readback) is then stale until
-    // refreshed by fresh_world().
-    bool world_stale = false;
+    // refreshed by fresh_world().  The refresh transforms with inst_Tw, the
+    // poses each instance's records were last made with (a caller may set new
+    // poses in between), and only the environments marked in stale_env unless
+    // stale_all is set; an environment outside a masked refit keeps its world
+    // triangles.
+    DBuf inst_Tw;    // [I][12] poses of the last build / refit per instance
+    DBuf inst_env;   // [I] owning environment
+    DBuf stale_env;  // [E] (padded to whole words) environments whose world copy is stale
+    bool world_stale = false;  // some environment may be stale
+    bool stale_all = false;    // every environment may be stale
     BuildView view() const;
     SceneView sview() const;
 };

@@ -205,10 +205,17 @@ def _mix_poses(scene, new, old, envs):
 def test_env_mask_build_and_refit():
     """A masked build (refit) updates only the masked environments: the
     outputs equal, bit for bit, a full build at the mixed poses (new poses
-    inside the mask, the previous ones outside), and match the oracle."""
+    inside the mask, the previous ones outside), and match the oracle.  Every
+    reader of the original-order world copy (brute force, further outputs,
+    stereo shadows, debug readback) sees the same mixed poses, also after the
+    caller sets new poses without a refit."""
+    import dataclasses
+
     from paper_2503_01471_amd import rc
     _need_gpu()
-    scene = S.make_cfg4(n_envs=6, env_ids=None)
+    base = S.make_cfg4(n_envs=6, env_ids=None)
+    stereo = [dataclasses.replace(d, stereo=(0.0, -0.3, 0.0)) if d.kind == S.PINHOLE else d for d in base.sensors]
+    scene = S.Scene(**{**base.__dict__, "sensors": stereo})
     R = _renderer(scene)
     T0 = np.asarray(scene.inst_T, np.float32).reshape(-1, 12)
     T1, T2 = O.moved_poses(scene, 40), O.moved_poses(scene, 90)
@@ -224,6 +231,31 @@ def test_env_mask_build_and_refit():
     R.refit(envs=[0, 4, 5])
     got_r = _host(R.render(mode=rc.RC_RENDER_BATCHED))
     mix_r = _mix_poses(scene, T2, mix_b, [0, 4, 5])
+    # the readers of the world copy: first after new poses that no refit has
+    # used (the copy is still stale from the masked refit), then again with
+    # the copy refreshed
+    w_r = O.world(scene, mix_r)
+    ora_r = O.render(scene, w_r)
+    every = dict(depth=True, seg=True, tri=True, hit=True, normal=True, bary=True, point=True, vert=True,
+                 shadow=True)
+    T3 = O.moved_poses(scene, 99)
+    rc.rc_set_instance_poses(R.ctx, torch.from_numpy(np.ascontiguousarray(T3)).cuda())
+    for when in ("after new poses without a refit", "with the world copy refreshed"):
+        _say(f"world copy readers {when}")
+        brute = _host(R.render(mode=rc.RC_RENDER_BRUTE, **every))
+        batched = _host(R.render(mode=rc.RC_RENDER_BATCHED, **every))
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(brute[k], got_r[k]), (when, k)
+        for k in brute:
+            if brute[k] is not None:
+                assert np.array_equal(brute[k], batched[k], equal_nan=brute[k].dtype.kind == "f"), (when, k)
+        assert np.array_equal(rc.rc_debug_world(R.ctx, R.n_tris), w_r.tris), when
+        rep = parity.compare_extras(batched, ora_r)
+        print(rep, flush=True)
+        parity.assert_extras(rep)
+        rob = ((ora_r.cls & O.BORDER_MASK) == 0) & ((ora_r.shadow_cls & 2) == 0)
+        assert not np.any(rob & (batched["shadow"] != ora_r.shadow)), when
+    rc.rc_set_instance_poses(R.ctx, torch.from_numpy(np.ascontiguousarray(T2)).cuda())
     # an empty mask changes nothing
     R.refit(envs=[])
     R.build(envs=[])
@@ -239,7 +271,7 @@ def test_env_mask_build_and_refit():
             assert np.array_equal(got[k], ref[k]), k
     for k in ("depth", "seg", "tri"):
         assert np.array_equal(got_e[k], got_r[k]), k
-    rep = parity.compare(got_r, O.render(scene, O.world(scene, mix_r)))
+    rep = parity.compare(got_r, ora_r)
     print(rep, flush=True)
     parity.assert_contract(rep)
 
