@@ -295,49 +295,78 @@ rc_status rc_graph_launch(rc_graph *graph, void *stream);
 rc_status rc_graph_destroy(rc_graph *graph);
 
 /* ------------------------------------------------------------------------ */
-/* Served form: a request loop over the resident scene and BVHs.             */
+/* Served form: a request loop over the resident scene and BVHs (the       */
+/* paper's per-environment rendering of Sec. III-D, taken request by        */
+/* request instead of step by step).                                         */
 /* A request renders n_envs environments (ids into the loaded scene) with    */
 /* one sensor model at the given poses (host float[n_envs][12], nullable =   */
 /* the pose of each environment's first attached sensor instance, as set by  */
-/* rc_set_sensor_poses before rc_server_create).  Outputs: caller DEVICE     */
-/* buffers float depth / int32 seg [n_envs * rays of the model] (each        */
-/* nullable), ray-major per environment in request order, same values as    */
-/* rc_render; they must be ready when submitted (the server writes them on  */
-/* its own streams) and stay valid until the ticket completes.  Requests    */
-/* are admitted in arrival order while their in-flight */
-/* bytes (8 per ray of outputs + work lists) fit the server budget; in      */
-/* RC_SERVE_BATCHED mode every admission round merges the admitted requests */
-/* into one persistent launch on one of n_streams streams, so batches that   */
-/* arrive while others run overlap on the device (continuous batching);     */
-/* RC_SERVE_PLAIN renders requests one at a time, one launch per            */
-/* environment (the per-environment reference path).  While a server        */
-/* exists the context's scene, sensors and tuning are read-only (calls that */
-/* would change them return RC_E_BUSY).  Submit, poll and wait may be called */
-/* from any one client thread.                                               */
+/* rc_set_sensor_poses before rc_server_create).  Outputs are ray-major per  */
+/* environment in request order, [n_envs * rays of the model] (hit_xyz      */
+/* [..][3]), with the same values as rc_render; only depth, seg, tri and     */
+/* hit_xyz can be served (the further data types must be NULL).  Either     */
+/* `out` holds caller DEVICE buffers (each nullable; ready when submitted,   */
+/* valid until the ticket completes; the server writes them on its own       */
+/* streams) and lib_outputs is 0, or every pointer of `out` is NULL and      */
+/* lib_outputs names the kinds (RC_OUT_*) the library allocates: they are    */
+/* carved at admission from one device slab of the server's budget,          */
+/* readable through rc_server_outputs once the ticket completes, and held    */
+/* until rc_server_release.                                                  */
+/* Admission: requests are taken in arrival order, later ones filling in     */
+/* while earlier ones do not fit, as long as the bytes in flight (the        */
+/* outputs: library blocks, or for caller buffers their size, at least 8 per */
+/* ray; plus 8 per 64-ray tile and 80 per environment of work lists) stay    */
+/* within the budget and every library block finds room in the slab.  A     */
+/* caller that never releases library outputs can hold the budget and stall  */
+/* later requests.  In RC_SERVE_BATCHED mode every admission round merges    */
+/* the admitted requests into one persistent launch on one of n_streams      */
+/* streams, so batches that arrive while others run overlap on the device    */
+/* (continuous batching); RC_SERVE_PLAIN renders requests one at a time,     */
+/* one launch per environment (the per-environment reference path).  While  */
+/* a server exists the context's scene, sensors and tuning are read-only     */
+/* (calls that would change them return RC_E_BUSY).  Submit, poll, wait,    */
+/* outputs and release may be called from any one client thread.             */
 /* ------------------------------------------------------------------------ */
 typedef struct rc_server rc_server;
+#define RC_OUT_DEPTH 1
+#define RC_OUT_SEG 2
+#define RC_OUT_TRI 4
+#define RC_OUT_HIT 8
 typedef struct {
     int32_t n_envs;
     const int32_t *env_ids;
     int32_t sensor_id;
     const float *sensor_T;
-    float *depth;
-    int32_t *seg;
+    rc_outputs out;
+    int32_t lib_outputs;
 } rc_request;
 #define RC_SERVE_PLAIN 0
 #define RC_SERVE_BATCHED 1
 
+/* hbm_budget: bytes in flight (see above), capped at the device memory free */
+/* at creation; 0 = half of the device memory free at creation.  The slab of */
+/* library outputs (the whole budget) is allocated by the first request that */
+/* asks for them, through the context's allocator.                           */
 rc_status rc_server_create(rc_context *ctx, int32_t mode, int32_t n_streams, size_t hbm_budget,
                            rc_server **server);
 /* Non-blocking; host arrays are copied.  RC_E_OOM if the request alone     */
-/* exceeds the budget.  ticket: host uint64 (> 0).                          */
+/* exceeds the budget (or the slab cannot be allocated).  ticket: host      */
+/* uint64 (> 0).                                                            */
 rc_status rc_server_submit(rc_server *server, const rc_request *req, uint64_t *ticket);
 /* done = 1 once the request's outputs are written (device work complete);  */
-/* latency_s = completion time - submit time (host monotonic clock).  A      */
-/* completed ticket is released by the poll that reports it.                */
+/* latency_s = completion time - submit time (host monotonic clock).  The   */
+/* call that reports completion releases a ticket with caller buffers; a    */
+/* ticket with library outputs stays until rc_server_release.               */
 rc_status rc_server_poll(rc_server *server, uint64_t ticket, int32_t *done, double *latency_s);
-/* Block until the ticket completes; releases it. */
+/* Block until the ticket completes (released as by rc_server_poll). */
 rc_status rc_server_wait(rc_server *server, uint64_t ticket, double *latency_s);
+/* Device pointers of a completed ticket's library outputs (NULL for the     */
+/* kinds not asked for).  Owned by the server: valid until the release.      */
+/* RC_E_STATE before completion; RC_E_INVALID for caller-buffer tickets.     */
+rc_status rc_server_outputs(rc_server *server, uint64_t ticket, rc_outputs *out);
+/* Return a completed ticket's library outputs to the slab and forget the    */
+/* ticket.  RC_E_STATE before completion; RC_E_INVALID for caller buffers.   */
+rc_status rc_server_release(rc_server *server, uint64_t ticket);
 /* Drains queued and running requests, then frees the server. */
 rc_status rc_server_destroy(rc_server *server);
 

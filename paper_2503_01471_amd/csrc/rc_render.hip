@@ -460,10 +460,19 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
     if (o.depth_tab) {  // per-request buffers (served batches)
         float *dp = o.depth_tab[tl.s];
         int32_t *sp = o.seg_tab[tl.s];
+        int32_t *tp = o.tri_tab[tl.s];
+        float *hp = o.hit_tab[tl.s];
         if (dp)
             dp[r_local] = depth;
         if (sp)
             sp[r_local] = seg;
+        if (tp)
+            tp[r_local] = tri;
+        if (hp) {
+            hp[3 * r_local + 0] = hx;
+            hp[3 * r_local + 1] = hy;
+            hp[3 * r_local + 2] = hz;
+        }
         return;
     }
     const int64_t idx = tl.ray_base + r_local;

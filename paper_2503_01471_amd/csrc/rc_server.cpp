@@ -9,7 +9,9 @@
 // request's own buffers; in plain mode one request at a time, one launch per
 // environment.  Completion is detected through one event per stream; while
 // a batch runs, newly arrived requests are admitted on the other streams, so
-// their work overlaps on the device.
+// their work overlaps on the device.  The admission round itself and the
+// arena that holds library-allocated outputs are the host-only code of
+// rc_sched.hpp.
 #include <string.h>
 
 #include <algorithm>
@@ -23,6 +25,7 @@
 #include <vector>
 
 #include "rc_runtime.hpp"
+#include "rc_sched.hpp"
 
 using namespace rc;
 
@@ -38,14 +41,22 @@ struct Req {
     std::vector<int32_t> envs;
     int32_t model = 0;
     std::vector<float> poses;  // 12 per environment
-    float *depth = nullptr;
+    float *depth = nullptr;    // outputs: caller buffers, or carved from the arena at admission
     int32_t *seg = nullptr;
+    int32_t *tri = nullptr;
+    float *hit = nullptr;
+    int32_t lib_outputs = 0;   // RC_OUT_* kinds the library allocates (0: caller buffers)
     int64_t rays_per_env = 0;
     int64_t tiles = 0;  // work items
-    size_t bytes = 0;   // budget charge while queued or running
+    sched::Pending pending;  // bytes charged while in flight; arena block of library outputs
     double t_submit = 0.0, t_done = 0.0;
     int state = 0;  // 0 queued, 1 running, 2 done
 };
+
+// Bytes per ray of each output kind, in the order the arena block holds them.
+constexpr int kOutKinds = 4;
+constexpr int kOutBit[kOutKinds] = {RC_OUT_DEPTH, RC_OUT_SEG, RC_OUT_TRI, RC_OUT_HIT};
+constexpr int64_t kOutBytes[kOutKinds] = {4, 4, 4, 12};
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -53,7 +64,7 @@ struct Slot {
     bool busy = false;
     std::vector<Req *> reqs;
     size_t charged = 0;
-    DBuf items, si_env, si_model, ray_off, pose, dtab, stab, head;
+    DBuf items, si_env, si_model, ray_off, pose, dtab, stab, ttab, htab, head;
     int64_t cap_items = 0, cap_si = 0;
     void *host = nullptr;
     size_t host_cap = 0;
@@ -71,6 +82,8 @@ struct rc_server {
     rc_context *ctx = nullptr;
     int mode = RC_SERVE_BATCHED;
     size_t budget = 0, in_use = 0;
+    sched::Arena arena;  // library-allocated outputs: offsets into `slab`
+    DBuf slab;           // allocated by the first request that asks for library outputs
     std::vector<SensorModel> models;  // host copies, current tile shape
     std::vector<float> env_pose;      // first attached pose per environment
     std::vector<uint8_t> env_has_pose;
@@ -103,9 +116,10 @@ rc_status ensure(rc_context *c, Slot &sl, DBuf &b, size_t bytes)
     return c->pool.alloc(b, bytes + bytes / 2);
 }
 
-// Byte offsets of the pinned staging block: items | si_env | si_model | pose | dtab | stab.
+// Byte offsets of the pinned staging block:
+// items | si_env | si_model | pose | dtab | stab | ttab | htab.
 struct Staging {
-    size_t o_items, o_env, o_model, o_pose, o_dtab, o_stab, total;
+    size_t o_items, o_env, o_model, o_pose, o_dtab, o_stab, o_ttab, o_htab, total;
     Staging(int64_t n_items, int64_t S)
     {
         o_items = 0;
@@ -114,7 +128,9 @@ struct Staging {
         o_pose = o_model + 4 * S;
         o_dtab = o_pose + 48 * S;
         o_stab = o_dtab + 8 * S;
-        total = o_stab + 8 * S;
+        o_ttab = o_stab + 8 * S;
+        o_htab = o_ttab + 8 * S;
+        total = o_htab + 8 * S;
     }
 };
 
@@ -128,6 +144,8 @@ rc_status reserve(rc_context *c, Slot &sl, int64_t S, int64_t n_items)
         RC_TRY(ensure(c, sl, sl.pose, 48 * S));
         RC_TRY(ensure(c, sl, sl.dtab, 8 * S));
         RC_TRY(ensure(c, sl, sl.stab, 8 * S));
+        RC_TRY(ensure(c, sl, sl.ttab, 8 * S));
+        RC_TRY(ensure(c, sl, sl.htab, 8 * S));
         RC_HIP(hipMemsetAsync(sl.ray_off.p, 0, sl.ray_off.n, sl.stream));
         sl.cap_si = (int64_t)(sl.si_env.n / 4);
     }
@@ -164,7 +182,7 @@ rc_status launch(rc_server *sv, Slot &sl)
     RC_TRY(reserve(c, sl, S, n_items));
     const Staging g(n_items, S);
     const size_t o_items = g.o_items, o_env = g.o_env, o_model = g.o_model, o_pose = g.o_pose, o_dtab = g.o_dtab,
-                 o_stab = g.o_stab;
+                 o_stab = g.o_stab, o_ttab = g.o_ttab, o_htab = g.o_htab;
     char *h = (char *)sl.host;
     int2 *items = (int2 *)(h + o_items);
     int32_t *si_env = (int32_t *)(h + o_env);
@@ -172,6 +190,8 @@ rc_status launch(rc_server *sv, Slot &sl)
     float *pose = (float *)(h + o_pose);
     float **dtab = (float **)(h + o_dtab);
     int32_t **stab = (int32_t **)(h + o_stab);
+    int32_t **ttab = (int32_t **)(h + o_ttab);
+    float **htab = (float **)(h + o_htab);
     int64_t k = 0;
     std::vector<int64_t> item_begin;  // per sensor instance, request order (plain mode)
     std::vector<int64_t> order, tiles;  // batched mode: queue order of the sensor instances
@@ -181,8 +201,11 @@ rc_status launch(rc_server *sv, Slot &sl)
             si_env[k] = r->envs[i];
             si_model[k] = r->model;
             memcpy(pose + 12 * k, r->poses.data() + 12 * i, 48);
-            dtab[k] = r->depth ? r->depth + (int64_t)i * r->rays_per_env : nullptr;
-            stab[k] = r->seg ? r->seg + (int64_t)i * r->rays_per_env : nullptr;
+            const int64_t at = (int64_t)i * r->rays_per_env;
+            dtab[k] = r->depth ? r->depth + at : nullptr;
+            stab[k] = r->seg ? r->seg + at : nullptr;
+            ttab[k] = r->tri ? r->tri + at : nullptr;
+            htab[k] = r->hit ? r->hit + 3 * at : nullptr;
             order.push_back(k);
             tiles.push_back(m.tiles);
         }
@@ -208,6 +231,8 @@ rc_status launch(rc_server *sv, Slot &sl)
     RC_HIP(hipMemcpyAsync(sl.pose.p, h + o_pose, 48 * S, hipMemcpyHostToDevice, st));
     RC_HIP(hipMemcpyAsync(sl.dtab.p, h + o_dtab, 8 * S, hipMemcpyHostToDevice, st));
     RC_HIP(hipMemcpyAsync(sl.stab.p, h + o_stab, 8 * S, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.ttab.p, h + o_ttab, 8 * S, hipMemcpyHostToDevice, st));
+    RC_HIP(hipMemcpyAsync(sl.htab.p, h + o_htab, 8 * S, hipMemcpyHostToDevice, st));
     SensorView ev;
     ev.models = se.models.as<SensorModel>();
     ev.tables = se.tables.as<float>();
@@ -219,6 +244,8 @@ rc_status launch(rc_server *sv, Slot &sl)
     OutView ov;
     ov.depth_tab = sl.dtab.as<float *>();
     ov.seg_tab = sl.stab.as<int32_t *>();
+    ov.tri_tab = sl.ttab.as<int32_t *>();
+    ov.hit_tab = sl.htab.as<float *>();
     if (sv->mode == RC_SERVE_BATCHED) {
         QueueView qv;
         qv.items = ev.items;
@@ -233,6 +260,34 @@ rc_status launch(rc_server *sv, Slot &sl)
     }
     RC_HIP(hipEventRecord(sl.done, st));
     return RC_OK;
+}
+
+// Point a request's library-allocated outputs into its arena block (kinds in
+// kOutBit order, each starting on an arena alignment boundary).
+void carve_outputs(rc_server *sv, Req &r)
+{
+    char *p = (char *)sv->slab.p + r.pending.arena_off;
+    const int64_t n = r.rays_per_env * (int64_t)r.envs.size();
+    void *dst[kOutKinds] = {};
+    for (int k = 0; k < kOutKinds; ++k)
+        if (r.lib_outputs & kOutBit[k]) {
+            dst[k] = p;
+            p += sched::align_up((size_t)(kOutBytes[k] * n));
+        }
+    r.depth = (float *)dst[0];
+    r.seg = (int32_t *)dst[1];
+    r.tri = (int32_t *)dst[2];
+    r.hit = (float *)dst[3];
+}
+
+// Arena bytes of a request's library-allocated outputs.
+size_t lib_output_bytes(int32_t kinds, int64_t rays)
+{
+    size_t b = 0;
+    for (int k = 0; k < kOutKinds; ++k)
+        if (kinds & kOutBit[k])
+            b += sched::align_up((size_t)(kOutBytes[k] * rays));
+    return b;
 }
 
 void worker_main(rc_server *sv)
@@ -254,7 +309,7 @@ void worker_main(rc_server *sv)
                     r->t_done = t;
                 }
                 sl.reqs.clear();
-                sv->in_use -= sl.charged;
+                sv->in_use -= sl.charged;  // library outputs stay charged until released
                 sl.charged = 0;
                 sl.busy = false;
                 sv->cv.notify_all();
@@ -279,35 +334,23 @@ void worker_main(rc_server *sv)
             Slot &sl = *slp;
             if (sl.busy || sv->queue.empty() || sv->error != RC_OK)
                 continue;
-            std::vector<Req *> batch;
-            size_t bytes = 0;
-            int64_t rays = 0;
-            int scanned = 0;
-            for (auto itq = sv->queue.begin(); itq != sv->queue.end() && scanned < kLookahead; ++scanned) {
-                Req *r = *itq;
-                const int64_t rr = r->rays_per_env * (int64_t)r->envs.size();
-                const bool fits = sv->in_use + bytes + r->bytes <= sv->budget &&
-                                  (batch.empty() || rays + rr <= kMaxBatchRays);
-                if (fits) {
-                    batch.push_back(r);
-                    bytes += r->bytes;
-                    rays += rr;
-                    itq = sv->queue.erase(itq);
-                    if (sv->mode == RC_SERVE_PLAIN)
-                        break;
-                } else {
-                    if (sv->mode == RC_SERVE_PLAIN)
-                        break;  // strict FIFO
-                    ++itq;
-                }
-            }
+            sched::RoundLimits lim;
+            lim.budget = sv->budget;
+            lim.max_rays = kMaxBatchRays;
+            lim.lookahead = kLookahead;
+            lim.fifo_only = sv->mode == RC_SERVE_PLAIN;
+            std::vector<Req *> batch = sched::admit(sv->queue, sv->in_use, sv->arena, lim);
             if (batch.empty())
                 continue;
-            for (Req *r : batch)
+            size_t charged = 0;
+            for (Req *r : batch) {
                 r->state = 1;
-            sv->in_use += bytes;
+                charged += r->pending.bytes - r->pending.arena_bytes;
+                if (r->lib_outputs)
+                    carve_outputs(sv, *r);
+            }
             sl.reqs = batch;
-            sl.charged = bytes;
+            sl.charged = charged;
             sl.busy = true;
             lk.unlock();
             const rc_status s = launch(sv, sl);
@@ -321,6 +364,7 @@ void worker_main(rc_server *sv)
                 sl.reqs.clear();
                 sl.busy = false;
                 sv->in_use -= sl.charged;
+                sl.charged = 0;
                 sv->cv.notify_all();
             }
             launched = true;
@@ -347,14 +391,18 @@ rc_status rc_server_create(rc_context *c, int32_t mode, int32_t n_streams, size_
     *out = nullptr;
     RC_CHECK(mode == RC_SERVE_PLAIN || mode == RC_SERVE_BATCHED, "unknown server mode %d", mode);
     RC_CHECK(n_streams >= 1 && n_streams <= 16, "n_streams must be in [1, 16]");
-    RC_CHECK(hbm_budget > 0, "hbm_budget must be positive");
     if (!c->scene || !c->scene->built || !c->sensors || !c->sensors->poses_set)
         return fail(RC_E_STATE, "server needs a built scene and attached, posed sensors");
     RC_TRY(set_device(c));
+    size_t free_b = 0, total_b = 0;
+    RC_HIP(hipMemGetInfo(&free_b, &total_b));
+    // 0: half of the device memory free now; never more than is free
+    const size_t budget = hbm_budget ? std::min(hbm_budget, free_b) : free_b / 2;
+    RC_CHECK(budget > 0, "no device memory free for the server budget");
     auto sv = new rc_server;
     sv->ctx = c;
     sv->mode = mode;
-    sv->budget = hbm_budget;
+    sv->budget = budget;
     const Sensors &se = *c->sensors;
     // host copies of the models (current tile shape) and of the attached poses
     sv->models.resize(c->models.size());
@@ -435,19 +483,47 @@ rc_status rc_server_submit(rc_server *sv, const rc_request *q, uint64_t *ticket)
     for (int32_t i = 0; i < q->n_envs; ++i)
         memcpy(&r->poses[12 * (size_t)i], q->sensor_T ? q->sensor_T + 12 * (size_t)i : &sv->env_pose[12 * (size_t)r->envs[i]],
                48);
-    r->depth = q->depth;
-    r->seg = q->seg;
+    const rc_outputs &o = q->out;
+    RC_CHECK(!o.normal && !o.bary && !o.point && !o.vert && !o.shadow,
+             "served requests write depth, seg, tri and hit_xyz only");
+    RC_CHECK((q->lib_outputs & ~(RC_OUT_DEPTH | RC_OUT_SEG | RC_OUT_TRI | RC_OUT_HIT)) == 0,
+             "lib_outputs has unknown bits 0x%x", q->lib_outputs);
+    RC_CHECK(!q->lib_outputs || (!o.depth && !o.seg && !o.tri && !o.hit_xyz),
+             "lib_outputs needs every output pointer NULL");
+    r->depth = o.depth;
+    r->seg = o.seg;
+    r->tri = o.tri;
+    r->hit = o.hit_xyz;
+    r->lib_outputs = q->lib_outputs;
     const SensorModel &m = sv->models[r->model];
     r->rays_per_env = (int64_t)m.W * m.H;
     r->tiles = (int64_t)m.tiles * q->n_envs;
-    r->bytes = (size_t)(8 * r->rays_per_env * q->n_envs + 8 * r->tiles + 80 * (int64_t)q->n_envs);
-    if (r->bytes > sv->budget)
-        return fail(RC_E_OOM, "request needs %zu bytes in flight, server budget is %zu", r->bytes, sv->budget);
+    const int64_t rays = r->rays_per_env * q->n_envs;
+    // in flight: the outputs (the arena block, or for caller buffers the bytes
+    // they stand for, at least depth and seg) and the work lists
+    int64_t caller_b = 0;
+    const void *given[kOutKinds] = {o.depth, o.seg, o.tri, o.hit_xyz};
+    for (int k = 0; k < kOutKinds; ++k)
+        caller_b += given[k] ? kOutBytes[k] : 0;
+    r->pending.rays = rays;
+    r->pending.arena_bytes = lib_output_bytes(r->lib_outputs, rays);
+    const size_t out_b = r->lib_outputs ? r->pending.arena_bytes : (size_t)(std::max<int64_t>(caller_b, 8) * rays);
+    r->pending.bytes = out_b + (size_t)(8 * r->tiles + 80 * q->n_envs);
+    sched::RoundLimits alone;
+    alone.budget = sv->budget;
+    if (!sched::fits_alone(r->pending, alone))
+        return fail(RC_E_OOM, "request needs %zu bytes in flight, server budget is %zu", r->pending.bytes,
+                    sv->budget);
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->error != RC_OK)
         return fail(sv->error, "server failed: %s", sv->error_msg.c_str());
     if (sv->stop)
         return fail(RC_E_STATE, "server is stopping");
+    if (r->lib_outputs && !sv->slab.p) {  // first request with library outputs: the arena slab
+        RC_TRY(set_device(c));
+        RC_TRY(c->pool.alloc(sv->slab, sv->budget));
+        sv->arena.reset(sv->budget);
+    }
     r->ticket = sv->next_ticket++;
     r->t_submit = now_s();
     *ticket = r->ticket;
@@ -457,6 +533,8 @@ rc_status rc_server_submit(rc_server *sv, const rc_request *q, uint64_t *ticket)
     return RC_OK;
 }
 
+// Completion of a ticket: a request with caller buffers is released by the
+// call that reports it; one with library outputs stays until rc_server_release.
 static rc_status finish(rc_server *sv, uint64_t ticket, bool block, int32_t *done, double *latency)
 {
     std::unique_lock<std::mutex> lk(sv->mu);
@@ -475,7 +553,8 @@ static rc_status finish(rc_server *sv, uint64_t ticket, bool block, int32_t *don
         *done = 1;
     if (latency)
         *latency = r->t_done - r->t_submit;
-    sv->reqs.erase(it);
+    if (!r->lib_outputs)
+        sv->reqs.erase(it);
     if (sv->error != RC_OK)
         return fail(sv->error, "server failed: %s", sv->error_msg.c_str());
     return RC_OK;
@@ -491,6 +570,48 @@ rc_status rc_server_wait(rc_server *sv, uint64_t ticket, double *latency_s)
 {
     RC_CHECK(sv, "NULL server");
     return finish(sv, ticket, true, nullptr, latency_s);
+}
+
+rc_status rc_server_outputs(rc_server *sv, uint64_t ticket, rc_outputs *out)
+{
+    RC_CHECK(sv && out, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end())
+        return fail(RC_E_INVALID, "unknown or already released ticket %llu", (unsigned long long)ticket);
+    const Req &r = *it->second;
+    if (!r.lib_outputs)
+        return fail(RC_E_INVALID, "ticket %llu writes caller buffers", (unsigned long long)ticket);
+    if (r.state != 2)
+        return fail(RC_E_STATE, "ticket %llu has not completed", (unsigned long long)ticket);
+    *out = rc_outputs{};
+    out->depth = r.depth;
+    out->seg = r.seg;
+    out->tri = r.tri;
+    out->hit_xyz = r.hit;
+    return RC_OK;
+}
+
+rc_status rc_server_release(rc_server *sv, uint64_t ticket)
+{
+    RC_CHECK(sv, "NULL server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end())
+        return fail(RC_E_INVALID, "unknown or already released ticket %llu", (unsigned long long)ticket);
+    Req &r = *it->second;
+    if (!r.lib_outputs)
+        return fail(RC_E_INVALID, "ticket %llu writes caller buffers (released by poll or wait)",
+                    (unsigned long long)ticket);
+    if (r.state != 2)
+        return fail(RC_E_STATE, "ticket %llu has not completed", (unsigned long long)ticket);
+    if (r.depth || r.seg || r.tri || r.hit) {  // admitted: its block and charge are held
+        sv->arena.release(r.pending.arena_off, r.pending.arena_bytes);
+        sv->in_use -= r.pending.arena_bytes;
+    }
+    sv->reqs.erase(it);
+    sv->cv.notify_all();
+    return RC_OK;
 }
 
 rc_status rc_server_destroy(rc_server *sv)

@@ -29,9 +29,10 @@ ABI = [
     "rc_set_instance_poses", "rc_set_sensor_poses", "rc_move_instances", "rc_build", "rc_refit", "rc_render",
     "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh", "rc_autotune", "rc_tuning_set", "rc_step_graph_create",
     "rc_graph_set_step", "rc_graph_launch", "rc_graph_destroy", "rc_server_create", "rc_server_submit",
-    "rc_server_poll", "rc_server_wait", "rc_server_destroy",
+    "rc_server_poll", "rc_server_wait", "rc_server_outputs", "rc_server_release", "rc_server_destroy",
 ]
 RC_SERVE_PLAIN, RC_SERVE_BATCHED = 0, 1
+RC_OUT_DEPTH, RC_OUT_SEG, RC_OUT_TRI, RC_OUT_HIT = 1, 2, 4, 8
 
 
 class RCError(RuntimeError):
@@ -89,7 +90,7 @@ def torch_allocator(device: int = 0) -> rc_allocator:
 
 class rc_request(C.Structure):
     _fields_ = [("n_envs", C.c_int32), ("env_ids", C.c_void_p), ("sensor_id", C.c_int32),
-                ("sensor_T", C.c_void_p), ("depth", C.c_void_p), ("seg", C.c_void_p)]
+                ("sensor_T", C.c_void_p), ("out", rc_outputs), ("lib_outputs", C.c_int32)]
 
 
 _lib = None
@@ -135,6 +136,8 @@ def lib():
             "rc_server_submit": (I32, [P, C.POINTER(rc_request), C.POINTER(C.c_uint64)]),
             "rc_server_poll": (I32, [P, C.c_uint64, C.POINTER(I32), C.POINTER(C.c_double)]),
             "rc_server_wait": (I32, [P, C.c_uint64, C.POINTER(C.c_double)]),
+            "rc_server_outputs": (I32, [P, C.c_uint64, C.POINTER(rc_outputs)]),
+            "rc_server_release": (I32, [P, C.c_uint64]),
             "rc_server_destroy": (I32, [P]),
         }
         for name, (res, args) in sig.items():
@@ -350,25 +353,61 @@ def rc_graph_destroy(graph) -> None:
 
 
 def rc_server_create(ctx, mode: int = RC_SERVE_BATCHED, n_streams: int = 4, hbm_budget: int = 4 << 30):
+    """hbm_budget 0: half of the device memory free at creation."""
     srv = C.c_void_p()
     _check(lib().rc_server_create(ctx, mode, n_streams, hbm_budget, C.byref(srv)))
     return srv.value
 
 
-def rc_server_submit(server, env_ids, sensor_id: int, depth=None, seg=None, sensor_T=None) -> int:
+def rc_server_submit(server, env_ids, sensor_id: int, depth=None, seg=None, sensor_T=None, tri=None,
+                     hit_xyz=None, lib_outputs: int = 0) -> int:
+    """Caller device buffers (depth / seg / tri / hit_xyz, each optional), or
+    with ``lib_outputs`` (RC_OUT_* bits) and no buffers, library outputs read
+    through :func:`rc_server_outputs` and freed by :func:`rc_server_release`."""
     ids = _host(env_ids, np.int32)
     T = None if sensor_T is None else _host(sensor_T, np.float32)
     n = len(ids)
-    req = rc_request(n, ids.ctypes.data, sensor_id, None if T is None else T.ctypes.data,
-                     None if depth is None else _dev(depth, "float32", 0, "depth"),
-                     None if seg is None else _dev(seg, "int32", 0, "seg"))
+    out = rc_outputs(None if depth is None else _dev(depth, "float32", 0, "depth"),
+                     None if seg is None else _dev(seg, "int32", 0, "seg"),
+                     None if tri is None else _dev(tri, "int32", 0, "tri"),
+                     None if hit_xyz is None else _dev(hit_xyz, "float32", 0, "hit_xyz"))
+    req = rc_request(n, ids.ctypes.data, sensor_id, None if T is None else T.ctypes.data, out, lib_outputs)
     t = C.c_uint64()
     _check(lib().rc_server_submit(server, C.byref(req), C.byref(t)))
     return t.value
 
 
+def rc_server_outputs(server, ticket: int, n_rays: int, device: int = 0) -> dict:
+    """Views (torch tensors, no copy) of a completed ticket's library outputs;
+    valid until :func:`rc_server_release`.  n_rays: rays of the request."""
+    import torch
+    o = rc_outputs()
+    _check(lib().rc_server_outputs(server, ticket, C.byref(o)))
+
+    def view(ptr, typestr, k):
+        if not ptr:
+            return None
+        return torch.as_tensor(_DeviceArray(ptr, n_rays * k, typestr), device=torch.device("cuda", device))
+    return {"depth": view(o.depth, "<f4", 1), "seg": view(o.seg, "<i4", 1), "tri": view(o.tri, "<i4", 1),
+            "hit_xyz": view(o.hit_xyz, "<f4", 3)}
+
+
+class _DeviceArray:
+    """A device buffer the library owns, described by the array interface
+    torch reads for device memory (the tensor views it without a copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (int(ptr), False),
+                                         "strides": None, "version": 2}
+
+
+def rc_server_release(server, ticket: int) -> None:
+    _check(lib().rc_server_release(server, ticket))
+
+
 def rc_server_poll(server, ticket: int):
-    """(done, latency_s); a reported completion releases the ticket."""
+    """(done, latency_s); a reported completion releases a caller-buffer
+    ticket (library-output tickets stay until rc_server_release)."""
     done = C.c_int32()
     lat = C.c_double()
     _check(lib().rc_server_poll(server, ticket, C.byref(done), C.byref(lat)))

@@ -171,6 +171,104 @@ def test_server_alone_equals_mix_and_plain():
     R.close()
 
 
+def _request_scene(scene, envs, sid):
+    """The scene a request renders: its environments in request order, each
+    with one instance of sensor model `sid` at the environment's own first
+    sensor pose (the pose the server takes when a request gives none)."""
+    sub = S.subset(scene, envs)
+    n = len(envs)
+    return S.Scene(**{**sub.__dict__, "sens_offsets": np.arange(n + 1, dtype=np.int64),
+                      "sensor_ids": np.full(n, sid, np.int32),
+                      "sensor_T": np.ascontiguousarray(scene.sensor_T[scene.sens_offsets[envs]], np.float32),
+                      "name": f"{scene.name}-request"})
+
+
+def test_server_matches_oracle():
+    """Every served request, in a mix of concurrent requests, against the
+    oracle on that request's environments and sensor model (also a model
+    other than the environment's own), under the parity contract: depth,
+    seg, tri and hit points, from caller buffers and from library outputs."""
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=24)
+    R = _R(scene)
+    rng = np.random.default_rng(21)
+    reqs = _requests(scene, rng, 30, 6)
+    srv = rc.rc_server_create(R.ctx, rc.RC_SERVE_BATCHED, 4, 1 << 30)
+    every = rc.RC_OUT_DEPTH | rc.RC_OUT_SEG | rc.RC_OUT_TRI | rc.RC_OUT_HIT
+    got = []
+    try:
+        caller = []
+        for i, (envs, sid) in enumerate(reqs):
+            nr = scene.sensors[sid].n_rays * len(envs)
+            if i % 2 == 0:
+                caller.append(dict(depth=torch.empty(nr, device="cuda"),
+                                   seg=torch.empty(nr, dtype=torch.int32, device="cuda"),
+                                   tri=torch.empty(nr, dtype=torch.int32, device="cuda"),
+                                   hit_xyz=torch.empty(nr * 3, device="cuda")))
+            else:
+                caller.append(None)
+        torch.cuda.synchronize()
+        _say("server: 30 requests, caller buffers and library outputs")
+        tickets = [rc.rc_server_submit(srv, envs, sid, **(c or {})) if c is not None else
+                   rc.rc_server_submit(srv, envs, sid, lib_outputs=every)
+                   for (envs, sid), c in zip(reqs, caller)]
+        for (envs, sid), c, t in zip(reqs, caller, tickets):
+            rc.rc_server_wait(srv, t)
+            if c is None:
+                nr = scene.sensors[sid].n_rays * len(envs)
+                o = rc.rc_server_outputs(srv, t, nr)
+                got.append({k: v.cpu().numpy() for k, v in o.items()})
+                rc.rc_server_release(srv, t)
+                with pytest.raises(rc.RCError) as ei:  # released once only
+                    rc.rc_server_release(srv, t)
+                assert ei.value.status == -1
+            else:
+                torch.cuda.synchronize()
+                got.append({k: v.cpu().numpy() for k, v in c.items()})
+    finally:
+        rc.rc_server_destroy(srv)
+    R.close()
+    for i, ((envs, sid), g) in enumerate(zip(reqs, got)):
+        ora = O.render(_request_scene(scene, envs, sid))
+        g["hit_xyz"] = g["hit_xyz"].reshape(-1, 3)
+        rep = parity.compare(g, ora)
+        print(f"request {i}: {len(envs)} envs, sensor {sid}: {rep}", flush=True)
+        parity.assert_contract(rep)
+
+
+def test_server_request_errors():
+    """Argument errors of served requests are reported synchronously."""
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=4)
+    R = _R(scene)
+    srv = rc.rc_server_create(R.ctx, rc.RC_SERVE_BATCHED, 2, 1 << 28)
+    try:
+        nr = scene.sensors[0].n_rays
+        d = torch.empty(nr, device="cuda")
+        with pytest.raises(rc.RCError) as ei:  # library outputs need every pointer NULL
+            rc.rc_server_submit(srv, np.int32([0]), 0, d, lib_outputs=rc.RC_OUT_DEPTH)
+        assert ei.value.status == -1
+        with pytest.raises(rc.RCError) as ei:
+            rc.rc_server_submit(srv, np.int32([0]), 0, lib_outputs=64)
+        assert ei.value.status == -1
+        with pytest.raises(rc.RCError) as ei:  # environment out of range
+            rc.rc_server_submit(srv, np.int32([4]), 0, d)
+        assert ei.value.status == -1
+        t = rc.rc_server_submit(srv, np.int32([1]), 0, d)
+        rc.rc_server_wait(srv, t)
+        with pytest.raises(rc.RCError) as ei:  # a caller-buffer ticket is gone once reported
+            rc.rc_server_release(srv, t)
+        assert ei.value.status == -1
+        t = rc.rc_server_submit(srv, np.int32([2, 3]), 0, lib_outputs=rc.RC_OUT_SEG)
+        rc.rc_server_wait(srv, t)
+        o = rc.rc_server_outputs(srv, t, 2 * nr)
+        assert o["depth"] is None and o["tri"] is None and o["seg"].numel() == 2 * nr
+        rc.rc_server_release(srv, t)
+    finally:
+        rc.rc_server_destroy(srv)
+    R.close()
+
+
 def test_server_budget_and_busy():
     _need_gpu()
     scene = S.make_cfg4(n_envs=12)
