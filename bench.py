@@ -13,10 +13,13 @@ rebuild of every BVH, done at randomisation) is timed beside it, alone and as
 a step that rebuilds instead of refitting.
 
 Prints ONE JSON line: Mrays/s (whole job), env-steps/s, the render kernel's
-roofline position, the same step on the plain per-environment path, a short
-served-form summary (p50/p99 latency) and the CPU oracle timed on this host
-on a bounded sample.  --cfg 4 times the per-step HIP graph of the uneven
-moving-obstacle batch, --cfg 5 the full request-serving run.
+roofline position, the same step in the flat form (one launch, no queue) and
+on the plain per-environment path, the served form at its stated size (10^4
+requests of 1-512 environments arriving at 2000 req/s, p50/p99 latency and
+throughput, with the plain server on the same arrivals for a prefix) and the
+CPU oracle timed on this host on a bounded sample.  --cfg 4 times the
+per-step HIP graph of the uneven moving-obstacle batch, --cfg 5 the serving
+run alone.
 """
 from __future__ import annotations
 
@@ -31,6 +34,43 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s & env-steps/s (4096-env cam+LiDAR) vs plain; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# Vector issue capacity of MI355X: 256 CUs x 2.4 GHz, one wave64 VALU
+# instruction per CU per clock (4 SIMDs x 16 lanes; the 157.3 TFLOP/s FP32
+# vector peak counts packed FMAs: 256 x 2.4e9 x 64 lanes x 2 flop x 2).
+VALU_PEAK_GINST = 256 * 2.4
+
+
+def roofline(kernel, cfg, rays, ms_launch, b_alg):
+    """Position of the render kernel: it is bound by vector instruction issue
+    (the counters show HBM far from busy), so `achieved` is its wave64 VALU
+    instructions per launch (SQ_INSTS_VALU from the committed counter record,
+    used only while the kernel source matches it) over the launch time
+    measured here; HBM traffic (FETCH_SIZE + WRITE_SIZE) gives the HBM
+    fraction beside it, and the canonical traversal's bytes per ray are the
+    bytes the L1/L2/Infinity-cache hierarchy serves (no HBM fraction)."""
+    rec = traffic_record(kernel, cfg)
+    t = ms_launch * 1e-3
+    out = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_GINST, "unit": "Ginst/s (wave64 VALU issue)",
+           "frac": None, "traffic": None, "kernel": kernel, "units_per_launch": rays, "launch_ms": ms_launch,
+           "peak_model": "256 CUs x 2.4 GHz x one wave64 VALU instruction per CU-clock",
+           "counters": None if rec is None else f"profiles/traffic_{kernel}_cfg{cfg}.json",
+           "cache_bytes_per_ray": b_alg, "cache_GBs": b_alg * rays / t / 1e9,
+           "cache_model": "canonical full-sweep SAH BVH2 traversal: 32 B/box test + 40 B/tri test + 8 B out, "
+                          "served by L1/L2/Infinity cache"}
+    if rec is not None:
+        valu = rec["issue"]["valu_insts_per_launch"]
+        out["achieved"] = valu / t / 1e9
+        out["frac"] = out["achieved"] / VALU_PEAK_GINST
+        out["valu_insts_per_ray"] = valu / rays
+        out["lane_utilisation"] = rec["issue"]["valu_lane_utilisation"]
+        out["traffic"] = rec["bytes_per_launch"]
+        out["hbm"] = {"achieved_GBs": rec["bytes_per_launch"] / t / 1e9, "peak_GBs": HBM_PEAK_GBS,
+                      "frac": rec["bytes_per_launch"] / t / 1e9 / HBM_PEAK_GBS,
+                      "write_bytes": rec["write_size_kib_per_dispatch"] * 1024 * rec["write_factor"]}
+        out["l2_hit_rate"] = rec.get("l2_hit_rate")
+    return out
+
+
 WORKLOADS = {
     1: "1 env, 64x48 pinhole camera, ground + 8 boxes (98 tris)",
     2: "1024 envs x 480x270 pinhole camera, room + 40 random box/cylinder/sphere obstacles (~5.3k tris/env)",
@@ -208,6 +248,18 @@ def bench_step(args):
                         float(xo["shadow"].sum()) / max(hits, 1)})
     log(f"further outputs: {further}")
     del xo
+    # FLAT: one launch over every tile, no queue (the one-launch baseline of the batched form)
+    def flat_step():
+        rc.rc_set_sensor_poses(ctx, R.sensor_T)
+        rc.rc_set_instance_poses(ctx, R.inst_T)
+        rc.rc_refit(ctx)
+        render(rc.RC_RENDER_FLAT)
+    ms_flat = timed(flat_step, args.steps)
+    ms_flat_render = timed(lambda: render(rc.RC_RENDER_FLAT), args.steps)
+    flat = {"ms_per_step": ms_flat, "Mrays_s": rays / ms_flat / 1e3, "ms_render": ms_flat_render,
+            "render_Mrays_s": rays / ms_flat_render / 1e3, "speedup_batched_vs_flat": ms_flat / ms,
+            "render_speedup_batched_vs_flat": ms_flat_render / ms_render}
+    log(f"flat step {ms_flat:.3f} ms, flat render {ms_flat_render:.3f} ms")
     plain = None
     if not args.no_plain:
         def plain_step():
@@ -224,9 +276,7 @@ def bench_step(args):
     stats = R.stats()
     from bytemodel import bytemodel
     b_ray = bytemodel.load()[f"cfg{args.cfg}"]["bytes_per_ray"]
-    achieved = b_ray * rays / (ms_render * 1e-3) / 1e9
     kernel = "k_render_batched" if mode == rc.RC_RENDER_BATCHED else "k_render_flat"
-    traffic = traffic_record(kernel, args.cfg)
     if args.calib:
         calibration_copy()
     result = {
@@ -257,20 +307,12 @@ def bench_step(args):
                            "step_with_rebuild_ms": ms_rebuild_step_lbvh,
                            "step_with_rebuild_Mrays_s": rays / ms_rebuild_step_lbvh / 1e3,
                            "env_steps_per_s": n_envs / (ms_rebuild_step_lbvh * 1e-3)}},
+        "flat": flat,
         "plain": plain,
         "further_outputs": further,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
                       "fp64_evals_per_ray": stats[2] / rays},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
-                     "kernel": kernel, "bytes_per_ray": b_ray, "units_per_launch": rays,
-                     "byte_model": "canonical full-sweep SAH traversal: 32 B/box test + 40 B/tri test + 8 B out",
-                     "l2_hit_rate": None if traffic is None else traffic.get("l2_hit_rate"),
-                     "valu_issue_frac": None if traffic is None else traffic.get("issue", {}).get("valu_issue_frac"),
-                     "note": "B_alg bytes are mostly served from L2 / Infinity Cache; what binds is the dependent "
-                             "node and triangle fetch latency together with VALU issue (valu_issue_frac, from the "
-                             "committed SQ counter profile)"},
+        "roofline": roofline(kernel, args.cfg, rays, ms_render, b_ray),
         "cpu_baseline": None,
     }
     R.close()
@@ -340,35 +382,63 @@ def make_requests(n_envs_pool, n_sensors, n_req, rate, seed):
     return arrivals, reqs
 
 
-def serve_run(R, reqs, arrivals, mode, budget, n_streams, scratch):
-    """Submit requests at their arrival times; every request writes its full
-    outputs into one shared scratch buffer (contents discarded)."""
+def serve_run(R, reqs, arrivals, mode, budget, n_streams, lib_outputs):
+    """Submit requests at their arrival times.  Every request gets its own
+    output buffers (library outputs carved from the server's slab at
+    admission); the client releases each one as soon as it has completed,
+    checking its completions in submission order between arrivals."""
+    from collections import deque
+
     import numpy as np
     from paper_2503_01471_amd import rc
     srv = rc.rc_server_create(R.ctx, mode, n_streams, budget)
-    lat = []
-    tickets = []
+    lat, pending = [], deque()
     rays = 0
+
+    def reap(block):
+        while pending:
+            t = pending[0]
+            if block:
+                lat.append(rc.rc_server_wait(srv, t))
+            else:
+                done, l = rc.rc_server_poll(srv, t)
+                if not done:
+                    return
+                lat.append(l)
+            rc.rc_server_release(srv, t)
+            pending.popleft()
     try:
+        # the slab of library outputs is allocated by the first such request: not timed
+        rc.rc_server_release(srv, _wait(rc, srv, rc.rc_server_submit(srv, reqs[0][0][:1], reqs[0][1],
+                                                                    lib_outputs=lib_outputs)))
         t0 = time.perf_counter()
         for i, (envs, sid) in enumerate(reqs):
             while time.perf_counter() - t0 < arrivals[i]:
+                reap(False)
                 time.sleep(0)  # yield the GIL: the server's worker may call back into Python
-            tickets.append(rc.rc_server_submit(srv, envs, sid, scratch[0], scratch[1]))
+            pending.append(rc.rc_server_submit(srv, envs, sid, lib_outputs=lib_outputs))
             rays += len(envs) * R.scene.sensors[sid].n_rays
-        for t in tickets:
-            lat.append(rc.rc_server_wait(srv, t))
+        reap(True)
         t_end = time.perf_counter()
     finally:
         rc.rc_server_destroy(srv)
     lat = np.array(lat)
     return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "Mrays_s": rays / (t_end - t0) / 1e6, "offered_req_s": len(reqs) / arrivals[-1],
-            "wall_s": t_end - t0}
+            "Mrays_s": rays / (t_end - t0) / 1e6, "req_s": len(reqs) / (t_end - t0),
+            "offered_req_s": len(reqs) / arrivals[-1], "wall_s": t_end - t0}
 
 
-def bench_serve(args, short=False):
+def _wait(rc, srv, t):
+    rc.rc_server_wait(srv, t)
+    return t
+
+
+def bench_serve(args):
+    """cfg5: the stated run (10^4 requests, Poisson arrivals at 2000 req/s) on
+    the batched server, the plain per-environment server on the same arrivals
+    for a prefix, a saturated burst, and a sweep below saturation where
+    latency is not backlog."""
     import torch
     from paper_2503_01471_amd import rc, scenes
     from paper_2503_01471_amd.renderer import Renderer
@@ -378,38 +448,42 @@ def bench_serve(args, short=False):
     R = Renderer(scene, build=True)
     if not args.no_autotune:
         rc.rc_autotune(R.ctx, args.tune_cache)
-    max_rays = 512 * max(s.n_rays for s in scene.sensors)
-    scratch = (torch.empty(max_rays, device="cuda"), torch.empty(max_rays, dtype=torch.int32, device="cuda"))
     torch.cuda.synchronize()
-    budget, K = 4 << 30, 4
-    n_full = 600 if short else args.requests
+    budget, K = 0, 4  # 0: half of the device memory free when the server starts
+    outs = rc.RC_OUT_DEPTH | rc.RC_OUT_SEG
+    free, total = torch.cuda.mem_get_info()
+    res = {"workload": f"cfg5: {WORKLOADS[5]}", "budget": "half of the free device memory at server start",
+           "free_bytes_at_start": free, "streams": K, "outputs": "depth+seg, library-allocated per request"}
+    # the stated arrival process: 10^4 requests at 2000 req/s, batched
+    arr, reqs = make_requests(scene.n_envs, len(scene.sensors), args.requests, 2000.0, 0)
+    log(f"stated run: {args.requests} requests at 2000 req/s")
+    res["stated_2000_req_s"] = st = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, outs)
+    log(f"stated: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, {st['Mrays_s']:.0f} Mrays/s, "
+        f"{st['req_s']:.0f} req/s")
+    m = min(len(reqs), args.plain_requests)
+    res["plain_same_arrivals"] = p = serve_run(R, reqs[:m], arr[:m], rc.RC_SERVE_PLAIN, budget, 1, outs)
+    log(f"plain, first {m}: p50 {p['p50_ms']:.1f} ms p99 {p['p99_ms']:.1f} ms, {p['Mrays_s']:.0f} Mrays/s")
     # saturated throughput: a burst of requests all arriving at t = 0
-    arr, reqs = make_requests(scene.n_envs, len(scene.sensors), 150 if short else 400, 1e9, 1)
-    sat = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, scratch)
+    arr, reqs = make_requests(scene.n_envs, len(scene.sensors), 1000, 1e9, 1)
+    sat = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, outs)
     mean_rays = sum(len(e) * scene.sensors[s].n_rays for e, s in reqs) / len(reqs)
     sat_req_s = sat["Mrays_s"] * 1e6 / mean_rays
+    res.update({"saturated_Mrays_s": sat["Mrays_s"], "saturated_req_s": sat_req_s})
     log(f"saturated {sat['Mrays_s']:.0f} Mrays/s ({sat_req_s:.0f} req/s)")
-    res = {"workload": f"cfg5: {WORKLOADS[5]}", "budget_bytes": budget, "streams": K,
-           "saturated_Mrays_s": sat["Mrays_s"], "saturated_req_s": sat_req_s}
-    # the stated arrival process (2000 req/s), batched
-    arr, reqs = make_requests(scene.n_envs, len(scene.sensors), n_full, 2000.0, 0)
-    res["stated_2000_req_s"] = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, scratch)
-    log(f"stated rate: {res['stated_2000_req_s']}")
     # below saturation, where latency is meaningful; plain server on the same arrivals
     sweep = []
-    for frac in ((0.5,) if short else (0.25, 0.5, 0.75)):
+    for frac in (0.25, 0.5, 0.75):
         rate = frac * sat_req_s
-        n = max(40, int(rate * (2.0 if short else 5.0)))
+        n = max(40, int(rate * 3.0))
         arr, reqs = make_requests(scene.n_envs, len(scene.sensors), n, rate, 2)
-        b = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, scratch)
-        m = min(n, 40 if short else 120)
-        p = serve_run(R, reqs[:m], arr[:m], rc.RC_SERVE_PLAIN, budget, 1, scratch)
+        b = serve_run(R, reqs, arr, rc.RC_SERVE_BATCHED, budget, K, outs)
+        m = min(n, 60)
+        p = serve_run(R, reqs[:m], arr[:m], rc.RC_SERVE_PLAIN, budget, 1, outs)
         sweep.append({"load_frac": frac, "rate_req_s": rate, "batched": b, "plain_same_arrivals_first_n": p})
         log(f"load {frac}: batched p50 {b['p50_ms']:.1f} p99 {b['p99_ms']:.1f} ms; plain p50 {p['p50_ms']:.1f} "
             f"p99 {p['p99_ms']:.1f} ms")
     res["sweep"] = sweep
     R.close()
-    del scratch
     torch.cuda.synchronize()
     return res
 
@@ -422,7 +496,9 @@ def main():
     ap.add_argument("--cfg", type=int, default=3, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--mode", default="batched", choices=["plain", "flat", "batched"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--requests", type=int, default=10000, help="cfg5 requests at the stated arrival rate")
+    ap.add_argument("--plain-requests", type=int, default=150,
+                    help="prefix of the same arrivals served by the plain per-environment server")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -443,8 +519,8 @@ def main():
     else:
         result = bench_step(args)
         if not args.no_serve and args.cfg == 3:
-            log("served summary")
-            result["served"] = bench_serve(args, short=True)
+            log("served (cfg5)")
+            result["served"] = bench_serve(args)
     if not args.no_cpu and args.cfg in (1, 2, 3, 4):
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(args.cfg, args.cpu_seconds)
