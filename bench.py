@@ -200,68 +200,72 @@ def bench_step(args):
     ms = timed(step, args.steps)
     ms_render = timed(render, args.steps)
     ms_refit = timed(lambda: rc.rc_refit(ctx), args.steps)
-    ms_build = timed(lambda: rc.rc_build(ctx), max(2, args.steps // 2))
-    ms_rebuild_step = timed(rebuild_step, max(2, args.steps // 2))
-    log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, transform+refit {ms_refit:.3f} ms; reset: build "
-        f"{ms_build:.3f} ms, step with rebuild {ms_rebuild_step:.3f} ms")
-    # the linear BVH builder (faster build, slower trees); the SAH trees are restored afterwards
+    # --quick (profiling runs): only the step and the render above
+    ms_build = ms_rebuild_step = ms_build_lbvh = ms_render_lbvh = ms_rebuild_step_lbvh = float("nan")
+    further = flat = None
+    if not args.quick:
+        ms_build = timed(lambda: rc.rc_build(ctx), max(2, args.steps // 2))
+        ms_rebuild_step = timed(rebuild_step, max(2, args.steps // 2))
+        log(f"step {ms:.3f} ms: render {ms_render:.3f} ms, transform+refit {ms_refit:.3f} ms; reset: build "
+            f"{ms_build:.3f} ms, step with rebuild {ms_rebuild_step:.3f} ms")
+        # the linear BVH builder (faster build, slower trees); the SAH trees are restored afterwards
 
-    def rebuild_step_lbvh():
-        rc.rc_set_sensor_poses(ctx, R.sensor_T)
-        rc.rc_set_instance_poses(ctx, R.inst_T)
-        rc.rc_build(ctx, rc.RC_BUILD_LBVH)
-        render()
+        def rebuild_step_lbvh():
+            rc.rc_set_sensor_poses(ctx, R.sensor_T)
+            rc.rc_set_instance_poses(ctx, R.inst_T)
+            rc.rc_build(ctx, rc.RC_BUILD_LBVH)
+            render()
 
-    ms_build_lbvh = timed(lambda: rc.rc_build(ctx, rc.RC_BUILD_LBVH), max(2, args.steps // 2))
-    ms_render_lbvh = timed(render, args.steps)
-    ms_rebuild_step_lbvh = timed(rebuild_step_lbvh, max(2, args.steps // 2))
-    rc.rc_build(ctx)
-    torch.cuda.synchronize()
-    log(f"lbvh: build {ms_build_lbvh:.3f} ms, render {ms_render_lbvh:.3f} ms, step with rebuild "
-        f"{ms_rebuild_step_lbvh:.3f} ms")
-    # further data types from the same hits (Sec. III-D): normal, barycentrics, sensor-frame point and
-    # vertex ids derived by a second pass from the winner ids; stereo shadows by segment tests
-    xo = R.alloc(depth=True, seg=True, tri=True, normal=True, bary=True, point=True, vert=True, shadow=stereo)
-
-    def render_tri():
-        rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays)
-
-    def render_all():
-        rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays, normal=xo["normal"],
-                     bary=xo["bary"], point=xo["point"], vert=xo["vert"])
-
-    def render_shadow():
-        rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays, shadow=xo["shadow"])
-
-    n_x = max(2, args.steps // 2)
-    ms_tri = timed(render_tri, n_x)
-    ms_all = timed(render_all, n_x)
-    further = {"render_with_tri_ms": ms_tri, "render_with_all_further_outputs_ms": ms_all,
-               "further_outputs_pass_ms": ms_all - ms_tri,
-               "outputs": "depth, seg, tri, normal[3], bary[2], sensor-frame point[3], vertex ids[3]"}
-    if stereo:
-        ms_sh = timed(render_shadow, n_x)
+        ms_build_lbvh = timed(lambda: rc.rc_build(ctx, rc.RC_BUILD_LBVH), max(2, args.steps // 2))
+        ms_render_lbvh = timed(render, args.steps)
+        ms_rebuild_step_lbvh = timed(rebuild_step_lbvh, max(2, args.steps // 2))
+        rc.rc_build(ctx)
         torch.cuda.synchronize()
-        hits = int((xo["tri"] >= 0).sum())
-        further.update({"render_with_stereo_shadow_ms": ms_sh, "stereo_shadow_pass_ms": ms_sh - ms_tri,
-                        "stereo_baseline_m": 0.095, "shadowed_fraction_of_hits":
-                        float(xo["shadow"].sum()) / max(hits, 1)})
-    log(f"further outputs: {further}")
-    del xo
-    # FLAT: one launch over every tile, no queue (the one-launch baseline of the batched form)
-    def flat_step():
-        rc.rc_set_sensor_poses(ctx, R.sensor_T)
-        rc.rc_set_instance_poses(ctx, R.inst_T)
-        rc.rc_refit(ctx)
-        render(rc.RC_RENDER_FLAT)
-    ms_flat = timed(flat_step, args.steps)
-    ms_flat_render = timed(lambda: render(rc.RC_RENDER_FLAT), args.steps)
-    flat = {"ms_per_step": ms_flat, "Mrays_s": rays / ms_flat / 1e3, "ms_render": ms_flat_render,
-            "render_Mrays_s": rays / ms_flat_render / 1e3, "speedup_batched_vs_flat": ms_flat / ms,
-            "render_speedup_batched_vs_flat": ms_flat_render / ms_render}
-    log(f"flat step {ms_flat:.3f} ms, flat render {ms_flat_render:.3f} ms")
+        log(f"lbvh: build {ms_build_lbvh:.3f} ms, render {ms_render_lbvh:.3f} ms, step with rebuild "
+            f"{ms_rebuild_step_lbvh:.3f} ms")
+        # further data types from the same hits (Sec. III-D): normal, barycentrics, sensor-frame point and
+        # vertex ids derived by a second pass from the winner ids; stereo shadows by segment tests
+        xo = R.alloc(depth=True, seg=True, tri=True, normal=True, bary=True, point=True, vert=True, shadow=stereo)
+
+        def render_tri():
+            rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays)
+
+        def render_all():
+            rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays, normal=xo["normal"],
+                         bary=xo["bary"], point=xo["point"], vert=xo["vert"])
+
+        def render_shadow():
+            rc.rc_render(ctx, xo["depth"], xo["seg"], xo["tri"], None, mode, None, rays, shadow=xo["shadow"])
+
+        n_x = max(2, args.steps // 2)
+        ms_tri = timed(render_tri, n_x)
+        ms_all = timed(render_all, n_x)
+        further = {"render_with_tri_ms": ms_tri, "render_with_all_further_outputs_ms": ms_all,
+                   "further_outputs_pass_ms": ms_all - ms_tri,
+                   "outputs": "depth, seg, tri, normal[3], bary[2], sensor-frame point[3], vertex ids[3]"}
+        if stereo:
+            ms_sh = timed(render_shadow, n_x)
+            torch.cuda.synchronize()
+            hits = int((xo["tri"] >= 0).sum())
+            further.update({"render_with_stereo_shadow_ms": ms_sh, "stereo_shadow_pass_ms": ms_sh - ms_tri,
+                            "stereo_baseline_m": 0.095, "shadowed_fraction_of_hits":
+                            float(xo["shadow"].sum()) / max(hits, 1)})
+        log(f"further outputs: {further}")
+        del xo
+        # FLAT: one launch over every tile, no queue (the one-launch baseline of the batched form)
+        def flat_step():
+            rc.rc_set_sensor_poses(ctx, R.sensor_T)
+            rc.rc_set_instance_poses(ctx, R.inst_T)
+            rc.rc_refit(ctx)
+            render(rc.RC_RENDER_FLAT)
+        ms_flat = timed(flat_step, args.steps)
+        ms_flat_render = timed(lambda: render(rc.RC_RENDER_FLAT), args.steps)
+        flat = {"ms_per_step": ms_flat, "Mrays_s": rays / ms_flat / 1e3, "ms_render": ms_flat_render,
+                "render_Mrays_s": rays / ms_flat_render / 1e3, "speedup_batched_vs_flat": ms_flat / ms,
+                "render_speedup_batched_vs_flat": ms_flat_render / ms_render}
+        log(f"flat step {ms_flat:.3f} ms, flat render {ms_flat_render:.3f} ms")
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and not args.quick:
         def plain_step():
             rc.rc_set_sensor_poses(ctx, R.sensor_T)
             rc.rc_set_instance_poses(ctx, R.inst_T)
@@ -300,7 +304,7 @@ def bench_step(args):
         "render_ms": ms_render,
         "render_Mrays_s": rays / ms_render / 1e3,
         "transform_refit_ms": ms_refit,
-        "reset": {"sah_build_ms": ms_build, "step_with_rebuild_ms": ms_rebuild_step,
+        "reset": None if args.quick else {"sah_build_ms": ms_build, "step_with_rebuild_ms": ms_rebuild_step,
                   "step_with_rebuild_Mrays_s": rays / ms_rebuild_step / 1e3,
                   "env_steps_per_s": n_envs / (ms_rebuild_step * 1e-3),
                   "lbvh": {"build_ms": ms_build_lbvh, "render_ms_on_lbvh_trees": ms_render_lbvh,
@@ -505,6 +509,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reused choices skip the timing)")
     ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
+    ap.add_argument("--quick", action="store_true",
+                    help="time the step and the render only (for profiler runs): no reset, linear-BVH, further "
+                         "outputs, flat or plain legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): environments shard across GPUs "

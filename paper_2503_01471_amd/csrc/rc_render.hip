@@ -39,7 +39,41 @@ struct Ray {
     float ix, iy, iz;
     float knd;  // kErr * max|d_i|
     float tn, tf;
+    // Plane constants of the single-octant slab test (slab_consts): axis a
+    // enters a box at fma(near_a, i_a, cn_a) and leaves it at
+    // fma(far_a, i_a, cf_a).
+    float cnx, cny, cnz, cfx, cfy, cfz;
 };
+
+// cn_a / cf_a = -o_a i_a moved down / up by s_a = 3u |o_a i_a|.  With p the
+// rounded product o_a i_a, the exact value of n i_a + cn_a is at most
+// (n - o_a) i_a: the product's rounding (u |o_a i_a|) and the constant's own
+// (u |p + s_a|) are covered by s_a; likewise the exit lies at or beyond
+// (f - o_a) i_a.  The fused multiply-add then rounds once, so each plane's
+// computed parameter is within one rounding (relative) of the
+// subtract-multiply value's exact counterpart, and the same growth factor
+// kBoxGrow keeps the test conservative.  An infinite or overflowing product
+// (a zero direction component) makes the constants infinite or NaN: the
+// plane parameters are then NaN or an infinity that cannot cull, and
+// fminf / fmaxf ignore NaN operands, so that axis never rejects a box.
+__device__ __forceinline__ float slab_slack(float p) { return (3.0f * kU) * fabsf(p); }
+
+__device__ __forceinline__ void slab_consts(Ray &r)
+{
+    const float px = r.ox * r.ix, py = r.oy * r.iy, pz = r.oz * r.iz;
+    const float sx = slab_slack(px), sy = slab_slack(py), sz = slab_slack(pz);
+    r.cnx = -px - sx;
+    r.cny = -py - sy;
+    r.cnz = -pz - sz;
+    r.cfx = -px + sx;
+    r.cfy = -py + sy;
+    r.cfz = -pz + sz;
+}
+
+__device__ __forceinline__ float uniform_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 
 // Unified wave-uniform view of one work item.
 struct Tile {
@@ -73,9 +107,11 @@ __device__ __forceinline__ void gen_ray(const SensorView &se, const Tile &t, int
     float lx, ly, lz;
     local_dir(se, t, row, col, lx, ly, lz);
     const float *P = se.pose + 12 * (int64_t)t.s;
-    r.ox = P[3];
-    r.oy = P[7];
-    r.oz = P[11];
+    // the origin and the range are those of the tile's sensor instance:
+    // wave-uniform, so they live in scalar registers
+    r.ox = uniform_f(P[3]);
+    r.oy = uniform_f(P[7]);
+    r.oz = uniform_f(P[11]);
     r.dx = fmaf(P[0], lx, fmaf(P[1], ly, P[2] * lz));
     r.dy = fmaf(P[4], lx, fmaf(P[5], ly, P[6] * lz));
     r.dz = fmaf(P[8], lx, fmaf(P[9], ly, P[10] * lz));
@@ -83,8 +119,9 @@ __device__ __forceinline__ void gen_ray(const SensorView &se, const Tile &t, int
     r.iy = 1.0f / r.dy;
     r.iz = 1.0f / r.dz;
     r.knd = kErr * fmaxf(fmaxf(fabsf(r.dx), fabsf(r.dy)), fabsf(r.dz));
-    r.tn = t.tn;
-    r.tf = t.tf;
+    r.tn = uniform_f(t.tn);
+    r.tf = uniform_f(t.tf);
+    slab_consts(r);
 }
 
 __device__ __forceinline__ Tile load_tile(const SensorView &se, int2 item)
@@ -126,14 +163,15 @@ __device__ __forceinline__ bool slab(const Ray &r, float lx, float hx, float ly,
 
 // The same test when every lane of the wavefront has the same direction
 // octant (bit a of OCT: the inverse direction component a has its sign bit
-// set; OCT = kMixed selects the general test above).  Subtraction and
-// multiplication round monotonically, so for a non-negative inverse the low
-// plane's computed t never exceeds the high plane's: the min / max pairs of
-// the general test reduce to a choice by sign.  The one difference is a plane
-// through the origin on an axis the ray runs parallel to (0 * inf = NaN): this
-// form ignores that plane where the general one treats the box as missed.
-// Both are safe, because a stored box lies strictly outside its triangles'
-// bounds (one float step), so such a ray cannot reach a triangle inside it.
+// set; OCT = kMixed selects the general test above).  The near plane of each
+// axis is then known from the sign alone (the low plane for a non-negative
+// inverse), so the min / max pairs of the general test reduce to a choice,
+// and each plane costs one fused multiply-add with the ray's plane constants
+// (slab_consts) instead of a subtraction and a multiplication.  Where the
+// general test treats a plane the ray runs parallel to as a miss or a hit
+// exactly, this one ignores the axis (see slab_consts); both are safe,
+// because a stored box lies strictly outside its triangles' bounds (one float
+// step), so such a ray cannot reach a triangle inside it.
 constexpr int kMixed = 8;
 
 template <int OCT>
@@ -146,8 +184,10 @@ __device__ __forceinline__ bool slab_oct(const Ray &r, float lx, float hx, float
         const float nx = (OCT & 1) ? hx : lx, fx = (OCT & 1) ? lx : hx;
         const float ny = (OCT & 2) ? hy : ly, fy = (OCT & 2) ? ly : hy;
         const float nz = (OCT & 4) ? hz : lz, fz = (OCT & 4) ? lz : hz;
-        const float tmin = fmaxf(fmaxf((nx - r.ox) * r.ix, (ny - r.oy) * r.iy), fmaxf((nz - r.oz) * r.iz, r.tn));
-        const float tmax = fminf(fminf((fx - r.ox) * r.ix, (fy - r.oy) * r.iy), fminf((fz - r.oz) * r.iz, tcap));
+        const float tmin = fmaxf(fmaxf(fmaf(nx, r.ix, r.cnx), fmaf(ny, r.iy, r.cny)),
+                                 fmaxf(fmaf(nz, r.iz, r.cnz), r.tn));
+        const float tmax = fminf(fminf(fmaf(fx, r.ix, r.cfx), fmaf(fy, r.iy, r.cfy)),
+                                 fminf(fmaf(fz, r.iz, r.cfz), tcap));
         tenter = tmin;
         return tmin <= tmax * kBoxGrow;
     }
