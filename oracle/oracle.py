@@ -54,6 +54,11 @@ def load(path: str):
     L.orc_cast.argtypes = [f32, i64, C.c_int64, i32, f32, f32, f32, f32, C.c_int32,
                            f64, i32, f64, f64, f64, f64, f64, f64, i32]
     L.orc_cast.restype = None
+    L.orc_transform64.argtypes = [C.c_int64, f32, i32, f32, f64]
+    L.orc_transform64.restype = None
+    L.orc_cast64.argtypes = [f64, i64, C.c_int64, i32, f32, f32, f32, f32, C.c_int32,
+                             f64, i32, f64, f64, f64, f64, f64, f64, i32]
+    L.orc_cast64.restype = None
     L.orc_move.argtypes = [C.c_int64, f32, f32, np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"),
                            C.c_int32, C.c_float, f32]
     L.orc_move.restype = None
@@ -79,7 +84,7 @@ def lib():
 # --------------------------------------------------------------------------
 @dataclass
 class World:
-    tris: np.ndarray  # float32 [N,9]
+    tris: np.ndarray  # float32 [N,9] (float64 from world64)
     env_off: np.ndarray  # int64 [E+1]
     tri_inst: np.ndarray  # int32 [N] global instance index
     tri_seg: np.ndarray  # int32 [N]
@@ -115,6 +120,17 @@ def world(scene, inst_T=None) -> World:
     corners, tri_inst, env_off = world_corners(scene)
     out = np.empty_like(corners)
     lib().orc_transform(len(corners), corners, tri_inst, T, out)
+    return World(out, env_off, tri_inst, scene.inst_seg[tri_inst].astype(np.int32))
+
+
+def world64(scene, inst_T=None) -> World:
+    """World triangles with the moved vertices kept in FP64, unrounded
+    (``orc_transform64``): the composition of each sub-mesh with its transform
+    that a renderer intersecting in each sub-mesh's own frame computes."""
+    T = np.ascontiguousarray(scene.inst_T if inst_T is None else inst_T, np.float32)
+    corners, tri_inst, env_off = world_corners(scene)
+    out = np.empty(corners.shape, np.float64)
+    lib().orc_transform64(len(corners), corners, tri_inst, T, out)
     return World(out, env_off, tri_inst, scene.inst_seg[tri_inst].astype(np.int32))
 
 
@@ -169,9 +185,12 @@ def cast(w: World, ray_env, o, d, near, far, nthreads: int = 0) -> dict:
                cls=np.empty(n, np.int32))
     if nthreads <= 0:
         nthreads = len(os.sched_getaffinity(0))
-    lib().orc_cast(np.ascontiguousarray(w.tris, np.float32), np.ascontiguousarray(w.env_off, np.int64),
-                   n, ray_env, o, d, near, far, nthreads, out["t"], out["tri"], out["u"], out["v"],
-                   out["hit"], out["mb"], out["md"], out["g"], out["cls"])
+    if w.tris.dtype == np.float64:
+        fn, tris = lib().orc_cast64, np.ascontiguousarray(w.tris, np.float64)
+    else:
+        fn, tris = lib().orc_cast, np.ascontiguousarray(w.tris, np.float32)
+    fn(tris, np.ascontiguousarray(w.env_off, np.int64), n, ray_env, o, d, near, far, nthreads, out["t"],
+       out["tri"], out["u"], out["v"], out["hit"], out["mb"], out["md"], out["g"], out["cls"])
     return out
 
 

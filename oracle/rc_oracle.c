@@ -19,7 +19,10 @@
  *
  * Precision: the vertex transform and the ray directions are FP32 with a
  * fixed fused-multiply-add order (the renderer's input precision); the
- * intersection itself is evaluated in FP64 on those FP32 values.
+ * intersection itself is evaluated in FP64 on those FP32 values.  A second
+ * transform (orc_transform64) keeps the moved vertices in FP64, unrounded,
+ * for renderers that intersect each sub-mesh in its own frame; orc_cast64
+ * runs the same search on those.
  *
  * Readings where the paper is silent (numbered as in the design notes):
  *   near/far is an interval on the ray parameter t (closed); triangles are
@@ -63,6 +66,34 @@ ORC_API void orc_transform(int64_t n, const float *corner_xyz, const int32_t *tr
             for (int r = 0; r < 3; ++r) {
                 const float *row = A + 4 * r;
                 out[9 * i + 3 * c + r] = fmaf(row[0], x, fmaf(row[1], y, fmaf(row[2], z, row[3])));
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* The same sub-mesh transform evaluated in FP64 and not rounded to FP32:   */
+/* out = A[:, :3] v + A[:, 3] for the FP32 pose A and prototype vertex v,   */
+/* as sums of FP64 products ((A_r0 x + A_r1 y) + A_r2 z) + A_r3.  This is   */
+/* the moved mesh of Sec. III-D (each sub-mesh's base mesh composed with    */
+/* its own transform) to FP64 accuracy, which is what a renderer that       */
+/* moves rays into each sub-mesh's frame instead of moving the vertices     */
+/* intersects.                                                              */
+/* ---------------------------------------------------------------------- */
+ORC_API void orc_transform64(int64_t n, const float *corner_xyz, const int32_t *tri_inst,
+                             const float *inst_T, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *A = inst_T + 12 * (int64_t)tri_inst[i];
+        for (int c = 0; c < 3; ++c) {
+            const double x = corner_xyz[9 * i + 3 * c + 0];
+            const double y = corner_xyz[9 * i + 3 * c + 1];
+            const double z = corner_xyz[9 * i + 3 * c + 2];
+            for (int r = 0; r < 3; ++r) {
+                const float *row = A + 4 * r;
+                out[9 * i + 3 * c + r] = (((double)row[0] * x + (double)row[1] * y) + (double)row[2] * z) +
+                                         (double)row[3];
             }
         }
     }
@@ -138,7 +169,8 @@ ORC_API void orc_rays(int32_t kind, int32_t W, int32_t H, float hfov, float vmin
 
 /* ---------------------------------------------------------------------- */
 /* Nearest hit by exhaustive search.                                        */
-/* tris:     [N][9] world triangles (FP32), environment e owns the env-local */
+/* tris:     [N][9] world triangles (FP32; FP64 for orc_cast64),            */
+/*           environment e owns the env-local                                */
 /*           triangles tris[env_off[e] .. env_off[e+1])                      */
 /* per ray:  env, origin o[3], direction d[3], near, far (FP32)              */
 /* outputs (all [n_rays], hit as [n][3]): t (-1 on miss), tri (env-local,    */
@@ -155,7 +187,15 @@ static int cand_less(double ta, int64_t ia, double tb, int64_t ib)
     return ta < tb || (ta == tb && ia < ib);
 }
 
-ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
+/* Corner coordinates of triangle k: from the FP32 array when it is given,  */
+/* else from the FP64 one.                                                  */
+static void tri_corners(const float *t32, const double *t64, int64_t k, double v[9])
+{
+    for (int j = 0; j < 9; ++j)
+        v[j] = t32 ? (double)t32[9 * k + j] : t64[9 * k + j];
+}
+
+static void cast_rays(const float *tris32, const double *tris64, const int64_t *env_off, int64_t n_rays,
                       const int32_t *ray_env, const float *o, const float *d,
                       const float *nearv, const float *farv, int32_t nthreads,
                       double *t_out, int32_t *tri_out, double *u_out, double *v_out,
@@ -177,10 +217,11 @@ ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
 
         const int64_t base = env_off[e], n = env_off[e + 1] - env_off[e];
         for (int64_t k = 0; k < n; ++k) {
-            const float *T = tris + 9 * (base + k);
+            double T[9];
+            tri_corners(tris32, tris64, base + k, T);
             const double ax = T[0], ay = T[1], az = T[2];
-            const double e1x = (double)T[3] - ax, e1y = (double)T[4] - ay, e1z = (double)T[5] - az;
-            const double e2x = (double)T[6] - ax, e2y = (double)T[7] - ay, e2z = (double)T[8] - az;
+            const double e1x = T[3] - ax, e1y = T[4] - ay, e1z = T[5] - az;
+            const double e2x = T[6] - ax, e2y = T[7] - ay, e2z = T[8] - az;
             /* p = d x e2, det = e1 . p */
             const double px = dy * e2z - dz * e2y;
             const double py = dz * e2x - dx * e2z;
@@ -236,9 +277,10 @@ ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
             if (other.id >= 0)
                 md = fmin(md, (other.t - bt) / bt);
             /* grazing cosine |n.d| / (|n| |d|) */
-            const float *T = tris + 9 * (base + bid);
-            const double e1x = (double)T[3] - T[0], e1y = (double)T[4] - T[1], e1z = (double)T[5] - T[2];
-            const double e2x = (double)T[6] - T[0], e2y = (double)T[7] - T[1], e2z = (double)T[8] - T[2];
+            double T[9];
+            tri_corners(tris32, tris64, base + bid, T);
+            const double e1x = T[3] - T[0], e1y = T[4] - T[1], e1z = T[5] - T[2];
+            const double e2x = T[6] - T[0], e2y = T[7] - T[1], e2z = T[8] - T[2];
             const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
             const double g = fabs(nx * dx + ny * dy + nz * dz) /
                              (sqrt(nx * nx + ny * ny + nz * nz) * sqrt(dx * dx + dy * dy + dz * dz));
@@ -264,6 +306,29 @@ ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
         }
         cls_out[r] = cls;
     }
+}
+
+ORC_API void orc_cast(const float *tris, const int64_t *env_off, int64_t n_rays,
+                      const int32_t *ray_env, const float *o, const float *d,
+                      const float *nearv, const float *farv, int32_t nthreads,
+                      double *t_out, int32_t *tri_out, double *u_out, double *v_out,
+                      double *hit_out, double *mb_out, double *md_out, double *g_out,
+                      int32_t *cls_out)
+{
+    cast_rays(tris, NULL, env_off, n_rays, ray_env, o, d, nearv, farv, nthreads, t_out, tri_out, u_out, v_out,
+              hit_out, mb_out, md_out, g_out, cls_out);
+}
+
+/* The same search over FP64 world triangles (orc_transform64).             */
+ORC_API void orc_cast64(const double *tris, const int64_t *env_off, int64_t n_rays,
+                        const int32_t *ray_env, const float *o, const float *d,
+                        const float *nearv, const float *farv, int32_t nthreads,
+                        double *t_out, int32_t *tri_out, double *u_out, double *v_out,
+                        double *hit_out, double *mb_out, double *md_out, double *g_out,
+                        int32_t *cls_out)
+{
+    cast_rays(NULL, tris, env_off, n_rays, ray_env, o, d, nearv, farv, nthreads, t_out, tri_out, u_out, v_out,
+              hit_out, mb_out, md_out, g_out, cls_out);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -800,7 +800,67 @@ def pin_stereo_exact(seeds=range(40)):
     return fails
 
 
+# --------------------------------------------------------------------------
+# 8. FP64 world vertices (the composition a renderer intersecting in each
+#    sub-mesh's own frame computes)
+# --------------------------------------------------------------------------
+def pin_world64(seeds=range(0, 200, 5)):
+    """orc_transform64 against exact rational evaluation of A[:, :3] v + A[:, 3]
+    (rounded once to FP64, so within a few FP64 ulps of the scale); orc_cast64
+    on FP32-representable vertices reproduces orc_cast bit for bit; and on
+    tiny scenes whose vertices are not FP32 numbers it picks the exact
+    rational winner with t to FP64 accuracy."""
+    from fractions import Fraction as Fr
+    fails = []
+    sc = S.make_cfg2(n_envs=2, W=16, H=9)
+    w64 = O.world64(sc)
+    corners, tri_inst, _ = O.world_corners(sc)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(len(corners), 300, replace=False):
+        A = sc.inst_T[tri_inst[k]].astype(np.float64).reshape(3, 4)
+        for c in range(3):
+            v = corners[k, 3 * c:3 * c + 3].astype(np.float64)
+            for r in range(3):
+                ex = sum((Fr(A[r, j]) * Fr(v[j]) for j in range(3)), Fr(A[r, 3]))
+                scale = float(sum(abs(A[r, j] * v[j]) for j in range(3)) + abs(A[r, 3]))
+                if abs(w64.tris[k, 3 * c + r] - float(ex)) > 4 * 2.0 ** -53 * scale:
+                    fails.append(f"world64: triangle {k} corner {c} row {r}: {w64.tris[k, 3 * c + r]} "
+                                 f"exact {float(ex)}")
+    if fails:
+        return fails[:5]
+    # the same search on FP64 copies of FP32 vertices is the FP32 search
+    sc1 = S.make_cfg1()
+    w = O.world(sc1)
+    w64 = O.World(w.tris.astype(np.float64), w.env_off, w.tri_inst, w.tri_seg)
+    o, d = O.sensor_rays(sc1, 0)
+    n = len(o)
+    env = np.zeros(n, np.int32)
+    a = O.cast(w, env, o, d, 0.2, 10.0, nthreads=1)
+    b = O.cast(w64, env, o, d, 0.2, 10.0, nthreads=1)
+    for key in ("t", "tri", "u", "v", "hit", "mb", "md", "g", "cls"):
+        if not np.array_equal(a[key], b[key], equal_nan=True):
+            fails.append(f"cast64: {key} differs from the FP32 search on FP32 vertices")
+    # exact rationals on vertices off the FP32 grid
+    near, far = 0.05, 50.0
+    for seed in seeds:
+        tris, o, d = tiny_scene(seed)
+        g = np.random.default_rng(1000 + seed)
+        t64 = tris.astype(np.float64) * (1.0 + g.uniform(-1e-6, 1e-6, tris.shape)) + g.uniform(-1e-7, 1e-7, tris.shape)
+        wt = O.World(np.ascontiguousarray(t64), np.array([0, len(t64)], np.int64), np.zeros(len(t64), np.int32),
+                     np.zeros(len(t64), np.int32))
+        r = O.cast(wt, np.zeros(len(o), np.int32), o, d, near, far, nthreads=1)
+        for i in range(len(o)):
+            k, t, u, v, m = exact.nearest(list(t64), o[i], d[i], near, far)
+            if m <= 1e-12:
+                continue
+            if r["tri"][i] != k:
+                fails.append(f"cast64 exact seed {seed} ray {i}: oracle tri {r['tri'][i]} exact {k}")
+            elif k >= 0 and abs(r["t"][i] - float(t)) > _t_tol(t64[k], o[i], d[i], float(t)):
+                fails.append(f"cast64 exact seed {seed} ray {i}: t {r['t'][i]} exact {float(t)}")
+    return fails
+
+
 ALL_PINS = [pin_exact, pin_duplicate_tie, pin_ray_plane, pin_boxes, pin_tessellated,
             pin_invariants, pin_transform, pin_motion, pin_rays, pin_table_rays, pin_classifier,
             pin_normals, pin_barycentric, pin_point_cloud, pin_vertex_ids,
-            pin_stereo_pillar, pin_stereo_zero_baseline, pin_stereo_exact]
+            pin_stereo_pillar, pin_stereo_zero_baseline, pin_stereo_exact, pin_world64]

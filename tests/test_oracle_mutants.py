@@ -63,6 +63,14 @@ MUTANTS = {
                                   "double md = (tf - bt) / bt;"),
     "depth_margin_far_dropped": ("double md = fmin((bt - tn) / bt, (tf - bt) / bt);",
                                  "double md = (bt - tn) / bt;"),
+    "transform64_transposed": ("(((double)row[0] * x + (double)row[1] * y) + (double)row[2] * z)",
+                               "(((double)A[r] * x + (double)A[4 + r] * y) + (double)A[8 + r] * z)"),
+    "transform64_z_from_y": ("(double)row[1] * y) + (double)row[2] * z)", "(double)row[1] * y) + (double)row[2] * y)"),
+    "transform64_rounded": ("out[9 * i + 3 * c + r] = (((double)row[0]", "out[9 * i + 3 * c + r] = (float)(((double)row[0]"),
+    "cast64_vertex_shift": ("v[j] = t32 ? (double)t32[9 * k + j] : t64[9 * k + j];",
+                            "v[j] = t32 ? (double)t32[9 * k + j] : t64[9 * k + (j + 3) % 9];"),
+    "cast64_vertices_rounded": ("v[j] = t32 ? (double)t32[9 * k + j] : t64[9 * k + j];",
+                                "v[j] = t32 ? (double)t32[9 * k + j] : (double)(float)t64[9 * k + j];"),
 }
 
 FAST_ARGS = {pins.pin_exact: dict(seeds=range(60))}
