@@ -36,7 +36,7 @@ def test_every_tuning_is_bit_exact():
     R = _R(scene)
     ref = _host(R.render(mode=rc.RC_RENDER_FLAT))
     for tw in (4, 8, 16, 32):
-        for gs in (1, 4, 16):
+        for gs in (1, 2, 4, 16):
             for lpt in (0, 1):
                 _say(f"tuning tile {tw} chunk {gs} lpt {lpt}")
                 rc.rc_tuning_set(R.ctx, tw, gs, lpt)
