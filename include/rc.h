@@ -256,6 +256,22 @@ typedef struct {
 
 rc_status rc_render(rc_context *ctx, const rc_outputs *out, int32_t mode, void *stream);
 
+/* rc_render in the RC_RENDER_BATCHED form for callers that cannot allocate */
+/* device memory (code under HIP graph capture, tight serving loops,         */
+/* harnesses that forbid allocation): the persistent launch's work-queue     */
+/* heads live in a fixed 2 KiB device array of the library (one per GPU,     */
+/* held until the process ends) instead of context memory, and the call      */
+/* makes no allocation of any kind.  Outputs, their layout, the further      */
+/* outputs and the shadow mask are those of rc_render and bit-identical to   */
+/* it.  Every call on one GPU, from any context, shares that array and       */
+/* clears it on `stream` before its launch: calls that overlap on one GPU    */
+/* (other streams, other host threads) race and must be serialised by the    */
+/* caller.  Errors: those of rc_render; RC_E_INVALID when a queue holds more */
+/* tiles than its 32-bit head can count (2^32 - 1 - tiles per pop).  The   */
+/* array's device address is looked up once per GPU by rc_create, which     */
+/* fails with RC_E_HIP if it cannot be found.                                */
+rc_status rc_render_noalloc(rc_context *ctx, const rc_outputs *out, void *stream);
+
 /* Traversal statistics of one FLAT render (same arithmetic, counters added): */
 /* counters host int64[4] = box tests, triangle tests, FP64 re-evaluations,  */
 /* rays.  Synchronous.                                                       */

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -300,6 +301,38 @@ const char *rc_status_string(rc_status s)
 
 const char *rc_last_error(void) { return rc::last_error(); }
 
+// Queue heads of rc_render_noalloc: a fixed device array (2 KiB), one copy
+// per GPU, resident until the process ends and shared by every context on
+// that GPU.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address): rc_create looks up
+// each device's address once, with that device current, and keeps it in
+// g_scratch.
+static __device__ __align__(256) unsigned int scratch[kQueues * kQueueStride];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned int *g_scratch[kScratchDevices] = {};
+}  // namespace
+
+// The current device is `device`.
+static rc_status scratch_setup(int device)
+{
+    RC_CHECK(device < kScratchDevices, "device %d: above the %d devices with static queue heads", device,
+             kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device])
+        return RC_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(RC_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    }
+    g_scratch[device] = (unsigned int *)p;
+    return RC_OK;
+}
+
 rc_status rc_create(int32_t device, void *stream, const rc_allocator *alloc, size_t hbm_budget, rc_context **out)
 {
     RC_CHECK(out, "out is NULL");
@@ -309,6 +342,7 @@ rc_status rc_create(int32_t device, void *stream, const rc_allocator *alloc, siz
     RC_HIP(hipGetDeviceCount(&n));
     RC_CHECK(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
     RC_HIP(hipSetDevice(device));
+    RC_TRY(scratch_setup(device));
     auto *c = new rc_context;
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -724,13 +758,10 @@ static rc_status render_ready(const rc_context *c)
     return RC_OK;
 }
 
-rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *stream)
+// One render on stream st; the batched form's queue heads are `heads`
+// (kQueues * kQueueStride words, cleared here by a fill kernel).
+static rc_status render_on(rc_context *c, const rc_outputs *out, int32_t mode, hipStream_t st, unsigned int *heads)
 {
-    RC_CHECK(c && out, "NULL argument");
-    RC_TRY(render_ready(c));
-    RC_CHECK(mode >= RC_RENDER_PLAIN && mode <= RC_RENDER_BRUTE, "unknown render mode %d", mode);
-    RC_TRY(set_device(c));
-    hipStream_t st = pick(c, stream);
     const Scene &sc = *c->scene;
     Sensors &se = *c->sensors;
     const SceneView sv = sc.sview();
@@ -748,9 +779,12 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
     case RC_RENDER_FLAT:
         RC_HIP(launch_render_flat(sv, ev, ov, 0, se.n_items, st));
         break;
-    case RC_RENDER_BATCHED:
-        RC_HIP(launch_render_batched(sv, ev, ov, se.queue(c->tuning.chunk), c->batched_grid(), st));
+    case RC_RENDER_BATCHED: {
+        QueueView q = se.queue(c->tuning.chunk);
+        q.head = heads;
+        RC_HIP(launch_render_batched(sv, ev, ov, q, c->batched_grid(), st));
         break;
+    }
     case RC_RENDER_BRUTE:
         RC_HIP(launch_render_brute(sv, ev, ov, se.n_items, st));
         break;
@@ -760,6 +794,31 @@ rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *st
     if (out->shadow)
         RC_HIP(launch_stereo_shadow(sv, ev, ov, se.n_items, st));
     return RC_OK;
+}
+
+rc_status rc_render(rc_context *c, const rc_outputs *out, int32_t mode, void *stream)
+{
+    RC_CHECK(c && out, "NULL argument");
+    RC_TRY(render_ready(c));
+    RC_CHECK(mode >= RC_RENDER_PLAIN && mode <= RC_RENDER_BRUTE, "unknown render mode %d", mode);
+    RC_TRY(set_device(c));
+    return render_on(c, out, mode, pick(c, stream), c->sensors->head.as<unsigned int>());
+}
+
+rc_status rc_render_noalloc(rc_context *c, const rc_outputs *out, void *stream)
+{
+    RC_CHECK(c && out, "NULL argument");
+    RC_TRY(render_ready(c));
+    RC_TRY(set_device(c));
+    if (c->device >= kScratchDevices || !g_scratch[c->device])
+        return fail(RC_E_HIP, "no static queue heads for device %d", c->device);
+    const Sensors &se = *c->sensors;
+    // each queue's head counts popped tiles in 32 bits and may pass the end by one pop
+    for (int i = 0; i < kQueues; ++i)
+        RC_CHECK(se.qoff[i + 1] - se.qoff[i] <= (int64_t)(0xffffffffu - (unsigned)c->tuning.chunk),
+                 "queue %d holds %lld tiles: above the 32-bit queue head's limit of %u", i,
+                 (long long)(se.qoff[i + 1] - se.qoff[i]), 0xffffffffu - (unsigned)c->tuning.chunk);
+    return render_on(c, out, RC_RENDER_BATCHED, pick(c, stream), g_scratch[c->device]);
 }
 
 rc_status rc_render_stats(rc_context *c, void *stream, int64_t *counters)

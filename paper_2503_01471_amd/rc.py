@@ -27,7 +27,7 @@ ABI = [
     "rc_status_string", "rc_last_error", "rc_create", "rc_destroy", "rc_memory_used", "rc_mesh_add",
     "rc_scene_load", "rc_sensor_add", "rc_sensors_attach", "rc_ray_layout", "rc_env_tri_offsets",
     "rc_set_instance_poses", "rc_set_sensor_poses", "rc_move_instances", "rc_build", "rc_refit", "rc_render",
-    "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh", "rc_autotune", "rc_tuning_set", "rc_step_graph_create",
+    "rc_render_noalloc", "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh", "rc_autotune", "rc_tuning_set", "rc_step_graph_create",
     "rc_graph_set_step", "rc_graph_launch", "rc_graph_destroy", "rc_server_create", "rc_server_submit",
     "rc_server_poll", "rc_server_wait", "rc_server_outputs", "rc_server_release", "rc_server_destroy",
 ]
@@ -122,6 +122,7 @@ def lib():
             "rc_build": (I32, [P, P, I32, P]),
             "rc_refit": (I32, [P, P, P]),
             "rc_render": (I32, [P, C.POINTER(rc_outputs), I32, P]),
+            "rc_render_noalloc": (I32, [P, C.POINTER(rc_outputs), P]),
             "rc_render_stats": (I32, [P, P, P]),
             "rc_debug_world": (I32, [P, P]),
             "rc_debug_rays": (I32, [P, I32, I64, P, P, P]),
@@ -284,6 +285,12 @@ def rc_render(ctx, depth=None, seg=None, tri=None, hit_xyz=None, mode: int = RC_
               total_rays: int = 0, normal=None, bary=None, point=None, vert=None, shadow=None) -> None:
     out = _outputs(total_rays, depth, seg, tri, hit_xyz, normal, bary, point, vert, shadow)
     _check(lib().rc_render(ctx, C.byref(out), mode, _stream(stream)))
+
+
+def rc_render_noalloc(ctx, depth=None, seg=None, tri=None, hit_xyz=None, stream=None, total_rays: int = 0,
+                      normal=None, bary=None, point=None, vert=None, shadow=None) -> None:
+    out = _outputs(total_rays, depth, seg, tri, hit_xyz, normal, bary, point, vert, shadow)
+    _check(lib().rc_render_noalloc(ctx, C.byref(out), _stream(stream)))
 
 
 def rc_render_stats(ctx, stream=None) -> np.ndarray:
