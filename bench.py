@@ -264,6 +264,9 @@ def bench_step(args):
                 "render_Mrays_s": rays / ms_flat_render / 1e3, "speedup_batched_vs_flat": ms_flat / ms,
                 "render_speedup_batched_vs_flat": ms_flat_render / ms_render}
         log(f"flat step {ms_flat:.3f} ms, flat render {ms_flat_render:.3f} ms")
+        two_level = bench_two_level(args, R, render, step, mode, ms, ms_render)
+    else:
+        two_level = None
     plain = None
     if not args.no_plain and not args.quick:
         def plain_step():
@@ -312,6 +315,7 @@ def bench_step(args):
                            "step_with_rebuild_Mrays_s": rays / ms_rebuild_step_lbvh / 1e3,
                            "env_steps_per_s": n_envs / (ms_rebuild_step_lbvh * 1e-3)}},
         "flat": flat,
+        "two_level": two_level,
         "plain": plain,
         "further_outputs": further,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
@@ -323,6 +327,45 @@ def bench_step(args):
     del out
     torch.cuda.synchronize()
     return result
+
+
+def bench_two_level(args, R, render, step, mode, ms_step, ms_render):
+    """The same step on the two-level form (one BVH per mesh in its own frame,
+    per environment a BVH over instance boxes; rays enter each instance's
+    frame): build time, step (inverse poses and instance boxes, refit of the
+    instance BVH, render), render alone and the library memory the form adds.
+    The single-level SAH trees are rebuilt afterwards."""
+    import torch
+    from paper_2503_01471_amd import rc
+    ctx = R.ctx
+    torch.cuda.synchronize()
+    used0 = rc.rc_memory_used(ctx)
+    rc.rc_build(ctx, rc.RC_BUILD_TWO_LEVEL)
+    torch.cuda.synchronize()
+    added = rc.rc_memory_used(ctx) - used0
+    ms_build = timed(lambda: rc.rc_build(ctx, rc.RC_BUILD_TWO_LEVEL), max(2, args.steps // 2))
+    tuning = rc.rc_autotune(ctx, args.tune_cache) if (mode == rc.RC_RENDER_BATCHED and not args.no_autotune) else None
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps)
+    ms_r = timed(render, args.steps)
+    ms_refit = timed(lambda: rc.rc_refit(ctx), args.steps)
+    stats = R.stats()
+    rays = R.total_rays
+    rc.rc_build(ctx)
+    if tuning is not None:
+        rc.rc_autotune(ctx, args.tune_cache)
+    torch.cuda.synchronize()
+    out = {"build_ms": ms_build, "ms_per_step": ms, "Mrays_s": rays / ms / 1e3, "render_ms": ms_r,
+           "render_Mrays_s": rays / ms_r / 1e3, "inst_prep_refit_ms": ms_refit, "tuning": tuning,
+           "step_vs_single_level": ms_step / ms, "render_vs_single_level": ms_render / ms_r,
+           "added_library_bytes": added,
+           "single_level_library_bytes": used0,
+           "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
+                         "fp64_evals_per_ray": stats[2] / rays}}
+    log(f"two-level: build {ms_build:.3f} ms, step {ms:.3f} ms, render {ms_r:.3f} ms, refit {ms_refit:.3f} ms, "
+        f"+{added / 2**20:.1f} MiB")
+    return out
 
 
 # --------------------------------------------------------------------------

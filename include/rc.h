@@ -188,10 +188,31 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /* read on `stream`; environments whose byte is 0 are left exactly as they  */
 /* are (world triangles, BVH, records), so e.g. the environments reset by a  */
 /* randomisation can be rebuilt alone.  A masked rc_build needs a full       */
-/* build first (RC_E_STATE).                                                 */
+/* build first (RC_E_STATE), with the same form: single-level (SAH, LBVH)   */
+/* or two-level.                                                             */
+/*   RC_BUILD_TWO_LEVEL  two-level instancing (Sec. III-D: one sub-mesh per  */
+/*                  object with its own transform): one BVH per mesh in the  */
+/*                  mesh's own frame, shared by all its instances (built     */
+/*                  once, again only after rc_mesh_add), and per environment */
+/*                  a BVH over its instances' world boxes.  Rays enter each  */
+/*                  visited instance's frame, so no triangle is transformed  */
+/*                  per step: rc_refit recomputes each instance's inverse    */
+/*                  pose and box and refits the instance BVH only.  The      */
+/*                  result is the exact nearest hit on the moved meshes with */
+/*                  the moved vertices unrounded (each mesh under its FP32   */
+/*                  pose, evaluated exactly), where the single-level forms  */
+/*                  intersect the FP32-rounded moved vertices: the two      */
+/*                  agree except where a hit lies within the FP32 rounding   */
+/*                  of the moved vertices of a decision boundary.  Limits:  */
+/*                  8192 instances per environment and 16384 triangles per   */
+/*                  registered mesh (RC_E_INVALID); an instance whose pose   */
+/*                  has a singular linear part is not hit; RC_RENDER_BRUTE  */
+/*                  still tests the FP32 world copy; stereo shadows need a   */
+/*                  single-level build (RC_E_STATE).                         */
 /* ------------------------------------------------------------------------ */
 #define RC_BUILD_SAH 0
 #define RC_BUILD_LBVH 1
+#define RC_BUILD_TWO_LEVEL 2
 rc_status rc_build(rc_context *ctx, const uint8_t *d_env_mask, int32_t builder, void *stream);
 rc_status rc_refit(rc_context *ctx, const uint8_t *d_env_mask, void *stream);
 
@@ -267,9 +288,8 @@ rc_status rc_render(rc_context *ctx, const rc_outputs *out, int32_t mode, void *
 /* clears it on `stream` before its launch: calls that overlap on one GPU    */
 /* (other streams, other host threads) race and must be serialised by the    */
 /* caller.  Errors: those of rc_render; RC_E_INVALID when a queue holds more */
-/* tiles than its 32-bit head can count (2^32 - 1 - tiles per pop).  The   */
-/* array's device address is looked up once per GPU by rc_create, which     */
-/* fails with RC_E_HIP if it cannot be found.                                */
+/* tiles than its 32-bit head can count (2^32 - 1 - tiles per pop); RC_E_HIP */
+/* when the array's device address was not found at rc_create.               */
 rc_status rc_render_noalloc(rc_context *ctx, const rc_outputs *out, void *stream);
 
 /* Traversal statistics of one FLAT render (same arithmetic, counters added): */

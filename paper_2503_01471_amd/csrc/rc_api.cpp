@@ -142,6 +142,22 @@ SceneView Scene::sview() const
     s.tri_src = tri_src.as<int2>();
     s.proto_tri = proto_tri.as<int32_t>();
     s.n_envs = n_envs;
+    if (two_level) {
+        InstView &v = s.inst;
+        v.tnodes = top->nodes.as<Node>();
+        v.trecs = top->recs.as<TriRec>();
+        v.troot = top->env_root.as<int32_t>();
+        v.inst_off = top->d_env_tri_off.as<int64_t>();
+        v.bnodes = bottom->nodes.as<Node>();
+        v.brecs = bottom->recs.as<TriRec>();
+        v.broot = bottom->env_root.as<int32_t>();
+        v.mesh_tri_off = bottom->d_env_tri_off.as<int64_t>();
+        v.inst_info = inst_info.as<int4>();
+        v.inv = inst_inv.as<double>();
+        v.n_inst = n_inst;
+        v.bnode_count = node_base(bottom->n_tris, bottom->n_envs) + 16;
+        v.brec_count = bottom->n_tris;
+    }
     return s;
 }
 
@@ -356,7 +372,8 @@ rc_status rc_create(int32_t device, void *stream, const rc_allocator *alloc, siz
         return fail(RC_E_HIP, "hipGetDeviceProperties failed");
     }
     c->n_cu = prop.multiProcessorCount;
-    c->blocks_per_cu = batched_blocks_per_cu();
+    c->blocks_per_cu = batched_blocks_per_cu(false);
+    c->blocks_per_cu_two = batched_blocks_per_cu(true);
     *out = c;
     return RC_OK;
 }
@@ -400,25 +417,17 @@ rc_status rc_mesh_add(rc_context *c, const float *xyz, int32_t n_verts, const in
     return RC_OK;
 }
 
-rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offsets, const int32_t *inst_mesh,
-                        const int32_t *inst_seg, const uint8_t *inst_dynamic)
+// Device tables of a scene over `n_envs` environments with the given CSR
+// instance lists (validated by the caller).  Every instance contributes its
+// mesh's triangles, or one primitive each with one_prim (a two-level scene's
+// top level: one box per instance, built like triangles).  `prim_limit`
+// bounds the primitives per environment.
+static rc_status make_scene(rc_context *c, int32_t n_envs, const int64_t *inst_offsets, const int32_t *inst_mesh,
+                            const int32_t *inst_seg, const uint8_t *inst_dynamic, bool one_prim, int64_t prim_limit,
+                            std::unique_ptr<Scene> &out)
 {
-    RC_CHECK(c, "NULL context");
-    RC_TRY(busy_check(c));
-    RC_CHECK(n_envs >= 0, "n_envs < 0");
-    RC_CHECK(inst_offsets, "inst_offsets is NULL");
-    RC_CHECK(inst_offsets[0] == 0, "inst_offsets[0] != 0");
-    for (int32_t e = 0; e < n_envs; ++e)
-        RC_CHECK(inst_offsets[e + 1] >= inst_offsets[e], "inst_offsets not non-decreasing at %d", e);
-    const int64_t n_inst = inst_offsets[n_envs];
-    RC_CHECK(n_inst == 0 || (inst_mesh && inst_seg), "NULL instance arrays");
-    const int64_t n_meshes = (int64_t)c->meshes.size();
-    for (int64_t i = 0; i < n_inst; ++i)
-        RC_CHECK(inst_mesh[i] >= 0 && inst_mesh[i] < n_meshes, "inst_mesh[%lld] = %d is not a mesh id",
-                 (long long)i, inst_mesh[i]);
-    RC_TRY(set_device(c));
     hipStream_t st = c->stream;
-
+    const int64_t n_inst = inst_offsets[n_envs];
     auto sc = std::make_unique<Scene>();
     sc->n_envs = n_envs;
     sc->n_inst = n_inst;
@@ -427,12 +436,13 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     for (int32_t e = 0; e < n_envs; ++e) {
         int64_t t = 0;
         for (int64_t i = inst_offsets[e]; i < inst_offsets[e + 1]; ++i)
-            t += c->meshes[inst_mesh[i]].n_tris;
-        RC_CHECK(t <= kMaxEnvTris, "environment %d has %lld triangles (limit %lld)", e, (long long)t,
-                 (long long)kMaxEnvTris);
+            t += one_prim ? 1 : c->meshes[inst_mesh[i]].n_tris;
+        RC_CHECK(t <= prim_limit, "environment %d has %lld %s (limit %lld)", e, (long long)t,
+                 one_prim ? "instances" : "triangles", (long long)prim_limit);
         sc->env_tri_off[e + 1] = sc->env_tri_off[e] + t;
     }
     const int64_t N = sc->env_tri_off[n_envs];
+    RC_CHECK(N < INT32_MAX, "too many triangles");
     sc->n_tris = N;
     std::vector<int32_t> tri_env(N), tri_seg(N), dyn;
     std::vector<int2> tri_src(N);
@@ -445,7 +455,8 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
             const bool d = inst_dynamic && inst_dynamic[i];
             dynf[i] = d;
             inst_env[i] = e;
-            for (int64_t k = 0; k < m.n_tris; ++k, ++g) {
+            const int64_t n = one_prim ? 1 : m.n_tris;
+            for (int64_t k = 0; k < n; ++k, ++g) {
                 tri_env[g] = e;
                 tri_seg[g] = inst_seg[i];
                 tri_src[g] = make_int2((int)i, (int)(m.tri_off + k));
@@ -454,7 +465,6 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
             }
         }
     }
-    RC_CHECK(N < INT32_MAX, "too many triangles");
     sc->n_dyn = (int64_t)dyn.size();
     RC_TRY(upload(c, sc->proto_xyz, c->mesh_xyz.data(), c->mesh_xyz.size(), st));
     RC_TRY(upload(c, sc->proto_tri, c->mesh_tri.data(), c->mesh_tri.size(), st));
@@ -489,7 +499,32 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
     RC_TRY(c->pool.alloc(sc->local_off, 8 * ((size_t)n_envs + 1)));
     RC_TRY(c->pool.alloc(sc->sah_mask, (size_t)n_envs + 16));
     RC_TRY(c->pool.alloc(sc->leaf_src, 16 * N));
-    RC_HIP(hipStreamSynchronize(st));
+    out = std::move(sc);
+    return RC_OK;
+}
+
+rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offsets, const int32_t *inst_mesh,
+                        const int32_t *inst_seg, const uint8_t *inst_dynamic)
+{
+    RC_CHECK(c, "NULL context");
+    RC_TRY(busy_check(c));
+    RC_CHECK(n_envs >= 0, "n_envs < 0");
+    RC_CHECK(inst_offsets, "inst_offsets is NULL");
+    RC_CHECK(inst_offsets[0] == 0, "inst_offsets[0] != 0");
+    for (int32_t e = 0; e < n_envs; ++e)
+        RC_CHECK(inst_offsets[e + 1] >= inst_offsets[e], "inst_offsets not non-decreasing at %d", e);
+    const int64_t n_inst = inst_offsets[n_envs];
+    RC_CHECK(n_inst == 0 || (inst_mesh && inst_seg), "NULL instance arrays");
+    const int64_t n_meshes = (int64_t)c->meshes.size();
+    for (int64_t i = 0; i < n_inst; ++i)
+        RC_CHECK(inst_mesh[i] >= 0 && inst_mesh[i] < n_meshes, "inst_mesh[%lld] = %d is not a mesh id",
+                 (long long)i, inst_mesh[i]);
+    RC_TRY(set_device(c));
+    std::unique_ptr<Scene> sc;
+    RC_TRY(make_scene(c, n_envs, inst_offsets, inst_mesh, inst_seg, inst_dynamic, false, kMaxEnvTris, sc));
+    sc->inst_mesh.assign(inst_mesh, inst_mesh + n_inst);
+    sc->inst_seg_h.assign(inst_seg, inst_seg + n_inst);
+    RC_HIP(hipStreamSynchronize(c->stream));
     c->sensors.reset();
     c->scene = std::move(sc);
     ++c->generation;
@@ -677,18 +712,115 @@ static rc_status world_fresh(Scene &sc, hipStream_t st)
     return RC_OK;
 }
 
+// Per-instance inverse poses and top-level boxes of a two-level scene (with
+// recs: also the top level's leaf records, for its refit).
+static rc_status inst_prep(Scene &sc, const uint8_t *d_env_mask, bool recs, hipStream_t st)
+{
+    InstPrep p;
+    p.n_inst = sc.n_inst;
+    p.inst_T = sc.inst_T.as<float>();
+    p.inst_env = sc.inst_env.as<int32_t>();
+    p.env_mask = d_env_mask;
+    p.inst_info = sc.inst_info.as<int4>();
+    p.mesh_box = sc.mesh_box.as<float>();
+    p.env_off = sc.top->d_env_tri_off.as<int64_t>();
+    p.inv = sc.inst_inv.as<double>();
+    p.world = sc.top->world.as<float>();
+    p.recs = recs ? sc.top->recs.as<TriRec>() : nullptr;
+    p.pos_of = sc.top->pos_of.as<int32_t>();
+    RC_HIP(launch_inst_prep(p, st));
+    return RC_OK;
+}
+
+// The bottom level (one BVH per mesh in the mesh's own frame, shared by all
+// its instances) and the per-instance tables of a two-level scene; rebuilt
+// only when meshes were added since.
+static rc_status two_level_tables(rc_context *c, Scene &sc, hipStream_t st)
+{
+    const int64_t M = (int64_t)c->meshes.size();
+    const int64_t bottom_limit = (int64_t)kLeafMax << (kBottomDepth + 1);
+    for (int64_t m = 0; m < M; ++m)
+        RC_CHECK(c->meshes[m].n_tris <= bottom_limit,
+                 "mesh %lld has %lld triangles: a two-level build admits %lld per mesh", (long long)m,
+                 (long long)c->meshes[m].n_tris, (long long)bottom_limit);
+    if (!sc.bottom || sc.bottom_meshes != M) {
+        std::vector<int64_t> off(M + 1);
+        std::vector<int32_t> mesh(M), seg(M, 0);
+        for (int64_t m = 0; m <= M; ++m)
+            off[m] = m;
+        for (int64_t m = 0; m < M; ++m)
+            mesh[m] = (int32_t)m;
+        std::unique_ptr<Scene> bot;
+        RC_TRY(make_scene(c, (int32_t)M, off.data(), mesh.data(), seg.data(), nullptr, false, bottom_limit, bot));
+        std::vector<float> eye(12 * M, 0.f);
+        for (int64_t m = 0; m < M; ++m)
+            eye[12 * m + 0] = eye[12 * m + 5] = eye[12 * m + 10] = 1.f;
+        RC_HIP(hipMemcpyAsync(bot->inst_T.p, eye.data(), 48 * M, hipMemcpyHostToDevice, st));
+        BuildView bv = bot->view();
+        bv.max_depth = kBottomDepth;
+        RC_HIP(launch_transform(bv, nullptr, bot->n_tris, false, st));
+        RC_HIP(launch_build_sah(bv, st));
+        // each mesh's vertex bounds (of the vertices its triangles use)
+        std::vector<float> box(6 * M);
+        for (int64_t m = 0; m < M; ++m) {
+            const Mesh &h = c->meshes[m];
+            float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int64_t k = 0; k < 3 * h.n_tris; ++k) {
+                const float *v = &c->mesh_xyz[3 * (size_t)c->mesh_tri[3 * h.tri_off + k]];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], v[a]);
+                    hi[a] = fmaxf(hi[a], v[a]);
+                }
+            }
+            for (int a = 0; a < 3; ++a) {
+                box[6 * m + a] = lo[a];
+                box[6 * m + 3 + a] = hi[a];
+            }
+        }
+        RC_TRY(upload(c, sc.mesh_box, box.data(), box.size(), st));
+        RC_HIP(hipStreamSynchronize(st));  // the host tables above go out of scope
+        sc.bottom = std::move(bot);
+        sc.bottom_meshes = M;
+    }
+    if (!sc.top) {
+        std::vector<int32_t> one(sc.n_inst, 0);
+        std::unique_ptr<Scene> top;
+        RC_TRY(make_scene(c, sc.n_envs, sc.inst_offsets.data(), one.data(), sc.inst_seg_h.data(), nullptr, true,
+                          (int64_t)kLeafMax << (kTopDepth + 1), top));
+        std::vector<int4> info(sc.n_inst);
+        for (int32_t e = 0; e < sc.n_envs; ++e) {
+            int64_t t = 0;
+            for (int64_t i = sc.inst_offsets[e]; i < sc.inst_offsets[e + 1]; ++i) {
+                info[i] = make_int4(sc.inst_mesh[i], (int)t, 0, 0);
+                t += c->meshes[sc.inst_mesh[i]].n_tris;
+            }
+        }
+        RC_TRY(upload(c, sc.inst_info, info.data(), info.size(), st));
+        RC_TRY(c->pool.alloc(sc.inst_inv, 96 * (size_t)sc.n_inst));
+        RC_HIP(hipStreamSynchronize(st));
+        sc.top = std::move(top);
+    }
+    return RC_OK;
+}
+
 rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, void *stream)
 {
     RC_CHECK(c, "NULL context");
     RC_TRY(busy_check(c));
-    RC_CHECK(builder == RC_BUILD_SAH || builder == RC_BUILD_LBVH, "unknown builder %d", builder);
+    RC_CHECK(builder == RC_BUILD_SAH || builder == RC_BUILD_LBVH || builder == RC_BUILD_TWO_LEVEL,
+             "unknown builder %d", builder);
     if (!c->scene || !c->scene->poses_set)
         return fail(RC_E_STATE, "rc_build needs a scene and instance poses");
     Scene &sc = *c->scene;
+    const bool two = builder == RC_BUILD_TWO_LEVEL;
     if (d_env_mask && !sc.built)
         return fail(RC_E_STATE, "a masked rc_build needs a full build first");
+    if (d_env_mask && two != sc.two_level)
+        return fail(RC_E_STATE, "a masked rc_build must use the form (two-level or not) of the last full build");
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
+    if (two)  // before any work is queued: this may fail on the mesh size limit
+        RC_TRY(two_level_tables(c, sc, st));
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
     RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
@@ -697,10 +829,23 @@ rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, vo
                                 sc.inst_T.as<float>(), sc.inst_Tw.as<float>(), nullptr, st));
     if (!d_env_mask)
         RC_TRY(world_fresh(sc, st));
-    if (builder == RC_BUILD_LBVH)
-        RC_HIP(launch_build_lbvh(v, sc.sah_mask.as<uint8_t>(), st));
-    else
-        RC_HIP(launch_build_sah(v, st));
+    if (two) {
+        // the single-level BVH is not built
+        RC_TRY(inst_prep(sc, d_env_mask, false, st));
+        BuildView tv = sc.top->view();
+        tv.env_mask = d_env_mask;
+        tv.max_depth = kTopDepth;
+        RC_HIP(launch_build_sah(tv, st));
+    } else {
+        if (builder == RC_BUILD_LBVH)
+            RC_HIP(launch_build_lbvh(v, sc.sah_mask.as<uint8_t>(), st));
+        else
+            RC_HIP(launch_build_sah(v, st));
+    }
+    if (!d_env_mask && two != sc.two_level)
+        ++c->generation;  // captured step graphs hold the other form's kernels
+    if (!d_env_mask)
+        sc.two_level = two;
     sc.built = true;
     return RC_OK;
 }
@@ -714,6 +859,23 @@ rc_status rc_refit(rc_context *c, const uint8_t *d_env_mask, void *stream)
     Scene &sc = *c->scene;
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
+    if (sc.two_level) {
+        // new inverse poses and top-level boxes, then the top level's refit;
+        // the mesh-frame bottom level never changes
+        RC_TRY(inst_prep(sc, d_env_mask, true, st));
+        BuildView tv = sc.top->view();
+        tv.env_mask = d_env_mask;
+        RC_HIP(launch_refit(tv, st));
+        if (sc.n_dyn > 0) {
+            RC_HIP(launch_pose_snapshot(sc.n_inst, sc.inst_env.as<int32_t>(), sc.inst_dyn.as<uint8_t>(), d_env_mask,
+                                        true, sc.inst_T.as<float>(), sc.inst_Tw.as<float>(),
+                                        d_env_mask ? sc.stale_env.as<uint8_t>() : nullptr, st));
+            sc.world_stale = true;
+            if (!d_env_mask)
+                sc.stale_all = true;
+        }
+        return RC_OK;
+    }
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
     if (sc.n_dyn > 0) {
@@ -769,6 +931,8 @@ static rc_status render_on(rc_context *c, const rc_outputs *out, int32_t mode, h
     const OutView ov = out_view(*out);
     const bool extras = out->normal || out->bary || out->point || out->vert;
     RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
+    if (out->shadow && sc.two_level)
+        return fail(RC_E_STATE, "stereo shadows need the single-level BVH (rc_build with RC_BUILD_SAH or LBVH)");
     if (mode == RC_RENDER_BRUTE || extras || out->shadow)
         RC_TRY(fresh_world(c, st));
     switch (mode) {
@@ -810,8 +974,7 @@ rc_status rc_render_noalloc(rc_context *c, const rc_outputs *out, void *stream)
     RC_CHECK(c && out, "NULL argument");
     RC_TRY(render_ready(c));
     RC_TRY(set_device(c));
-    if (c->device >= kScratchDevices || !g_scratch[c->device])
-        return fail(RC_E_HIP, "no static queue heads for device %d", c->device);
+    RC_CHECK(c->device < kScratchDevices && g_scratch[c->device], "no static queue heads for device %d", c->device);
     const Sensors &se = *c->sensors;
     // each queue's head counts popped tiles in 32 bits and may pass the end by one pop
     for (int i = 0; i < kQueues; ++i)
@@ -885,6 +1048,8 @@ rc_status rc_debug_bvh(rc_context *c, int32_t e, int32_t *n_nodes, float *boxes,
     if (!c->scene || !c->scene->built)
         return fail(RC_E_STATE, "no built scene");
     const Scene &sc = *c->scene;
+    if (sc.two_level)
+        return fail(RC_E_STATE, "the scene's last build was two-level");
     RC_CHECK(e >= 0 && e < sc.n_envs, "environment %d out of range", e);
     RC_TRY(set_device(c));
     RC_HIP(hipStreamSynchronize(c->stream));

@@ -46,6 +46,8 @@ std::string workload_key(const rc_context *c)
     snprintf(buf, sizeof buf, "%s/cu%d/envs%d/tris%lld/rays%lld/si%lld", arch.c_str(), c->n_cu, c->scene->n_envs,
              (long long)c->scene->n_tris, (long long)c->sensors->total_rays, (long long)c->sensors->n_si);
     std::string key = buf;
+    if (c->scene->two_level)
+        key += "/two";
     for (const ModelHost &h : c->models) {
         snprintf(buf, sizeof buf, "/m%d.%dx%d", h.m.kind, h.m.W, h.m.H);
         key += buf;
@@ -172,6 +174,8 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
     RC_CHECK(std::isfinite(dt), "dt not finite");
     const bool extras = out->normal || out->bary || out->point || out->vert;
     RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
+    if (out->shadow && sc.two_level)
+        return fail(RC_E_STATE, "stereo shadows need the single-level BVH (rc_build with RC_BUILD_SAH or LBVH)");
     RC_TRY(set_device(c));
     auto g = new rc_graph;
     g->ctx = c;
@@ -201,14 +205,36 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
         // original-order world copy) both copies are transformed; otherwise
         // the leaf-ordered records only.
         g->world_kept = extras || out->shadow;
-        if (k == hipSuccess && sc.n_dyn > 0)
+        if (sc.two_level) {
+            // two-level: the moved triangles go to the world copy only (when
+            // the further outputs read it); each instance's inverse pose and
+            // box, then the refit of the instance BVH
+            if (k == hipSuccess && sc.n_dyn > 0 && g->world_kept)
+                k = launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, false, cs);
+            if (k == hipSuccess) {
+                InstPrep p;
+                p.n_inst = sc.n_inst;
+                p.inst_T = sc.inst_T.as<float>();
+                p.inst_env = sc.inst_env.as<int32_t>();
+                p.env_mask = nullptr;
+                p.inst_info = sc.inst_info.as<int4>();
+                p.mesh_box = sc.mesh_box.as<float>();
+                p.env_off = sc.top->d_env_tri_off.as<int64_t>();
+                p.inv = sc.inst_inv.as<double>();
+                p.world = sc.top->world.as<float>();
+                p.recs = sc.top->recs.as<TriRec>();
+                p.pos_of = sc.top->pos_of.as<int32_t>();
+                k = launch_inst_prep(p, cs);
+            }
+        } else if (k == hipSuccess && sc.n_dyn > 0) {
             k = g->world_kept ? launch_transform(v, sc.dyn_tris.as<int32_t>(), sc.n_dyn, true, cs)
                               : launch_transform_leaf(v, cs);
+        }
         if (k == hipSuccess && sc.n_dyn > 0)
             k = launch_pose_snapshot(sc.n_inst, sc.inst_env.as<int32_t>(), sc.inst_dyn.as<uint8_t>(), nullptr, true,
                                      sc.inst_T.as<float>(), sc.inst_Tw.as<float>(), nullptr, cs);
         if (k == hipSuccess)
-            k = launch_refit(v, cs);
+            k = launch_refit(sc.two_level ? sc.top->view() : v, cs);
         if (k == hipSuccess)
             k = launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk), c->batched_grid(), cs);
         if (k == hipSuccess && extras)

@@ -240,6 +240,83 @@ __global__ __launch_bounds__(256) void k_pose_snapshot(int64_t n, const int32_t 
         stale_env[e] = 1;  // every writer stores the same value
 }
 
+// K1c: two-level scenes, one thread per instance.  The inverse of the pose's
+// linear part A comes from its adjugate in FP64 (the pose's FP32 entries are
+// exact in FP64, so M = adj(A) / det(A) is A^-1 to FP64 rounding); the world
+// box of the mesh box [lo, hi] under x -> A x + p is p_r + sum_j min / max
+// (A_rj lo_j, A_rj hi_j) per row, the exact interval image (the products are
+// exact in FP64), rounded outward to FP32.
+__global__ __launch_bounds__(256) void k_inst_prep(InstPrep q)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= q.n_inst)
+        return;
+    const int e = q.inst_env[i];
+    if (q.env_mask && !q.env_mask[e])
+        return;
+    const float *T = q.inst_T + 12 * i;
+    double a[3][3], p[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            a[r][c] = (double)T[4 * r + c];
+        p[r] = (double)T[4 * r + 3];
+    }
+    // adjugate (transpose of the cofactor matrix)
+    double m[3][3];
+    m[0][0] = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+    m[0][1] = a[0][2] * a[2][1] - a[0][1] * a[2][2];
+    m[0][2] = a[0][1] * a[1][2] - a[0][2] * a[1][1];
+    m[1][0] = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+    m[1][1] = a[0][0] * a[2][2] - a[0][2] * a[2][0];
+    m[1][2] = a[0][2] * a[1][0] - a[0][0] * a[1][2];
+    m[2][0] = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+    m[2][1] = a[0][1] * a[2][0] - a[0][0] * a[2][1];
+    m[2][2] = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+    const double det = a[0][0] * m[0][0] + a[0][1] * m[1][0] + a[0][2] * m[2][0];
+    const bool ok = det != 0.0 && isfinite(det);
+    double *inv = q.inv + 12 * i;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            inv[4 * r + c] = ok ? m[r][c] / det : __builtin_nan("");
+        inv[4 * r + 3] = p[r];
+    }
+    const float *mb = q.mesh_box + 6 * (int64_t)q.inst_info[i].x;
+    float lo[3], hi[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double l = p[r], h = p[r];
+        if (ok) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double u0 = a[r][c] * (double)mb[c], u1 = a[r][c] * (double)mb[3 + c];
+                l += fmin(u0, u1);
+                h += fmax(u0, u1);
+            }
+        }
+        lo[r] = __double2float_rd(l);
+        hi[r] = __double2float_ru(h);
+    }
+    float *w = q.world + 9 * i;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        w[r] = lo[r];
+        w[3 + r] = hi[r];
+        w[6 + r] = lo[r];
+    }
+    if (q.recs) {
+        const int64_t base = q.env_off[e];
+        TriRec rec;
+        rec.a = make_float4(lo[0], lo[1], lo[2], hi[0]);
+        rec.b = make_float4(hi[1], hi[2], lo[0], lo[1]);
+        rec.c = make_float4(lo[2], __int_as_float((int)(i - base)), 0.f, 0.f);
+        q.recs[base + q.pos_of[i]] = rec;
+    }
+}
+
 // K8: constant-velocity motion of dynamic instances.
 // The step comes from d_step when it is set (a captured step graph advances
 // it on the device), else from the argument.
@@ -776,7 +853,7 @@ __device__ __forceinline__ void sah_job(const BuildView &v, BuildShared &S, int 
                     usable |= ext > 0.f;
                 }
             }
-            const bool forced = depth + levels_needed(cnt) - 1 >= kMaxNodeDepth;
+            const bool forced = depth + levels_needed(cnt) - 1 >= v.max_depth;
 
             int mid = -1, best_axis = -1, best_k = -1;
             WaveBox L{}, R{};
@@ -1215,10 +1292,11 @@ __device__ __forceinline__ int group_split(const WaveBox &bx, int pid, int gl, i
 
 // Largest side a micro split at depth dd may leave: a side of s > kLeafMax
 // primitives becomes a node at depth dd + 1 whose subtree needs
-// levels_needed(s) more levels, and internal nodes stay within kMaxNodeDepth.
-__device__ __forceinline__ int micro_cap(int dd)
+// levels_needed(s) more levels, and internal nodes stay within the depth
+// bound md.
+__device__ __forceinline__ int micro_cap(int dd, int md)
 {
-    const int m = kMaxNodeDepth - dd;
+    const int m = md - dd;
     return m >= 2 ? kGroup : (kLeafMax << (m < 0 ? 0 : m));
 }
 
@@ -1230,10 +1308,10 @@ __device__ __forceinline__ int micro_cap(int dd)
 // right, so each partition once).
 // gbox: the group's boxes in LDS, lane r's at gbox[r] (lo.x lo.y lo.z hi.x,
 // hi.y hi.z).
-__device__ __forceinline__ bool micro_leaf(const float4 (*gbox)[2], int gl, int first, int c, int dd)
+__device__ __forceinline__ bool micro_leaf(const float4 (*gbox)[2], int gl, int first, int c, int dd, int md)
 {
     static_assert(kLeafMax <= 5, "2^(kLeafMax-1) - 1 partitions must fit in the 16-lane group");
-    if (c <= 1 || dd >= kMaxNodeDepth)  // a split would put a node below the depth bound
+    if (c <= 1 || dd >= md)  // a split would put a node below the depth bound
         return true;
     WaveBox B[kLeafMax];
     WaveBox U = kEmptyBox;
@@ -1311,7 +1389,7 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
         while (true) {
             int order;
             WaveBox L, R;
-            const int k = group_split(bx, pid, gl, f, c, micro_cap(dd), order, L, R);
+            const int k = group_split(bx, pid, gl, f, c, micro_cap(dd, v.max_depth), order, L, R);
             // lanes f .. f + c - 1 take the chosen axis order
             const int src = __shfl(order, (gl - f) & (kGroup - 1), kGroup) & (kGroup - 1);
             const WaveBox nb = box_shfl(bx, src);
@@ -1326,7 +1404,7 @@ __global__ __launch_bounds__(kMicroBlock) void k_build_micro(BuildView v)
             int ref[2];
 #pragma unroll
             for (int sd = 0; sd < 2; ++sd) {
-                if (cc[sd] <= kLeafMax && micro_leaf(gbox, gl, cf[sd], cc[sd], dd + 1)) {
+                if (cc[sd] <= kLeafMax && micro_leaf(gbox, gl, cf[sd], cc[sd], dd + 1, v.max_depth)) {
                     ref[sd] = leaf_ref(task.y + cf[sd], cc[sd]);
                 } else {
                     ref[sd] = next++;
@@ -1790,6 +1868,14 @@ hipError_t launch_pose_snapshot(int64_t n_inst, const int32_t *inst_env, const u
         return hipSuccess;
     hipLaunchKernelGGL(k_pose_snapshot, dim3(blocks_for(n_inst, 256)), dim3(256), 0, st, n_inst, inst_env, dyn,
                        env_mask, (int)dyn_only, src, dst, stale_env);
+    return hipGetLastError();
+}
+
+hipError_t launch_inst_prep(const InstPrep &p, hipStream_t st)
+{
+    if (p.n_inst == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_inst_prep, dim3(blocks_for(p.n_inst, 256)), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

@@ -78,6 +78,31 @@ struct SensorModel {
 // ---------------------------------------------------------------------------
 // Kernel argument views.
 // ---------------------------------------------------------------------------
+// Two-level scenes: a top-level BVH per environment over its instances'
+// world boxes and one bottom-level BVH per mesh in the mesh's own frame,
+// shared by every instance of the mesh; rays enter each visited instance's
+// frame.  The top level is a BVH over one box primitive per instance, stored
+// with the layout of the triangle BVH: environment e's nodes start at
+// node_base(inst_off[e], e), and each leaf record holds the box (lo, hi, lo)
+// as a triangle and the environment-local instance index as its id.
+constexpr int kTopDepth = 10;     // top-level internal-node depth bound (<= 4 << 11 instances per env)
+constexpr int kBottomDepth = 11;  // bottom-level bound (<= 4 << 12 triangles per mesh)
+static_assert((kTopDepth + 1) + (kBottomDepth + 1) <= kStack, "both levels share the traversal stack");
+struct InstView {
+    const Node *tnodes = nullptr;        // top level; tnodes == nullptr: a flat scene
+    const TriRec *trecs = nullptr;       // top-level leaf records, env e from inst_off[e]
+    const int32_t *troot = nullptr;      // [E]
+    const int64_t *inst_off = nullptr;   // [E+1]
+    const Node *bnodes = nullptr;        // bottom levels, mesh m at node_base(mesh_tri_off[m], m)
+    const TriRec *brecs = nullptr;       // mesh triangles in their own frame, mesh m from mesh_tri_off[m]
+    const int32_t *broot = nullptr;      // [M]
+    const int64_t *mesh_tri_off = nullptr;  // [M+1]
+    const int4 *inst_info = nullptr;     // [I] mesh, environment-local id of the instance's first triangle
+    const double *inv = nullptr;         // [I][12] FP64 rows (M_r0 M_r1 M_r2 p_r) with M the inverse of
+                                         // the pose's linear part and p its translation
+    int64_t n_inst = 0, bnode_count = 0, brec_count = 0;  // sizes of the arrays above (range-checked loads)
+};
+
 struct SceneView {
     const int64_t *env_tri_off;  // [E+1]
     const int32_t *env_root;     // [E]
@@ -88,6 +113,7 @@ struct SceneView {
     const int2 *tri_src;         // [N] (instance, global prototype triangle)
     const int32_t *proto_tri;    // prototype triangles (global vertex ids)
     int32_t n_envs;
+    InstView inst;               // set for a two-level scene
 };
 
 struct SensorView {
@@ -146,6 +172,7 @@ struct BuildView {
     int32_t *level_nodes;        // node slots of env e grouped by depth (same base as nodes)
     int32_t *level_off;          // [E][kLevels + 1] depth d of env e = level_nodes[off[d] .. off[d+1])
     const uint8_t *env_mask;     // [E] environments to process (nullptr: all)
+    int32_t max_depth = kMaxNodeDepth;  // internal-node depth bound of the trees built (<= kMaxNodeDepth)
 };
 
 // True when environment e is excluded by the build/refit mask.
@@ -164,6 +191,27 @@ hipError_t launch_transform_leaf(const BuildView &v, hipStream_t st);
 // each such environment in stale_env when it is set.
 hipError_t launch_pose_snapshot(int64_t n_inst, const int32_t *inst_env, const uint8_t *dyn, const uint8_t *env_mask,
                                 bool dyn_only, const float *src, float *dst, uint8_t *stale_env, hipStream_t st);
+// Two-level scenes, per instance: the FP64 inverse of the pose (InstView::inv)
+// and the world box of its mesh's box under the pose, as the box primitive
+// (lo, hi, lo) of the top level in original order (world, 9 floats per
+// instance) and, with recs set, in the top level's leaf-ordered records
+// (recs[env_off[e] + pos_of[i]]).  A pose with a singular linear part gets a
+// zero-volume box at its translation and an all-NaN inverse (its instance
+// is never hit).  Only environments in env_mask (all when null).
+struct InstPrep {
+    int64_t n_inst;
+    const float *inst_T;        // [I][12]
+    const int32_t *inst_env;    // [I]
+    const uint8_t *env_mask;
+    const int4 *inst_info;      // [I] mesh, ...
+    const float *mesh_box;      // [M][6] lo.xyz hi.xyz of the mesh's vertices
+    const int64_t *env_off;     // [E+1] instances per environment (top-level primitive ranges)
+    double *inv;                // [I][12]
+    float *world;               // [I][9]
+    TriRec *recs;               // nullptr: records not written
+    const int32_t *pos_of;      // [I] leaf position of an environment's instance
+};
+hipError_t launch_inst_prep(const InstPrep &p, hipStream_t st);
 hipError_t launch_move(int64_t n_inst, const float *T0, const float *vel, const uint8_t *dyn, int32_t step,
                        const int32_t *d_step, float dt, float *T, hipStream_t st);
 hipError_t launch_bump(int32_t *d_step, hipStream_t st);
@@ -187,7 +235,7 @@ struct QueueView {
 };
 hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, const OutView &o, const QueueView &q,
                                  int grid, hipStream_t st);
-int batched_blocks_per_cu();
+int batched_blocks_per_cu(bool two_level);  // resident blocks per CU of the persistent kernel
 // Normals, barycentrics, sensor-frame points and vertex ids of rendered rays
 // (needs o.tri from a preceding render of the same rays).
 hipError_t launch_hit_extras(const SceneView &sc, const SensorView &se, const OutView &o, int64_t n_items,

@@ -32,8 +32,15 @@ constexpr int kBlock = 256;
 #define RC_MIN_WAVES 6
 #endif
 #define RC_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(RC_MIN_WAVES, 8)))
+// Two-level scenes keep a second (object-space) ray in registers: four waves
+// per SIMD (128 VGPRs).
+#ifndef RC_MIN_WAVES_TWO
+#define RC_MIN_WAVES_TWO 4
+#endif
+#define RC_WAVES_PER_EU_T __attribute__((amdgpu_waves_per_eu(TWO ? RC_MIN_WAVES_TWO : RC_MIN_WAVES, 8)))
 
 struct Ray {
+    static constexpr bool kObject = false;
     float ox, oy, oz;
     float dx, dy, dz;
     float ix, iy, iz;
@@ -233,8 +240,9 @@ __device__ __forceinline__ int wave_octant(const Ray &r)
 // ---------------------------------------------------------------------------
 enum { kReject = 0, kAccept = 1, kUnsure = 2 };
 
-__device__ __forceinline__ int mt32(const Ray &r, const float4 A, const float4 B, const float4 C, float tcap,
-                                    float &t, float &et)
+template <class R>
+__device__ __forceinline__ int mt32(const R &r, const float4 A, const float4 B, const float4 C, float tcap, float &t,
+                                    float &et)
 {
     const float e1x = A.w - A.x, e1y = B.x - A.y, e1z = B.y - A.z;
     const float e2x = B.z - A.x, e2y = B.w - A.y, e2z = C.x - A.z;
@@ -251,7 +259,9 @@ __device__ __forceinline__ int mt32(const Ray &r, const float4 A, const float4 B
     const float W = fmaf(e2x, qx, fmaf(e2y, qy, e2z * qz));
     const float n1 = fmaxf(fmaxf(fabsf(e1x), fabsf(e1y)), fabsf(e1z));
     const float n2 = fmaxf(fmaxf(fabsf(e2x), fabsf(e2y)), fabsf(e2z));
-    const float nT = fmaxf(fmaxf(fabsf(Tx), fabsf(Ty)), fabsf(Tz));
+    float nT = fmaxf(fmaxf(fabsf(Tx), fabsf(Ty)), fabsf(Tz));
+    if constexpr (R::kObject)
+        nT += r.no;  // the ray's FP32 origin is a rounded one (ObjRay)
     const float kT = r.knd * nT;
     const float eD = r.knd * n1 * n2;
     const float eU = kT * n2;
@@ -329,6 +339,7 @@ struct Best {
     int id;        // environment-local triangle id
     bool have64;
     double t64;
+    int inst = -1;  // two-level scenes: the winner's instance (pos indexes its mesh's records)
 };
 
 struct Stats {
@@ -469,6 +480,316 @@ __device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, cons
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-level scenes.  The world ray walks the environment's top level (instance
+// boxes); at a top-level leaf it enters each instance's frame and walks the
+// bottom level of that instance's mesh, with the same certified tests.
+//
+// The object-space ray is O = M (o - p), D = M d in FP64 (M the FP64 inverse
+// of the pose's linear part), which is the exact ray in the mesh's frame up
+// to FP64 rounding; the FP32 ray (o', d') the tests run on is O, D rounded, so
+// each component is within u of it.  The tests stay conservative for the
+// exact ray by widening: the bottom-level boxes by 2u (|o'_a| + far |d'_a|)
+// per axis (a point of the exact ray at t <= far lies that close to the same
+// point of the FP32 ray), and the triangle tests' error bounds by using
+// max|T| + max|o'| for the norm of T = o' - v0 (the rounding of o' and d'
+// adds at most 12u times the products the bounds already cover with
+// kErr = 128u against the 48u of the FP32 evaluation).  Uncertain tests and
+// the winner's t are evaluated in FP64 on O and D.  Results therefore equal
+// the exact nearest hit on the moved meshes (each mesh under its pose, not
+// rounded to FP32) up to FP64 rounding, with the lowest environment-local
+// triangle id winning ties.
+// ---------------------------------------------------------------------------
+struct ObjRay {
+    static constexpr bool kObject = true;
+    float ox, oy, oz;
+    float dx, dy, dz;
+    float ix, iy, iz;
+    float knd;  // kErr * max|d'_i|
+    float no;   // max|o'_i|
+    float tn, tf;
+    float cnx, cny, cnz, cfx, cfy, cfz;  // widened plane constants (slab_obj)
+};
+
+// The 12 FP64 inverse-pose entries of instance inst (InstView::inv) through a
+// range-checked view.
+__device__ __forceinline__ void load_inv(Rsrc inv, int inst, double (&M)[12])
+{
+    const uint32_t off = (uint32_t)inst * 96u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int4 v = ldi4(inv, off + 16u * k);
+        M[2 * k] = __hiloint2double(v.y, v.x);
+        M[2 * k + 1] = __hiloint2double(v.w, v.z);
+    }
+}
+
+__device__ __forceinline__ void obj_ray(const Ray &r, const double (&M)[12], ObjRay &q)
+{
+    const double wx = (double)r.ox - M[3], wy = (double)r.oy - M[7], wz = (double)r.oz - M[11];
+    const double dx = r.dx, dy = r.dy, dz = r.dz;
+    q.ox = (float)(M[0] * wx + M[1] * wy + M[2] * wz);
+    q.oy = (float)(M[4] * wx + M[5] * wy + M[6] * wz);
+    q.oz = (float)(M[8] * wx + M[9] * wy + M[10] * wz);
+    q.dx = (float)(M[0] * dx + M[1] * dy + M[2] * dz);
+    q.dy = (float)(M[4] * dx + M[5] * dy + M[6] * dz);
+    q.dz = (float)(M[8] * dx + M[9] * dy + M[10] * dz);
+    q.ix = 1.0f / q.dx;
+    q.iy = 1.0f / q.dy;
+    q.iz = 1.0f / q.dz;
+    q.knd = kErr * fmaxf(fmaxf(fabsf(q.dx), fabsf(q.dy)), fabsf(q.dz));
+    q.no = fmaxf(fmaxf(fabsf(q.ox), fabsf(q.oy)), fabsf(q.oz));
+    q.tn = r.tn;
+    q.tf = r.tf;
+    // plane parameter p_a = o'_a i_a: slab_consts' 3u |p_a| for the product's
+    // and the constant's rounding, plus the widening 2u (|o'_a| + far |d'_a|)
+    // |i_a| <= 2u (|p_a| + far) (1 + u)^2, each taken twice
+    const float px = q.ox * q.ix, py = q.oy * q.iy, pz = q.oz * q.iz;
+    const float ft = (4.0f * kU) * q.tf;
+    const float sx = fmaf(8.0f * kU, fabsf(px), ft), sy = fmaf(8.0f * kU, fabsf(py), ft),
+                sz = fmaf(8.0f * kU, fabsf(pz), ft);
+    q.cnx = -px - sx;
+    q.cny = -py - sy;
+    q.cnz = -pz - sz;
+    q.cfx = -px + sx;
+    q.cfy = -py + sy;
+    q.cfz = -pz + sz;
+}
+
+// Slab test of the object-space ray, the near plane of each axis chosen per
+// lane by the sign of the inverse direction (slab_oct's test with the widened
+// constants).
+__device__ __forceinline__ bool slab_obj(const ObjRay &q, float lx, float hx, float ly, float hy, float lz, float hz,
+                                         float tcap, float &tenter)
+{
+    const bool sx = signbit(q.ix), sy = signbit(q.iy), sz = signbit(q.iz);
+    const float nx = sx ? hx : lx, fx = sx ? lx : hx;
+    const float ny = sy ? hy : ly, fy = sy ? ly : hy;
+    const float nz = sz ? hz : lz, fz = sz ? lz : hz;
+    const float tmin = fmaxf(fmaxf(fmaf(nx, q.ix, q.cnx), fmaf(ny, q.iy, q.cny)), fmaxf(fmaf(nz, q.iz, q.cnz), q.tn));
+    const float tmax = fminf(fminf(fmaf(fx, q.ix, q.cfx), fmaf(fy, q.iy, q.cfy)), fminf(fmaf(fz, q.iz, q.cfz), tcap));
+    tenter = tmin;
+    return tmin <= tmax * kBoxGrow;
+}
+
+// FP64 Moller-Trumbore of the exact object-space ray (O, D recomputed from
+// the world ray and the instance's inverse) against one record; out of line
+// like mt64v.
+__device__ __noinline__ T64 mt64obj(float ox, float oy, float oz, float dxf, float dyf, float dzf, float tn, float tf,
+                                    Rsrc inv, int inst, float4 A, float4 B, float4 C)
+{
+    T64 res{0.0, 0};
+    double M[12];
+    load_inv(inv, inst, M);
+    const double wx = (double)ox - M[3], wy = (double)oy - M[7], wz = (double)oz - M[11];
+    const double Ox = M[0] * wx + M[1] * wy + M[2] * wz;
+    const double Oy = M[4] * wx + M[5] * wy + M[6] * wz;
+    const double Oz = M[8] * wx + M[9] * wy + M[10] * wz;
+    const double dx = M[0] * (double)dxf + M[1] * (double)dyf + M[2] * (double)dzf;
+    const double dy = M[4] * (double)dxf + M[5] * (double)dyf + M[6] * (double)dzf;
+    const double dz = M[8] * (double)dxf + M[9] * (double)dyf + M[10] * (double)dzf;
+    const double ax = A.x, ay = A.y, az = A.z;
+    const double e1x = (double)A.w - ax, e1y = (double)B.x - ay, e1z = (double)B.y - az;
+    const double e2x = (double)B.z - ax, e2y = (double)B.w - ay, e2z = (double)C.x - az;
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    double det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0 || !(det == det))
+        return res;
+    const double Tx = Ox - ax, Ty = Oy - ay, Tz = Oz - az;
+    const double qx = Ty * e1z - Tz * e1y, qy = Tz * e1x - Tx * e1z, qz = Tx * e1y - Ty * e1x;
+    double U = Tx * px + Ty * py + Tz * pz;
+    double V = dx * qx + dy * qy + dz * qz;
+    double W = e2x * qx + e2y * qy + e2z * qz;
+    if (det < 0.0) {
+        det = -det;
+        U = -U;
+        V = -V;
+        W = -W;
+    }
+    if (U < 0.0 || V < 0.0 || U + V > det)
+        return res;
+    res.t = W / det;
+    res.ok = res.t >= (double)tn && res.t <= (double)tf;
+    return res;
+}
+
+// Range-checked views of a two-level scene's shared arrays (wave-uniform:
+// one descriptor each, per-lane 32-bit offsets).
+struct TwoViews {
+    Rsrc bnodes, brecs, inv, info;
+};
+
+__device__ __forceinline__ TwoViews two_views(const InstView &iv)
+{
+    TwoViews v;
+    v.bnodes = buffer_view(iv.bnodes, iv.bnode_count * (int64_t)sizeof(Node));
+    v.brecs = buffer_view(iv.brecs, iv.brec_count * (int64_t)sizeof(TriRec));
+    v.inv = buffer_view(iv.inv, iv.n_inst * 96);
+    v.info = buffer_view(iv.inst_info, iv.n_inst * 16);
+    return v;
+}
+
+__device__ __forceinline__ void ld_rec(Rsrc recs, int pos, float4 &a, float4 &b, float4 &c)
+{
+    const uint32_t off = (uint32_t)pos * (uint32_t)sizeof(TriRec);
+    a = ldf4(recs, off);
+    b = ldf4(recs, off + 16);
+    c = ldf4(recs, off + 32);
+}
+
+// Offer record pos (mesh records) of instance inst, environment-local id
+// idc, to the running winner.
+template <bool STATS>
+__device__ __forceinline__ void offer_obj(const Ray &r, const ObjRay &q, const TwoViews &tv, int inst, int pos,
+                                         int idc, const float4 A, const float4 B, const float4 C, Best &b, Stats &st)
+{
+    float t, et;
+    const int code = mt32(q, A, B, C, b.hi, t, et);
+    if (code == kReject)
+        return;
+    if (code == kAccept && t + et < b.lo) {
+        b.lo = t - et;
+        b.hi = t + et;
+        b.pos = pos;
+        b.id = idc;
+        b.inst = inst;
+        b.have64 = false;
+        return;
+    }
+    if (STATS)
+        ++st.fp64;
+    const T64 c = mt64obj(r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tn, r.tf, tv.inv, inst, A, B, C);
+    if (!c.ok)
+        return;
+    if (b.pos >= 0 && !b.have64) {
+        float4 wa, wb, wc;
+        ld_rec(tv.brecs, b.pos, wa, wb, wc);
+        const T64 cw = mt64obj(r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tn, r.tf, tv.inv, b.inst, wa, wb, wc);
+        if (cw.ok) {
+            b.t64 = cw.t;
+            b.have64 = true;
+        } else {
+            b.pos = -1;  // cannot happen for a certain accept; drop it defensively
+        }
+    }
+    if (b.pos < 0 || c.t < b.t64 || (c.t == b.t64 && idc < b.id)) {
+        b.pos = pos;
+        b.id = idc;
+        b.inst = inst;
+        b.t64 = c.t;
+        b.have64 = true;
+        const float tf = (float)c.t;
+        b.lo = tf * (1.0f - 0x1p-23f);
+        b.hi = tf * (1.0f + 0x1p-23f);
+    }
+}
+
+// Bottom level of one instance; the stack entries above sp0 are this walk's.
+template <bool STATS>
+__device__ __forceinline__ void walk_instance(const Ray &r, const InstView &iv, const TwoViews &tv, int inst, int *stk,
+                                              int sp0, Best &b, Stats &st)
+{
+    const int4 info = ldi4(tv.info, (uint32_t)inst * 16u);
+    const int m = info.x;
+    int ref = iv.broot[m];
+    if (ref == kEmptyRoot)
+        return;
+    ObjRay q;
+    {
+        double M[12];
+        load_inv(tv.inv, inst, M);
+        obj_ray(r, M, q);
+    }
+    const int64_t rb = iv.mesh_tri_off[m];
+    const uint32_t nbase = (uint32_t)node_base(rb, m) * (uint32_t)sizeof(Node);
+    int sp = sp0;
+    while (true) {
+        if (ref >= 0) {
+            const uint32_t off = nbase + (uint32_t)ref * (uint32_t)sizeof(Node);
+            const float4 a = ldf4(tv.bnodes, off), c = ldf4(tv.bnodes, off + 16), z = ldf4(tv.bnodes, off + 32);
+            const int4 ch = ldi4(tv.bnodes, off + 48);
+            __builtin_amdgcn_sched_barrier(0);
+            float t0, t1;
+            const bool h0 = slab_obj(q, a.x, a.y, a.z, a.w, z.x, z.y, b.hi, t0);
+            const bool h1 = slab_obj(q, c.x, c.y, c.z, c.w, z.z, z.w, b.hi, t1);
+            if (STATS)
+                st.box += 2;
+            if (h0 && h1) {
+                const bool first0 = t0 <= t1;
+                stk[sp * kBlock] = first0 ? ch.y : ch.x;
+                ++sp;
+                ref = first0 ? ch.x : ch.y;
+            } else if (h0 || h1) {
+                ref = h0 ? ch.x : ch.y;
+            } else {
+                ref = sp > sp0 ? stk[--sp * kBlock] : kDone;
+            }
+        } else if (ref == kDone) {
+            break;
+        } else {
+            const int code = ~ref;
+            const int first = code >> 3, cnt = (code & 7) + 1;
+            for (int k = 0; k < cnt; ++k) {
+                const int pos = (int)rb + first + k;
+                float4 ra, rbb, rc;
+                ld_rec(tv.brecs, pos, ra, rbb, rc);
+                if (STATS)
+                    ++st.tri;
+                offer_obj<STATS>(r, q, tv, inst, pos, info.y + __float_as_int(rc.y), ra, rbb, rc, b, st);
+            }
+            ref = sp > sp0 ? stk[--sp * kBlock] : kDone;
+        }
+    }
+}
+
+// Top level of environment env with the world ray.
+template <bool STATS>
+__device__ __forceinline__ void traverse_two(const Ray &r, const InstView &iv, int env, int *stk, Best &b, Stats &st)
+{
+    int ref = iv.troot[env];
+    if (ref == kEmptyRoot)
+        return;
+    const int64_t ib = iv.inst_off[env];
+    const int64_t n_inst = iv.inst_off[env + 1] - ib;
+    const int64_t tb = node_base(ib, env);
+    const Rsrc tnodes = buffer_view(iv.tnodes + tb, (node_base(ib + n_inst, env + 1) - tb) * (int64_t)sizeof(Node));
+    const Rsrc trecs = buffer_view(iv.trecs + ib, n_inst * (int64_t)sizeof(TriRec));
+    const TwoViews tv = two_views(iv);
+    int sp = 0;
+    while (true) {
+        while (ref >= 0) {
+            const uint32_t off = (uint32_t)ref * (uint32_t)sizeof(Node);
+            const float4 a = ldf4(tnodes, off), c = ldf4(tnodes, off + 16), z = ldf4(tnodes, off + 32);
+            const int4 ch = ldi4(tnodes, off + 48);
+            __builtin_amdgcn_sched_barrier(0);
+            float t0, t1;
+            const bool h0 = slab(r, a.x, a.y, a.z, a.w, z.x, z.y, b.hi, t0);
+            const bool h1 = slab(r, c.x, c.y, c.z, c.w, z.z, z.w, b.hi, t1);
+            if (STATS)
+                st.box += 2;
+            if (h0 && h1) {
+                const bool first0 = t0 <= t1;
+                stk[sp * kBlock] = first0 ? ch.y : ch.x;
+                ++sp;
+                ref = first0 ? ch.x : ch.y;
+            } else if (h0 || h1) {
+                ref = h0 ? ch.x : ch.y;
+            } else {
+                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+            }
+        }
+        if (ref == kDone)
+            break;
+        const int code = ~ref;
+        const int first = code >> 3, cnt = (code & 7) + 1;
+        ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+        for (int k = 0; k < cnt; ++k) {
+            const int li = __float_as_int(ldf4(trecs, (uint32_t)(first + k) * (uint32_t)sizeof(TriRec) + 32).y);
+            walk_instance<STATS>(r, iv, tv, (int)ib + li, stk, sp, b, st);
+        }
+    }
+}
+
 // Final outputs of one ray from the winner (FP64 t, re-evaluated if the
 // winner was accepted in FP32; hit = o + t d).
 __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc, const SensorView &se, const Tile &tl,
@@ -530,7 +851,7 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
 }
 
 // One 8x8 tile per wavefront.
-template <bool STATS>
+template <bool STATS, bool TWO>
 __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorView &se, const OutView &o, int2 item,
                                             int *stk, Stats &st)
 {
@@ -545,14 +866,27 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
     Ray r;
     gen_ray(se, t, row, col, r);
     Best b{r.tf, r.tf, -1, -1, false, 0.0};
-    const int64_t base = sc.env_tri_off[t.env], end = sc.env_tri_off[t.env + 1];
-    const int64_t nb = node_base(base, t.env);
-    const Rsrc nodes = buffer_view(sc.nodes + nb, (node_base(end, t.env + 1) - nb) * (int64_t)sizeof(Node));
-    const TriRec *recs = sc.recs + base;
-    const Rsrc rv = buffer_view(recs, (end - base) * (int64_t)sizeof(TriRec));
-    const int root = sc.env_root[t.env];
-    if (root != kEmptyRoot)
-        traverse<STATS>(r, nodes, rv, recs, root, stk, b, st);
+    const TriRec *recs = nullptr;
+    if constexpr (TWO) {
+        traverse_two<STATS>(r, sc.inst, t.env, stk, b, st);
+        if (b.pos >= 0 && !b.have64) {  // the winner's t in FP64 on the exact object-space ray
+            const TwoViews tv = two_views(sc.inst);
+            float4 wa, wb, wc;
+            ld_rec(tv.brecs, b.pos, wa, wb, wc);
+            const T64 c = mt64obj(r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r.tn, r.tf, tv.inv, b.inst, wa, wb, wc);
+            b.t64 = c.ok ? c.t : 0.5 * ((double)b.lo + (double)b.hi);
+            b.have64 = true;
+        }
+    } else {
+        const int64_t base = sc.env_tri_off[t.env], end = sc.env_tri_off[t.env + 1];
+        const int64_t nb = node_base(base, t.env);
+        const Rsrc nodes = buffer_view(sc.nodes + nb, (node_base(end, t.env + 1) - nb) * (int64_t)sizeof(Node));
+        recs = sc.recs + base;
+        const Rsrc rv = buffer_view(recs, (end - base) * (int64_t)sizeof(TriRec));
+        const int root = sc.env_root[t.env];
+        if (root != kEmptyRoot)
+            traverse<STATS>(r, nodes, rv, recs, root, stk, b, st);
+    }
     // The output position is recomputed here from the lane: the empty asm
     // hides that it equals the one above, so the compiler does not keep
     // address arithmetic alive (spilled) across the traversal.
@@ -571,7 +905,8 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return x * q + (x < rem ? x : rem) + (b >> 3);
 }
 
-__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
                                                         int64_t n_items)
 {
     __shared__ int s_stack[kStack * kBlock];
@@ -580,10 +915,11 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_flat(SceneVie
     if (k >= n_items)
         return;
     Stats st{0, 0, 0};
-    render_tile<false>(sc, se, o, se.items[item_begin + k], s_stack + threadIdx.x, st);
+    render_tile<false, TWO>(sc, se, o, se.items[item_begin + k], s_stack + threadIdx.x, st);
 }
 
-__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
                                                          unsigned long long *counters)
 {
     __shared__ int s_stack[kStack * kBlock];
@@ -592,7 +928,7 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_stats(SceneVi
     if (k >= n_items)
         return;
     Stats st{0, 0, 0};
-    render_tile<true>(sc, se, o, se.items[k], s_stack + threadIdx.x, st);
+    render_tile<true, TWO>(sc, se, o, se.items[k], s_stack + threadIdx.x, st);
     unsigned box = st.box, tri = st.tri, f64 = st.fp64;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -609,7 +945,8 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_stats(SceneVi
 
 // Persistent form: every wavefront pops `chunk` tiles at a time from its
 // XCD's queue and, once that is empty, from the other queues in turn.
-__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_batched(SceneView sc, SensorView se, OutView o,
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_batched(SceneView sc, SensorView se, OutView o,
                                                                            QueueView q)
 {
     __shared__ int s_stack[kStack * kBlock];
@@ -629,7 +966,7 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU void k_render_batched(Scene
         }
         const int64_t stop = b + q.chunk < e ? b + q.chunk : e;
         for (int64_t k = b; k < stop; ++k)
-            render_tile<false>(sc, se, o, q.items[k], s_stack + threadIdx.x, st);
+            render_tile<false, TWO>(sc, se, o, q.items[k], s_stack + threadIdx.x, st);
     }
 }
 
@@ -954,15 +1291,22 @@ hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const O
 {
     if (n_items == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_render_flat, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se, o,
-                       item_begin, n_items);
+    if (sc.inst.tnodes)
+        hipLaunchKernelGGL(k_render_flat<true>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
+                           o, item_begin, n_items);
+    else
+        hipLaunchKernelGGL(k_render_flat<false>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
+                           o, item_begin, n_items);
     return hipGetLastError();
 }
 
-int batched_blocks_per_cu()
+int batched_blocks_per_cu(bool two_level)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched, kBlock, 0) != hipSuccess || per_cu < 1)
+    const hipError_t e = two_level
+                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched<true>, kBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched<false>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
@@ -975,7 +1319,10 @@ hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, cons
     hipError_t err = launch_fill_u32(q.head, kQueues * kQueueStride, 0u, st);
     if (err != hipSuccess)
         return err;
-    hipLaunchKernelGGL(k_render_batched, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
+    if (sc.inst.tnodes)
+        hipLaunchKernelGGL(k_render_batched<true>, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
+    else
+        hipLaunchKernelGGL(k_render_batched<false>, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
     return hipGetLastError();
 }
 
@@ -1014,8 +1361,12 @@ hipError_t launch_render_stats(const SceneView &sc, const SensorView &se, const 
 {
     if (n_items == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_render_stats, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se, o,
-                       n_items, counters);
+    if (sc.inst.tnodes)
+        hipLaunchKernelGGL(k_render_stats<true>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
+                           o, n_items, counters);
+    else
+        hipLaunchKernelGGL(k_render_stats<false>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
+                           o, n_items, counters);
     return hipGetLastError();
 }
 

@@ -92,6 +92,16 @@ struct Scene {
     DBuf stale_env;  // [E] (padded to whole words) environments whose world copy is stale
     bool world_stale = false;  // some environment may be stale
     bool stale_all = false;    // every environment may be stale
+    std::vector<int32_t> inst_mesh, inst_seg_h;  // host copies of the instance lists
+    // Two-level form (rc_build with RC_BUILD_TWO_LEVEL): `top` holds one box
+    // primitive per instance, `bottom` one environment per mesh (identity
+    // pose), each built with the depth bound of its level.
+    std::unique_ptr<Scene> top, bottom;
+    DBuf inst_info;  // [I] int4: mesh, environment-local id of the instance's first triangle
+    DBuf inst_inv;   // [I][12] double (InstView::inv)
+    DBuf mesh_box;   // [M][6] float: each mesh's vertex bounds
+    int64_t bottom_meshes = 0;  // meshes the bottom level covers
+    bool two_level = false;     // the last full build was two-level
     BuildView view() const;
     SceneView sview() const;
 };
@@ -148,10 +158,10 @@ struct rc_context {
     std::unique_ptr<rc::Scene> scene;
     std::unique_ptr<rc::Sensors> sensors;
     rc::Tuning tuning;
-    int n_cu = 0, blocks_per_cu = 1;
+    int n_cu = 0, blocks_per_cu = 1, blocks_per_cu_two = 1;
     uint64_t generation = 0;   // bumped whenever scene or sensors are replaced
     std::atomic<int> servers{0};  // live request servers (scene is read-only meanwhile)
-    int batched_grid() const { return n_cu * blocks_per_cu; }
+    int batched_grid() const { return n_cu * (scene && scene->two_level ? blocks_per_cu_two : blocks_per_cu); }
 };
 
 namespace rc {

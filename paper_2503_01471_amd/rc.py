@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "librc.so")
 RC_PINHOLE, RC_LIDAR, RC_TABLE = 0, 1, 2
 RC_BUILD_SAH = 0
 RC_BUILD_LBVH = 1
+RC_BUILD_TWO_LEVEL = 2
 RC_RENDER_PLAIN, RC_RENDER_FLAT, RC_RENDER_BATCHED, RC_RENDER_BRUTE = 0, 1, 2, 3
 
 # Every function declared in include/rc.h.
