@@ -13,13 +13,16 @@ rebuild of every BVH, done at randomisation) is timed beside it, alone and as
 a step that rebuilds instead of refitting.
 
 Prints ONE JSON line: Mrays/s (whole job), env-steps/s, the render kernel's
-roofline position, the same step in the flat form (one launch, no queue) and
-on the plain per-environment path, the served form at its stated size (10^4
-requests of 1-512 environments arriving at 2000 req/s, p50/p99 latency and
-throughput, with the plain server on the same arrivals for a prefix) and the
+roofline position, the same step in the flat form (one launch, no queue), on
+the two-level form (per-mesh BVHs in the mesh frame under a per-environment
+instance BVH) and on the plain per-environment path, the served form at its
+stated size (10^4 requests of 1-512 environments arriving at 2000 req/s,
+p50/p99 latency and throughput, with the plain server on the same arrivals for
+a prefix), the camera-room workload (1024 envs, 480x270) and the uneven moving
+batch (2048 envs, one captured HIP graph per step) as further legs, and the
 CPU oracle timed on this host on a bounded sample.  --cfg 4 times the
-per-step HIP graph of the uneven moving-obstacle batch, --cfg 5 the serving
-run alone.
+per-step HIP graph of the uneven moving-obstacle batch alone, --cfg 5 the
+serving run alone.
 """
 from __future__ import annotations
 
@@ -403,6 +406,21 @@ def bench_graph(args):
     ms_plain = timed(plain_step, 5)
     log(f"plain step {ms_plain:.3f} ms")
     rc.rc_graph_destroy(g)
+    # the same graph on the two-level form (instance boxes refitted, no triangle transformed per step)
+    used0 = rc.rc_memory_used(ctx)
+    rc.rc_build(ctx, rc.RC_BUILD_TWO_LEVEL)
+    torch.cuda.synchronize()
+    added = rc.rc_memory_used(ctx) - used0
+    tuning2 = rc.rc_autotune(ctx, args.tune_cache) if not args.no_autotune else None
+    g2 = rc.rc_step_graph_create(ctx, R.inst_vel, float(scene.dt), depth=out["depth"], seg=out["seg"],
+                                 total_rays=rays)
+    rc.rc_graph_set_step(g2, 0)
+    for _ in range(10):
+        rc.rc_graph_launch(g2)
+    rc.rc_graph_set_step(g2, 0)
+    ms2 = timed(lambda: rc.rc_graph_launch(g2), n_steps)
+    rc.rc_graph_destroy(g2)
+    log(f"two-level graph step {ms2:.3f} ms")
     R.close()
     return {"metric": METRIC, "value": rays / ms / 1e3, "unit": "Mrays/s", "n_gpus": 1, "steps": n_steps,
             "warmup": 10, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -411,7 +429,10 @@ def bench_graph(args):
                        "tuning": tuning, "step": "move + transform + refit + queue reset + batched render (graph)"},
             "env_steps_per_s": scene.n_envs / (ms * 1e-3),
             "plain": {"ms_per_step": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_graph_vs_plain":
-                      ms_plain / ms}}
+                      ms_plain / ms},
+            "two_level": {"ms_per_step": ms2, "Mrays_s": rays / ms2 / 1e3, "tuning": tuning2,
+                          "step_vs_single_level": ms / ms2, "added_library_bytes": added,
+                          "single_level_library_bytes": used0}}
 
 
 # --------------------------------------------------------------------------
@@ -550,6 +571,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="cfg3 run: skip the cfg2 and cfg4 legs")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reused choices skip the timing)")
     ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
     ap.add_argument("--quick", action="store_true",
@@ -571,6 +593,22 @@ def main():
         if not args.no_serve and args.cfg == 3:
             log("served (cfg5)")
             result["served"] = bench_serve(args)
+        if not args.no_other and args.cfg == 3:
+            # the camera room and the uneven moving batch, same run: refit step in the three forms (cfg2)
+            # and the captured 100-step graph (cfg4)
+            import copy
+            a2 = copy.copy(args)
+            a2.cfg = 2
+            log("cfg2")
+            r2 = bench_step(a2)
+            log("cfg4")
+            r4 = bench_graph(args)
+            result["other_workloads"] = {
+                "cfg2": {k: r2[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "render_ms",
+                                            "render_Mrays_s", "transform_refit_ms", "flat", "two_level", "plain",
+                                            "traversal", "further_outputs")},
+                "cfg4": {k: r4[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "plain",
+                                            "two_level")}}
     if not args.no_cpu and args.cfg in (1, 2, 3, 4):
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(args.cfg, args.cpu_seconds)

@@ -824,29 +824,38 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
         int32_t *tp = o.tri_tab[tl.s];
         float *hp = o.hit_tab[tl.s];
         if (dp)
-            dp[r_local] = depth;
+            __builtin_nontemporal_store(depth, dp + r_local);
         if (sp)
-            sp[r_local] = seg;
+            __builtin_nontemporal_store(seg, sp + r_local);
         if (tp)
-            tp[r_local] = tri;
+            __builtin_nontemporal_store(tri, tp + r_local);
         if (hp) {
-            hp[3 * r_local + 0] = hx;
-            hp[3 * r_local + 1] = hy;
-            hp[3 * r_local + 2] = hz;
+            __builtin_nontemporal_store(hx, hp + 3 * r_local + 0);
+            __builtin_nontemporal_store(hy, hp + 3 * r_local + 1);
+            __builtin_nontemporal_store(hz, hp + 3 * r_local + 2);
         }
         return;
     }
-    const int64_t idx = tl.ray_base + r_local;
+    // the sensor instance's first ray, loaded here: kept from load_tile it
+    // would occupy two vector registers across the traversal (spilled)
+    int s2 = tl.s;
+    asm volatile("" : "+s"(s2));
+    const int64_t idx = se.ray_off[s2] + r_local;
+    // Streaming stores (here and for served requests above): a tile row fills
+    // only part of a 128-byte line, and the neighbouring tile that completes
+    // the line is rendered tens of microseconds later, by when L2 has often
+    // written the half-dirty line back; output lines are never read here, so
+    // they bypass the cache.
     if (o.depth)
-        o.depth[idx] = depth;
+        __builtin_nontemporal_store(depth, o.depth + idx);
     if (o.seg)
-        o.seg[idx] = seg;
+        __builtin_nontemporal_store(seg, o.seg + idx);
     if (o.tri)
-        o.tri[idx] = tri;
+        __builtin_nontemporal_store(tri, o.tri + idx);
     if (o.hit) {
-        o.hit[3 * idx + 0] = hx;
-        o.hit[3 * idx + 1] = hy;
-        o.hit[3 * idx + 2] = hz;
+        __builtin_nontemporal_store(hx, o.hit + 3 * idx + 0);
+        __builtin_nontemporal_store(hy, o.hit + 3 * idx + 1);
+        __builtin_nontemporal_store(hz, o.hit + 3 * idx + 2);
     }
 }
 
