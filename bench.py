@@ -203,6 +203,18 @@ def bench_step(args):
     ms = timed(step, args.steps)
     ms_render = timed(render, args.steps)
     ms_refit = timed(lambda: rc.rc_refit(ctx), args.steps)
+    widths = None
+    if tuning is not None:
+        # the same launch shape with the other node width (binary nodes / four-wide records)
+        alt = list(tuning)
+        alt[3] = 6 - alt[3]
+        rc.rc_tuning_set(ctx, *alt)
+        ms_alt_render = timed(render, args.steps)
+        ms_alt_step = timed(step, args.steps)
+        rc.rc_tuning_set(ctx, *tuning)
+        widths = {"chosen": tuning[3], "other": alt[3], "other_render_ms": ms_alt_render,
+                  "other_step_ms": ms_alt_step, "render_speedup_chosen_vs_other": ms_alt_render / ms_render}
+        log(f"node width {alt[3]}: render {ms_alt_render:.3f} ms, step {ms_alt_step:.3f} ms")
     # --quick (profiling runs): only the step and the render above
     ms_build = ms_rebuild_step = ms_build_lbvh = ms_render_lbvh = ms_rebuild_step_lbvh = float("nan")
     further = flat = None
@@ -323,6 +335,7 @@ def bench_step(args):
         "further_outputs": further,
         "traversal": {"box_tests_per_ray": stats[0] / rays, "tri_tests_per_ray": stats[1] / rays,
                       "fp64_evals_per_ray": stats[2] / rays},
+        "node_width": widths,
         "roofline": roofline(kernel, args.cfg, rays, ms_render, b_ray),
         "cpu_baseline": None,
     }
@@ -606,7 +619,7 @@ def main():
             result["other_workloads"] = {
                 "cfg2": {k: r2[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "render_ms",
                                             "render_Mrays_s", "transform_refit_ms", "flat", "two_level", "plain",
-                                            "traversal", "further_outputs")},
+                                            "traversal", "node_width", "further_outputs")},
                 "cfg4": {k: r4[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "plain",
                                             "two_level")}}
     if not args.no_cpu and args.cfg in (1, 2, 3, 4):

@@ -302,16 +302,23 @@ rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
 /* ------------------------------------------------------------------------ */
 /* Choose the ray-tile shape (columns x rows of one 64-lane wavefront: 4x16, */
 /* 8x8, 16x4 or 32x2), the tiles taken per work-queue pop (2, 4 or 16), the */
-/* queue order (largest estimated cost first, or natural) of the batched    */
-/* render by timing each combination on the loaded                          */
-/* scene, sensors and poses (temporary outputs are allocated within the     */
+/* queue order (largest estimated cost first, or natural) and the node     */
+/* width (2 or 4; single-level scenes) of the batched render by timing each */
+/* combination on the loaded scene, sensors and poses (temporary outputs   */
+/* and, for width 4, the four-wide records are allocated within the         */
 /* budget).  cache_path (nullable): a text file of previous choices keyed   */
 /* by device and workload; a hit skips the timing, a miss appends a line.    */
-/* choice (nullable): host int32[3] = tile columns, tiles per pop, 1 if     */
-/* cost order.  Outputs are bit-identical for every choice.  Synchronous.   */
+/* choice (nullable): host int32[4] = tile columns, tiles per pop, 1 if     */
+/* cost order, node width.  Outputs are bit-identical for every choice.     */
+/* Synchronous.                                                              */
 rc_status rc_autotune(rc_context *ctx, const char *cache_path, int32_t *choice);
-/* Set those choices directly: choice host int32[3] = tile columns (4, 8,   */
-/* 16 or 32), tiles per pop (1..64), cost order (0 or 1).                   */
+/* Set those choices directly: choice host int32[4] = tile columns (4, 8,   */
+/* 16 or 32), tiles per pop (1..64), cost order (0 or 1), node width (2 or  */
+/* 4).  Node width 4 traverses four-wide records of the same BVH (for each  */
+/* internal node, the boxes one level below its children, 128 bytes, kept   */
+/* beside the binary nodes and refreshed by every single-level build and    */
+/* refit; allocated on first use, 128 bytes per node slot, RC_E_OOM beyond  */
+/* the budget): half the dependent node fetches per ray.                    */
 rc_status rc_tuning_set(rc_context *ctx, const int32_t *choice);
 
 typedef struct rc_graph rc_graph;

@@ -124,6 +124,7 @@ BuildView Scene::view() const
     v.level_nodes = level_nodes.as<int32_t>();
     v.level_off = level_off.as<int32_t>();
     v.env_mask = nullptr;
+    v.wide = wide_on ? wide.as<WideRec>() : nullptr;
     return v;
 }
 
@@ -142,6 +143,7 @@ SceneView Scene::sview() const
     s.tri_src = tri_src.as<int2>();
     s.proto_tri = proto_tri.as<int32_t>();
     s.n_envs = n_envs;
+    s.wide = wide_on ? wide.as<WideRec>() : nullptr;
     if (two_level) {
         InstView &v = s.inst;
         v.tnodes = top->nodes.as<Node>();
@@ -251,6 +253,26 @@ void models_for(const rc_context *c, std::vector<SensorModel> &models, std::vect
 }  // namespace
 
 namespace rc {
+
+// Traversal on four-wide records (tuning node width 4): the records are
+// allocated on first use and filled from the binary tree whenever it is
+// current (the next single-level build or refit fills them otherwise).
+rc_status set_node_width(rc_context *c, int width)
+{
+    if (!c->scene)
+        return RC_OK;
+    Scene &sc = *c->scene;
+    if (width != 4) {
+        sc.wide_on = false;
+        return RC_OK;
+    }
+    if (!sc.wide.p)
+        RC_TRY(c->pool.alloc(sc.wide, sizeof(WideRec) * (size_t)(node_base(sc.n_tris, sc.n_envs) + 16)));
+    sc.wide_on = true;
+    if (sc.built && !sc.two_level)
+        RC_HIP(launch_wide_fill(sc.view(), c->stream));
+    return RC_OK;
+}
 
 rc_status rebuild_items(rc_context *c, Sensors &se)
 {
@@ -711,6 +733,7 @@ static rc_status world_fresh(Scene &sc, hipStream_t st)
     sc.world_stale = sc.stale_all = false;
     return RC_OK;
 }
+
 
 // Per-instance inverse poses and top-level boxes of a two-level scene (with
 // recs: also the top level's leaf records, for its refit).

@@ -73,13 +73,17 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
     bool found = false;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
-            char k[1024];
-            int tw, ch, lpt;
-            while (fscanf(f, "%1023s %d %d %d", k, &tw, &ch, &lpt) == 4) {
-                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && ch >= 1 && ch <= 64) {
+            char line[1200], k[1024];
+            int tw, ch, lpt, width;
+            while (fgets(line, sizeof line, f)) {
+                if (sscanf(line, "%1023s %d %d %d %d", k, &tw, &ch, &lpt, &width) != 5)
+                    continue;  // a line of another format
+                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && ch >= 1 && ch <= 64 &&
+                    (width == 2 || width == 4)) {
                     best.tw_shift = __builtin_ctz(tw);
                     best.chunk = ch;
                     best.lpt = lpt != 0;
+                    best.width = width;
                     found = true;
                 }
             }
@@ -99,11 +103,15 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
         RC_HIP(hipEventCreate(&e1));
         float best_ms = 1e30f;
         const int chunks[3] = {2, 4, 16};
+        // node width 4 (four-wide records) for single-level scenes only
+        for (int width = 2; width <= (sc.two_level ? 2 : 4); width += 2)
         for (int tws = 2; tws <= 5; ++tws)
             for (int ci = 0; ci < 3; ++ci)
                 for (int lpt = 1; lpt >= 0; --lpt) {
-                    c->tuning = Tuning{tws, chunks[ci], lpt != 0};
-                    rc_status s = rebuild_items(c, se);
+                    c->tuning = Tuning{tws, chunks[ci], lpt != 0, width};
+                    rc_status s = set_node_width(c, width);
+                    if (s == RC_OK)
+                        s = rebuild_items(c, se);
                     if (s != RC_OK) {
                         (void)hipEventDestroy(e0);
                         (void)hipEventDestroy(e1);
@@ -129,18 +137,21 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
         (void)hipEventDestroy(e1);
         if (cache_path) {
             if (FILE *f = fopen(cache_path, "a")) {
-                fprintf(f, "%s %d %d %d\n", key.c_str(), 1 << best.tw_shift, best.chunk, best.lpt ? 1 : 0);
+                fprintf(f, "%s %d %d %d %d\n", key.c_str(), 1 << best.tw_shift, best.chunk, best.lpt ? 1 : 0,
+                        best.width);
                 fclose(f);
             }
         }
     }
     c->tuning = best;
+    RC_TRY(set_node_width(c, best.width));
     RC_TRY(rebuild_items(c, se));
     ++c->generation;
     if (choice) {
         choice[0] = 1 << best.tw_shift;
         choice[1] = best.chunk;
         choice[2] = best.lpt ? 1 : 0;
+        choice[3] = best.width;
     }
     return RC_OK;
 }
@@ -154,11 +165,12 @@ rc_status rc_tuning_set(rc_context *c, const int32_t *choice)
     RC_CHECK(tw == 4 || tw == 8 || tw == 16 || tw == 32, "tile columns must be 4, 8, 16 or 32");
     RC_CHECK(choice[1] >= 1 && choice[1] <= 64, "tiles per pop must be in [1, 64]");
     RC_CHECK(choice[2] == 0 || choice[2] == 1, "cost order must be 0 or 1");
-    c->tuning = Tuning{__builtin_ctz(tw), choice[1], choice[2] != 0};
-    if (c->sensors) {
-        RC_TRY(set_device(c));
+    RC_CHECK(choice[3] == 2 || choice[3] == 4, "node width must be 2 or 4");
+    c->tuning = Tuning{__builtin_ctz(tw), choice[1], choice[2] != 0, choice[3]};
+    RC_TRY(set_device(c));
+    RC_TRY(set_node_width(c, c->tuning.width));
+    if (c->sensors)
         RC_TRY(rebuild_items(c, *c->sensors));
-    }
     ++c->generation;
     return RC_OK;
 }

@@ -1652,6 +1652,73 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(BuildView v)
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// K7b: four-wide records (WideRec), one workgroup per environment, one
+// thread per node slot.  Reads the node and its internal children; a slot
+// that is a hole of the node numbering (depth -1) is skipped.
+__global__ __launch_bounds__(kRefitBlock) void k_wide_fill(BuildView v)
+{
+    const int e = blockIdx.x;
+    if (masked_out(v, e))
+        return;
+    const int64_t base = node_base(v.env_tri_off[e], e);
+    const Node *nodes = v.nodes + base;
+    WideRec *wide = v.wide + base;
+    const int nn = v.env_nodes[e];
+    for (int m = threadIdx.x; m < nn; m += kRefitBlock) {
+        const Node nd = nodes[m];
+        if (nd.ch.w < 0)
+            continue;
+        float lx[4], hx[4], ly[4], hy[4], lz[4], hz[4];
+        int ref[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int c = i ? nd.ch.y : nd.ch.x;
+            if (c >= 0) {
+                const Node cn = nodes[c];
+                lx[2 * i] = cn.xy0.x;
+                hx[2 * i] = cn.xy0.y;
+                ly[2 * i] = cn.xy0.z;
+                hy[2 * i] = cn.xy0.w;
+                lz[2 * i] = cn.z01.x;
+                hz[2 * i] = cn.z01.y;
+                lx[2 * i + 1] = cn.xy1.x;
+                hx[2 * i + 1] = cn.xy1.y;
+                ly[2 * i + 1] = cn.xy1.z;
+                hy[2 * i + 1] = cn.xy1.w;
+                lz[2 * i + 1] = cn.z01.z;
+                hz[2 * i + 1] = cn.z01.w;
+                ref[2 * i] = cn.ch.x;
+                ref[2 * i + 1] = cn.ch.y;
+            } else {
+                const float4 xy = i ? nd.xy1 : nd.xy0;
+                lx[2 * i] = xy.x;
+                hx[2 * i] = xy.y;
+                ly[2 * i] = xy.z;
+                hy[2 * i] = xy.w;
+                lz[2 * i] = i ? nd.z01.z : nd.z01.x;
+                hz[2 * i] = i ? nd.z01.w : nd.z01.y;
+                ref[2 * i] = c;
+                // empty slot: a point at +infinity, which both slab tests reject
+                lx[2 * i + 1] = ly[2 * i + 1] = lz[2 * i + 1] = INFINITY;
+                hx[2 * i + 1] = hy[2 * i + 1] = hz[2 * i + 1] = INFINITY;
+                ref[2 * i + 1] = kDoneRef;
+            }
+        }
+        WideRec w;
+        w.lox = make_float4(lx[0], lx[1], lx[2], lx[3]);
+        w.hix = make_float4(hx[0], hx[1], hx[2], hx[3]);
+        w.loy = make_float4(ly[0], ly[1], ly[2], ly[3]);
+        w.hiy = make_float4(hy[0], hy[1], hy[2], hy[3]);
+        w.loz = make_float4(lz[0], lz[1], lz[2], lz[3]);
+        w.hiz = make_float4(hz[0], hz[1], hz[2], hz[3]);
+        w.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
+        w.pair = make_int4(nd.ch.x, nd.ch.y, 0, 0);
+        wide[m] = w;
+    }
+}
+
+
+
 // ---------------------------------------------------------------------------
 // K6: linear BVH (builder RC_BUILD_LBVH), one workgroup per environment of
 // kLeafMax + 1 .. kLbvhMax triangles.  Centroids are quantised to 10 bits per
@@ -1945,7 +2012,9 @@ hipError_t launch_build_sah(const BuildView &v, hipStream_t st)
     if ((err = hipGetLastError()) != hipSuccess)
         return err;
     hipLaunchKernelGGL(k_level_order, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
-    return hipGetLastError();
+    if ((err = hipGetLastError()) != hipSuccess)
+        return err;
+    return launch_wide_fill(v, st);
 }
 
 hipError_t launch_build_lbvh(const BuildView &v, uint8_t *sah_mask, hipStream_t st)
@@ -1980,8 +2049,7 @@ hipError_t launch_build_lbvh(const BuildView &v, uint8_t *sah_mask, hipStream_t 
     hipLaunchKernelGGL(k_level_order, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
     if ((err = hipGetLastError()) != hipSuccess)
         return err;
-    hipLaunchKernelGGL(k_refit, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
-    return hipGetLastError();
+    return launch_refit(v, st);
 }
 
 hipError_t launch_refit(const BuildView &v, hipStream_t st)
@@ -1989,6 +2057,17 @@ hipError_t launch_refit(const BuildView &v, hipStream_t st)
     if (v.n_envs == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_refit, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || !v.wide)
+        return err;
+    return launch_wide_fill(v, st);
+}
+
+hipError_t launch_wide_fill(const BuildView &v, hipStream_t st)
+{
+    if (v.n_envs == 0 || !v.wide)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_wide_fill, dim3(v.n_envs), dim3(kRefitBlock), 0, st, v);
     return hipGetLastError();
 }
 

@@ -43,6 +43,24 @@ struct alignas(16) Node {
 };
 static_assert(sizeof(Node) == 64, "node is one 64-byte fetch");
 
+// Four-wide view of the same tree: for internal node m, the boxes one level
+// further down, stored beside the node array (same index).  Slots 0 and 1
+// come from child 0 of m, slots 2 and 3 from child 1: an internal child
+// contributes its two children (refs and boxes as stored in the child), a
+// leaf child occupies its first slot with its own box (as stored in m) and
+// leaves the second one empty (ref kDoneRef, the box [+inf, +inf] on every
+// axis, which no slab test accepts).  pair.x / pair.y
+// are m's two children themselves.  Box components are stored slot-major
+// (lox = the low x of slots 0..3), so that one 16-byte load gives one plane
+// of all four boxes.  Rebuilt by k_wide_fill after every build and refit.
+constexpr int kDoneRef = INT32_MIN;  // "nothing": an empty slot, the end of a traversal
+struct alignas(16) WideRec {
+    float4 lox, hix, loy, hiy, loz, hiz;
+    int4 ref;
+    int4 pair;  // child 0, child 1 of m, 0, 0
+};
+static_assert(sizeof(WideRec) == 128, "wide record is two 64-byte lines");
+
 // Leaf-ordered triangle record: 3 vertices + environment-local triangle id.
 struct alignas(16) TriRec {
     float4 a;  // v0.x v0.y v0.z v1.x
@@ -114,6 +132,7 @@ struct SceneView {
     const int32_t *proto_tri;    // prototype triangles (global vertex ids)
     int32_t n_envs;
     InstView inst;               // set for a two-level scene
+    const WideRec *wide = nullptr;  // set: four-wide traversal (same index as nodes)
 };
 
 struct SensorView {
@@ -173,6 +192,7 @@ struct BuildView {
     int32_t *level_off;          // [E][kLevels + 1] depth d of env e = level_nodes[off[d] .. off[d+1])
     const uint8_t *env_mask;     // [E] environments to process (nullptr: all)
     int32_t max_depth = kMaxNodeDepth;  // internal-node depth bound of the trees built (<= kMaxNodeDepth)
+    WideRec *wide = nullptr;            // four-wide records, refreshed by launch_wide_fill
 };
 
 // True when environment e is excluded by the build/refit mask.
@@ -218,6 +238,9 @@ hipError_t launch_bump(int32_t *d_step, hipStream_t st);
 hipError_t launch_build_sah(const BuildView &v, hipStream_t st);
 hipError_t launch_build_lbvh(const BuildView &v, uint8_t *sah_mask, hipStream_t st);
 hipError_t launch_refit(const BuildView &v, hipStream_t st);
+// The four-wide records of every internal node of the environments the view
+// admits (v.wide must be set).
+hipError_t launch_wide_fill(const BuildView &v, hipStream_t st);
 
 hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const OutView &o, int64_t item_begin,
                               int64_t n_items, hipStream_t st);

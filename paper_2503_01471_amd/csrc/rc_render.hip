@@ -434,7 +434,79 @@ __device__ __forceinline__ void descend(const Ray &r, Rsrc nodes, int *stk, floa
     }
 }
 
-template <bool STATS>
+__device__ __forceinline__ float comp(const float4 &v, int k)
+{
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+
+// Phase 1 on the four-wide records (WideRec): one visit of internal node m
+// tests the up to four boxes one level below m's children.  The nearer
+// pair's nearer slot is visited next; the farther pair is pushed as one
+// entry (m's child itself when both of its slots are hit, else the one slot
+// hit), then the nearer pair's other slot.  Every path visit leaves on the
+// stack at most as many entries as it descends levels of the binary tree, so
+// the stack bound of the binary traversal (kMaxNodeDepth + 2) still holds.
+// A popped child entry is visited through its own record, which tests the
+// level below the boxes already passed: conservative, and the certified
+// triangle tests make the result independent of the order.
+template <bool STATS, int OCT>
+__device__ __forceinline__ void descend_wide(const Ray &r, Rsrc wide, int *stk, float tcap, int &sp, int &ref,
+                                             int &leaf, Stats &st)
+{
+    while (ref >= 0) {
+        const uint32_t off = (uint32_t)ref * (uint32_t)sizeof(WideRec);
+        const float4 lx = ldf4(wide, off), hx = ldf4(wide, off + 16), ly = ldf4(wide, off + 32);
+        const float4 hy = ldf4(wide, off + 48), lz = ldf4(wide, off + 64), hz = ldf4(wide, off + 80);
+        const int4 rf = ldi4(wide, off + 96);
+        const int4 pr = ldi4(wide, off + 112);
+        __builtin_amdgcn_sched_barrier(0);
+        float t[4];
+        bool h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            h[k] = slab_oct<OCT>(r, comp(lx, k), comp(hx, k), comp(ly, k), comp(hy, k), comp(lz, k), comp(hz, k), tcap,
+                                 t[k]);
+        if (STATS)
+            st.box += (rf.x != kDone) + (rf.y != kDone) + (rf.z != kDone) + (rf.w != kDone);
+        // per pair: its nearer hit slot and whether both are hit
+        const bool a0 = h[0] && (!h[1] || t[0] <= t[1]);
+        const int nA = a0 ? rf.x : rf.y, oA = a0 ? rf.y : rf.x;
+        const float tA = h[0] || h[1] ? (a0 ? t[0] : t[1]) : INFINITY;
+        const bool bothA = h[0] && h[1], anyA = h[0] || h[1];
+        const bool b0 = h[2] && (!h[3] || t[2] <= t[3]);
+        const int nB = b0 ? rf.z : rf.w, oB = b0 ? rf.w : rf.z;
+        const float tB = h[2] || h[3] ? (b0 ? t[2] : t[3]) : INFINITY;
+        const bool bothB = h[2] && h[3], anyB = h[2] || h[3];
+        const bool firstA = anyA && (!anyB || tA <= tB);
+        const bool anyN = firstA ? anyA : anyB, anyF = firstA ? anyB : anyA;
+        const bool bothN = firstA ? bothA : bothB, bothF = firstA ? bothB : bothA;
+        const int near = firstA ? nA : nB, nfar = firstA ? oA : oB;
+        const int fent = bothF ? (firstA ? pr.y : pr.x) : (firstA ? nB : nA);
+        // (the depth argument above keeps sp <= kStack; the guards only make
+        // an overflow impossible by construction)
+        if (anyF && sp < kStack) {
+            stk[sp * kBlock] = fent;
+            ++sp;
+        }
+        if (bothN && sp < kStack) {
+            stk[sp * kBlock] = nfar;
+            ++sp;
+        }
+        if (anyN)
+            ref = near;
+        else
+            ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+        if (ref < 0 && ref != kDone && leaf == kDone) {
+            leaf = ref;
+            ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+        }
+        if (__all(leaf != kDone))
+            break;
+    }
+}
+
+// nodes: the binary node array, or with WIDE the four-wide records.
+template <bool STATS, bool WIDE>
 __device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, const TriRec *__restrict__ recs, int root,
                                          int *stk, Best &b, Stats &st)
 {
@@ -448,15 +520,60 @@ __device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, cons
     }
     while (true) {
         switch (oct) {
-        case 0: descend<STATS, 0>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 1: descend<STATS, 1>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 2: descend<STATS, 2>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 3: descend<STATS, 3>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 4: descend<STATS, 4>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 5: descend<STATS, 5>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 6: descend<STATS, 6>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        case 7: descend<STATS, 7>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
-        default: descend<STATS, kMixed>(r, nodes, stk, b.hi, sp, ref, leaf, st); break;
+        case 0:
+            if constexpr (WIDE)
+                descend_wide<STATS, 0>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 0>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 1:
+            if constexpr (WIDE)
+                descend_wide<STATS, 1>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 1>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 2:
+            if constexpr (WIDE)
+                descend_wide<STATS, 2>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 2>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 3:
+            if constexpr (WIDE)
+                descend_wide<STATS, 3>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 3>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 4:
+            if constexpr (WIDE)
+                descend_wide<STATS, 4>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 4>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 5:
+            if constexpr (WIDE)
+                descend_wide<STATS, 5>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 5>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 6:
+            if constexpr (WIDE)
+                descend_wide<STATS, 6>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 6>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        case 7:
+            if constexpr (WIDE)
+                descend_wide<STATS, 7>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, 7>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
+        default:
+            if constexpr (WIDE)
+                descend_wide<STATS, kMixed>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            else
+                descend<STATS, kMixed>(r, nodes, stk, b.hi, sp, ref, leaf, st);
+            break;
         }
         while (leaf != kDone) {
             const int code = ~leaf;
@@ -860,7 +977,7 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
 }
 
 // One 8x8 tile per wavefront.
-template <bool STATS, bool TWO>
+template <bool STATS, bool TWO, bool WIDE>
 __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorView &se, const OutView &o, int2 item,
                                             int *stk, Stats &st)
 {
@@ -888,13 +1005,14 @@ __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorVie
         }
     } else {
         const int64_t base = sc.env_tri_off[t.env], end = sc.env_tri_off[t.env + 1];
-        const int64_t nb = node_base(base, t.env);
-        const Rsrc nodes = buffer_view(sc.nodes + nb, (node_base(end, t.env + 1) - nb) * (int64_t)sizeof(Node));
+        const int64_t nb = node_base(base, t.env), nn = node_base(end, t.env + 1) - nb;
+        const Rsrc nodes = WIDE ? buffer_view(sc.wide + nb, nn * (int64_t)sizeof(WideRec))
+                                : buffer_view(sc.nodes + nb, nn * (int64_t)sizeof(Node));
         recs = sc.recs + base;
         const Rsrc rv = buffer_view(recs, (end - base) * (int64_t)sizeof(TriRec));
         const int root = sc.env_root[t.env];
         if (root != kEmptyRoot)
-            traverse<STATS>(r, nodes, rv, recs, root, stk, b, st);
+            traverse<STATS, WIDE>(r, nodes, rv, recs, root, stk, b, st);
     }
     // The output position is recomputed here from the lane: the empty asm
     // hides that it equals the one above, so the compiler does not keep
@@ -914,7 +1032,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     return x * q + (x < rem ? x : rem) + (b >> 3);
 }
 
-template <bool TWO>
+template <bool TWO, bool WIDE>
 __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
                                                         int64_t n_items)
 {
@@ -924,10 +1042,10 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_flat(SceneV
     if (k >= n_items)
         return;
     Stats st{0, 0, 0};
-    render_tile<false, TWO>(sc, se, o, se.items[item_begin + k], s_stack + threadIdx.x, st);
+    render_tile<false, TWO, WIDE>(sc, se, o, se.items[item_begin + k], s_stack + threadIdx.x, st);
 }
 
-template <bool TWO>
+template <bool TWO, bool WIDE>
 __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
                                                          unsigned long long *counters)
 {
@@ -937,7 +1055,7 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_stats(Scene
     if (k >= n_items)
         return;
     Stats st{0, 0, 0};
-    render_tile<true, TWO>(sc, se, o, se.items[k], s_stack + threadIdx.x, st);
+    render_tile<true, TWO, WIDE>(sc, se, o, se.items[k], s_stack + threadIdx.x, st);
     unsigned box = st.box, tri = st.tri, f64 = st.fp64;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -954,7 +1072,7 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_stats(Scene
 
 // Persistent form: every wavefront pops `chunk` tiles at a time from its
 // XCD's queue and, once that is empty, from the other queues in turn.
-template <bool TWO>
+template <bool TWO, bool WIDE>
 __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_batched(SceneView sc, SensorView se, OutView o,
                                                                            QueueView q)
 {
@@ -975,7 +1093,7 @@ __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_batched(Sce
         }
         const int64_t stop = b + q.chunk < e ? b + q.chunk : e;
         for (int64_t k = b; k < stop; ++k)
-            render_tile<false, TWO>(sc, se, o, q.items[k], s_stack + threadIdx.x, st);
+            render_tile<false, TWO, WIDE>(sc, se, o, q.items[k], s_stack + threadIdx.x, st);
     }
 }
 
@@ -1300,21 +1418,22 @@ hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const O
 {
     if (n_items == 0)
         return hipSuccess;
+    const dim3 grid(blocks_for(n_items, kBlock / 64));
     if (sc.inst.tnodes)
-        hipLaunchKernelGGL(k_render_flat<true>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
-                           o, item_begin, n_items);
+        hipLaunchKernelGGL((k_render_flat<true, false>), grid, dim3(kBlock), 0, st, sc, se, o, item_begin, n_items);
+    else if (sc.wide)
+        hipLaunchKernelGGL((k_render_flat<false, true>), grid, dim3(kBlock), 0, st, sc, se, o, item_begin, n_items);
     else
-        hipLaunchKernelGGL(k_render_flat<false>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
-                           o, item_begin, n_items);
+        hipLaunchKernelGGL((k_render_flat<false, false>), grid, dim3(kBlock), 0, st, sc, se, o, item_begin, n_items);
     return hipGetLastError();
 }
 
 int batched_blocks_per_cu(bool two_level)
 {
     int per_cu = 0;
-    const hipError_t e = two_level
-                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched<true>, kBlock, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched<false>, kBlock, 0);
+    const hipError_t e =
+        two_level ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched<true, false>, kBlock, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_batched<false, false>, kBlock, 0);
     if (e != hipSuccess || per_cu < 1)
         per_cu = 1;
     return per_cu;
@@ -1329,9 +1448,11 @@ hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, cons
     if (err != hipSuccess)
         return err;
     if (sc.inst.tnodes)
-        hipLaunchKernelGGL(k_render_batched<true>, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
+        hipLaunchKernelGGL((k_render_batched<true, false>), dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
+    else if (sc.wide)
+        hipLaunchKernelGGL((k_render_batched<false, true>), dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
     else
-        hipLaunchKernelGGL(k_render_batched<false>, dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
+        hipLaunchKernelGGL((k_render_batched<false, false>), dim3(grid), dim3(kBlock), 0, st, sc, se, o, q);
     return hipGetLastError();
 }
 
@@ -1370,12 +1491,13 @@ hipError_t launch_render_stats(const SceneView &sc, const SensorView &se, const 
 {
     if (n_items == 0)
         return hipSuccess;
+    const dim3 grid(blocks_for(n_items, kBlock / 64));
     if (sc.inst.tnodes)
-        hipLaunchKernelGGL(k_render_stats<true>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
-                           o, n_items, counters);
+        hipLaunchKernelGGL((k_render_stats<true, false>), grid, dim3(kBlock), 0, st, sc, se, o, n_items, counters);
+    else if (sc.wide)
+        hipLaunchKernelGGL((k_render_stats<false, true>), grid, dim3(kBlock), 0, st, sc, se, o, n_items, counters);
     else
-        hipLaunchKernelGGL(k_render_stats<false>, dim3(blocks_for(n_items, kBlock / 64)), dim3(kBlock), 0, st, sc, se,
-                           o, n_items, counters);
+        hipLaunchKernelGGL((k_render_stats<false, false>), grid, dim3(kBlock), 0, st, sc, se, o, n_items, counters);
     return hipGetLastError();
 }
 

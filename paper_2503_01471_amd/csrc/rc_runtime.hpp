@@ -102,6 +102,8 @@ struct Scene {
     DBuf mesh_box;   // [M][6] float: each mesh's vertex bounds
     int64_t bottom_meshes = 0;  // meshes the bottom level covers
     bool two_level = false;     // the last full build was two-level
+    DBuf wide;                  // four-wide records (WideRec), same index as nodes
+    bool wide_on = false;       // traverse the four-wide records
     BuildView view() const;
     SceneView sview() const;
 };
@@ -143,6 +145,7 @@ struct Tuning {
     int tw_shift = 3;     // ray tile 8 x 8
     int chunk = 4;        // tiles per queue pop
     bool lpt = true;      // queue in decreasing estimated cost
+    int width = 2;        // node width of the single-level traversal (2 or 4)
 };
 
 }  // namespace rc
@@ -174,4 +177,6 @@ rc_status set_device(const rc_context *c);
 const char *last_error();
 // (Re)build the tile work lists of sensors `se` for the current tuning.
 rc_status rebuild_items(rc_context *c, Sensors &se);
+// Traverse the scene's four-wide records (width 4) or its binary nodes.
+rc_status set_node_width(rc_context *c, int width);
 }  // namespace rc

@@ -329,14 +329,14 @@ def rc_debug_bvh(ctx, e: int, n_tris: int) -> dict:
 
 
 def rc_autotune(ctx, cache_path: Optional[str] = None):
-    """Returns (tile columns, tiles per queue pop, cost order flag)."""
-    ch = np.zeros(3, np.int32)
+    """Returns (tile columns, tiles per queue pop, cost order flag, node width)."""
+    ch = np.zeros(4, np.int32)
     _check(lib().rc_autotune(ctx, None if cache_path is None else cache_path.encode(), _ptr(ch)))
     return tuple(int(x) for x in ch)
 
 
-def rc_tuning_set(ctx, tile_cols: int = 8, chunk: int = 4, cost_order: int = 1) -> None:
-    ch = np.array([tile_cols, chunk, cost_order], np.int32)
+def rc_tuning_set(ctx, tile_cols: int = 8, chunk: int = 4, cost_order: int = 1, width: int = 2) -> None:
+    ch = np.array([tile_cols, chunk, cost_order, width], np.int32)
     _check(lib().rc_tuning_set(ctx, _ptr(ch)))
 
 

@@ -35,15 +35,69 @@ def test_every_tuning_is_bit_exact():
     scene = S.make_cfg4(n_envs=8)
     R = _R(scene)
     ref = _host(R.render(mode=rc.RC_RENDER_FLAT))
-    for tw in (4, 8, 16, 32):
-        for gs in (1, 2, 4, 16):
-            for lpt in (0, 1):
-                _say(f"tuning tile {tw} chunk {gs} lpt {lpt}")
-                rc.rc_tuning_set(R.ctx, tw, gs, lpt)
-                for mode in (rc.RC_RENDER_BATCHED, rc.RC_RENDER_FLAT, rc.RC_RENDER_PLAIN):
-                    got = _host(R.render(mode=mode))
-                    for k in ("depth", "seg", "tri"):
-                        assert np.array_equal(got[k], ref[k]), (tw, gs, lpt, mode, k)
+    for width in (2, 4):
+        for tw in (4, 8, 16, 32):
+            for gs in (1, 2, 4, 16):
+                for lpt in (0, 1):
+                    _say(f"tuning tile {tw} chunk {gs} lpt {lpt} width {width}")
+                    rc.rc_tuning_set(R.ctx, tw, gs, lpt, width)
+                    for mode in (rc.RC_RENDER_BATCHED, rc.RC_RENDER_FLAT, rc.RC_RENDER_PLAIN):
+                        got = _host(R.render(mode=mode))
+                        for k in ("depth", "seg", "tri"):
+                            assert np.array_equal(got[k], ref[k]), (tw, gs, lpt, width, mode, k)
+    R.close()
+
+
+def test_wide_nodes_equal_binary():
+    """The four-wide records give the binary traversal's outputs bit for bit
+    (and the oracle's under the contract) after builds with either builder,
+    refits of moving boxes, masked refits and in a captured step graph; the
+    traversal statistics count both."""
+    _need_gpu()
+    for scene in (S.make_cfg3(n_envs=6), S.make_cfg2(n_envs=4, W=240, H=135)):
+        _say(f"wide {scene.name}")
+        R = _R(scene)
+        ref = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+        s2 = rc.rc_render_stats(R.ctx)
+        rc.rc_tuning_set(R.ctx, 16, 4, 1, 4)
+        got = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+        s4 = rc.rc_render_stats(R.ctx)
+        for k in ("depth", "seg", "tri", "hit_xyz"):
+            assert np.array_equal(got[k], ref[k], equal_nan=True), k
+        assert s4[1] > 0 and s4[0] > 0, s4  # box and triangle tests counted
+        print(f"box/tri tests per ray: binary {s2[0] / s2[3]:.2f} / {s2[1] / s2[3]:.2f}, "
+              f"wide {s4[0] / s4[3]:.2f} / {s4[1] / s4[3]:.2f}", flush=True)
+        parity.assert_contract(parity.compare(got, O.render(scene)))
+        rc.rc_build(R.ctx, rc.RC_BUILD_LBVH)
+        got = _host(R.render(mode=rc.RC_RENDER_FLAT))
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(got[k], ref[k]), ("lbvh", k)
+        R.close()
+    scene = S.make_cfg4(n_envs=8)
+    R = _R(scene)
+    rc.rc_tuning_set(R.ctx, 8, 4, 1, 4)
+    for step in (3, 40):
+        _say(f"wide cfg4 step {step}")
+        R.move(step)
+        R.refit(envs=[1, 2, 5] if step == 40 else None)
+        got = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+        rc.rc_tuning_set(R.ctx, 8, 4, 1, 2)
+        ref = _host(R.render(mode=rc.RC_RENDER_BATCHED))
+        rc.rc_tuning_set(R.ctx, 8, 4, 1, 4)
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(got[k], ref[k]), (step, k)
+    n = R.total_rays
+    gout = dict(depth=torch.empty(n, device="cuda"), seg=torch.empty(n, dtype=torch.int32, device="cuda"),
+                tri=torch.empty(n, dtype=torch.int32, device="cuda"))
+    g = rc.rc_step_graph_create(R.ctx, R.inst_vel, float(scene.dt), depth=gout["depth"], seg=gout["seg"],
+                                tri=gout["tri"], total_rays=n)
+    rc.rc_graph_set_step(g, 60)
+    rc.rc_graph_launch(g)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in gout.items()}
+    rc.rc_graph_destroy(g)
+    rep = parity.compare(got, O.render(scene, O.world(scene, O.moved_poses(scene, 60))))
+    parity.assert_contract(rep)
     R.close()
 
 
@@ -55,7 +109,7 @@ def test_autotune_and_cache(tmp_path):
     cache = str(tmp_path / "tune.txt")
     _say("autotune")
     ch = rc.rc_autotune(R.ctx, cache)
-    assert ch[0] in (4, 8, 16, 32) and ch[1] in (2, 4, 16) and ch[2] in (0, 1)
+    assert ch[0] in (4, 8, 16, 32) and ch[1] in (2, 4, 16) and ch[2] in (0, 1) and ch[3] in (2, 4)
     got = _host(R.render(mode=rc.RC_RENDER_BATCHED))
     for k in ("depth", "seg", "tri"):
         assert np.array_equal(got[k], ref[k])
