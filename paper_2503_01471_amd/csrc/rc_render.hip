@@ -1242,7 +1242,7 @@ __device__ __forceinline__ void write_extras(const OutView &o, const SceneView &
 // kernels so that they carry none of its registers.
 __global__ __launch_bounds__(kBlock) void k_hit_extras(SceneView sc, SensorView se, OutView o, int64_t n_items)
 {
-    const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    const int64_t k = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + uniform(threadIdx.x >> 6);
     if (k >= n_items)
         return;
     const int2 item = se.items[k];
@@ -1281,48 +1281,58 @@ __global__ __launch_bounds__(kBlock) void k_hit_extras(SceneView sc, SensorView 
 // ---------------------------------------------------------------------------
 constexpr float kShadowS0 = 0x1p-13f;  // lower end of the segment parameter
 
-__device__ __forceinline__ bool any_hit(const Ray &r, const Node *__restrict__ nodes, const TriRec *__restrict__ recs,
-                                        int root, int *stk)
+// Any-hit traversal in the two phases of the nearest-hit search (internal
+// nodes until every active lane holds a leaf, then the leaves), with the
+// node loop specialised on the wavefront's direction octant; a lane that
+// finds an occluder stops.  The answer does not depend on the order.
+__device__ __forceinline__ bool any_hit(const Ray &r, Rsrc nodes, Rsrc rv, int root, int *stk)
 {
+    const int oct = wave_octant(r);
+    Stats st{0, 0, 0};
     int sp = 0;
     int ref = root;
+    int leaf = kDone;
+    if (root < 0) {
+        leaf = root;
+        ref = kDone;
+    }
+    bool hit = false;
     while (true) {
-        if (ref >= 0) {
-            const Node *n = nodes + ref;
-            const float4 a = n->xy0, c = n->xy1, z = n->z01;
-            const int4 ch = n->ch;
-            float t0, t1;
-            const bool h0 = slab(r, a.x, a.y, a.z, a.w, z.x, z.y, r.tf, t0);
-            const bool h1 = slab(r, c.x, c.y, c.z, c.w, z.z, z.w, r.tf, t1);
-            if (h0 && h1) {
-                stk[sp * kBlock] = ch.y;
-                ++sp;
-                ref = ch.x;
-                continue;
-            }
-            if (h0 || h1) {
-                ref = h0 ? ch.x : ch.y;
-                continue;
-            }
-        } else {
-            const int code = ~ref;
+        switch (oct) {
+        case 0: descend<false, 0>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 1: descend<false, 1>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 2: descend<false, 2>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 3: descend<false, 3>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 4: descend<false, 4>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 5: descend<false, 5>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 6: descend<false, 6>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        case 7: descend<false, 7>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        default: descend<false, kMixed>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
+        }
+        while (leaf != kDone) {
+            const int code = ~leaf;
             const int first = code >> 3, cnt = (code & 7) + 1;
-            for (int k = 0; k < cnt; ++k) {
-                const TriRec T = recs[first + k];
+            for (int k = 0; k < cnt && !hit; ++k) {
+                const uint32_t off = (uint32_t)(first + k) * (uint32_t)sizeof(TriRec);
+                const float4 ta = ldf4(rv, off), tb = ldf4(rv, off + 16), tc = ldf4(rv, off + 32);
                 float tt, et;
-                const int d = mt32(r, T.a, T.b, T.c, r.tf, tt, et);
-                if (d == kAccept)
-                    return true;
+                const int d = mt32(r, ta, tb, tc, r.tf, tt, et);
                 double t64;
-                if (d == kUnsure && mt64(r, T.a, T.b, T.c, t64))
-                    return true;
+                hit = d == kAccept || (d == kUnsure && mt64(r, ta, tb, tc, t64));
+            }
+            if (hit) {
+                leaf = ref = kDone;
+            } else if (ref < 0 && ref != kDone) {
+                leaf = ref;
+                ref = sp > 0 ? stk[--sp * kBlock] : kDone;
+            } else {
+                leaf = kDone;
             }
         }
-        if (sp == 0)
-            return false;
-        --sp;
-        ref = stk[sp * kBlock];
+        if (ref == kDone)
+            break;
     }
+    return hit;
 }
 
 // One wavefront per 64-ray tile: the hit point p = o + t d (FP64 t of the
@@ -1332,7 +1342,8 @@ __device__ __forceinline__ bool any_hit(const Ray &r, const Node *__restrict__ n
 __global__ __launch_bounds__(kBlock) void k_stereo_shadow(SceneView sc, SensorView se, OutView o, int64_t n_items)
 {
     __shared__ int s_stack[kStack * kBlock];
-    const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + uniform(threadIdx.x >> 6);
+    // each XCD walks a contiguous range of tiles (environments stay in one L2)
+    const int64_t k = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + uniform(threadIdx.x >> 6);
     if (k >= n_items)
         return;
     const int2 item = se.items[k];
@@ -1378,7 +1389,12 @@ __global__ __launch_bounds__(kBlock) void k_stereo_shadow(SceneView sc, SensorVi
         s.knd = kErr * fmaxf(fmaxf(fabsf(s.dx), fabsf(s.dy)), fabsf(s.dz));
         s.tn = kShadowS0;
         s.tf = 1.0f;
-        hidden = any_hit(s, sc.nodes + node_base(base, t.env), sc.recs + base, root, s_stack + threadIdx.x) ? 1 : 0;
+        slab_consts(s);
+        const int64_t end = sc.env_tri_off[t.env + 1];
+        const int64_t nb = node_base(base, t.env);
+        const Rsrc nodes = buffer_view(sc.nodes + nb, (node_base(end, t.env + 1) - nb) * (int64_t)sizeof(Node));
+        const Rsrc rv = buffer_view(sc.recs + base, (end - base) * (int64_t)sizeof(TriRec));
+        hidden = any_hit(s, nodes, rv, root, s_stack + threadIdx.x) ? 1 : 0;
     }
     o.shadow[idx] = hidden;
 }
