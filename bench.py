@@ -281,7 +281,7 @@ def bench_step(args):
         log(f"flat step {ms_flat:.3f} ms, flat render {ms_flat_render:.3f} ms")
         two_level = bench_two_level(args, R, render, step, mode, ms, ms_render)
     else:
-        two_level = None
+        two_level = bench_two_level(args, R, render, step, mode, ms, ms_render) if args.two_level else None
     plain = None
     if not args.no_plain and not args.quick:
         def plain_step():
@@ -585,6 +585,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="cfg3 run: skip the cfg2 and cfg4 legs")
+    ap.add_argument("--two-level", action="store_true", help="with --quick: time the two-level form as well")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reused choices skip the timing)")
     ap.add_argument("--calib", action="store_true", help="also run a 256 MiB copy kernel (counter calibration)")
     ap.add_argument("--quick", action="store_true",

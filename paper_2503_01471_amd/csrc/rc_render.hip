@@ -901,8 +901,15 @@ __device__ __forceinline__ void traverse_two(const Ray &r, const InstView &iv, i
         const int first = code >> 3, cnt = (code & 7) + 1;
         ref = sp > 0 ? stk[--sp * kBlock] : kDone;
         for (int k = 0; k < cnt; ++k) {
-            const int li = __float_as_int(ldf4(trecs, (uint32_t)(first + k) * (uint32_t)sizeof(TriRec) + 32).y);
-            walk_instance<STATS>(r, iv, tv, (int)ib + li, stk, sp, b, st);
+            // the instance's own world box (the record's triangle (lo, hi, lo)):
+            // the object-space setup and walk only for an instance the ray meets
+            const uint32_t roff = (uint32_t)(first + k) * (uint32_t)sizeof(TriRec);
+            const float4 ra = ldf4(trecs, roff), rb = ldf4(trecs, roff + 16), rc = ldf4(trecs, roff + 32);
+            float te;
+            if (STATS)
+                ++st.box;
+            if (slab(r, ra.x, ra.w, ra.y, rb.x, ra.z, rb.y, b.hi, te))
+                walk_instance<STATS>(r, iv, tv, (int)ib + __float_as_int(rc.y), stk, sp, b, st);
         }
     }
 }
