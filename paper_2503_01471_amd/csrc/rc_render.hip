@@ -154,6 +154,44 @@ __device__ __forceinline__ Tile load_tile(const SensorView &se, int2 item)
 }
 
 // ---------------------------------------------------------------------------
+// Maximum and minimum of quiet operands.  fmaxf / fminf must quiet a
+// signalling NaN, so the compiler re-quiets every operand it cannot prove to
+// be an arithmetic result, and a loop-invariant limit (the ray's near limit,
+// the current hit bound) costs one extra instruction per node visit.  Every
+// operand here is an arithmetic result or a finite limit checked on the host,
+// so the plain instructions give the same result: a NaN operand is ignored,
+// as by fmaxf / fminf.  The operand `u` of the _u forms is read from a scalar
+// register and must be wave-uniform.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float qmax3(float a, float b, float c)
+{
+    float d;
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+__device__ __forceinline__ float qmin3(float a, float b, float c)
+{
+    float d;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+__device__ __forceinline__ float qmax_u(float a, float u)
+{
+    float d;
+    asm("v_max_f32 %0, %1, %2" : "=v"(d) : "s"(u), "v"(a));
+    return d;
+}
+
+__device__ __forceinline__ float qmin(float a, float b)
+{
+    float d;
+    asm("v_min_f32 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+
+// ---------------------------------------------------------------------------
 // Robust slab test (boxes are stored expanded outward by one float step).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool slab(const Ray &r, float lx, float hx, float ly, float hy, float lz, float hz,
@@ -162,8 +200,8 @@ __device__ __forceinline__ bool slab(const Ray &r, float lx, float hx, float ly,
     const float t0x = (lx - r.ox) * r.ix, t1x = (hx - r.ox) * r.ix;
     const float t0y = (ly - r.oy) * r.iy, t1y = (hy - r.oy) * r.iy;
     const float t0z = (lz - r.oz) * r.iz, t1z = (hz - r.oz) * r.iz;
-    const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), r.tn));
-    const float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tcap));
+    const float tmin = qmax_u(qmax3(fminf(t0x, t1x), fminf(t0y, t1y), fminf(t0z, t1z)), r.tn);
+    const float tmax = qmin(qmin3(fmaxf(t0x, t1x), fmaxf(t0y, t1y), fmaxf(t0z, t1z)), tcap);
     tenter = tmin;
     return tmin <= tmax * kBoxGrow;
 }
@@ -191,10 +229,8 @@ __device__ __forceinline__ bool slab_oct(const Ray &r, float lx, float hx, float
         const float nx = (OCT & 1) ? hx : lx, fx = (OCT & 1) ? lx : hx;
         const float ny = (OCT & 2) ? hy : ly, fy = (OCT & 2) ? ly : hy;
         const float nz = (OCT & 4) ? hz : lz, fz = (OCT & 4) ? lz : hz;
-        const float tmin = fmaxf(fmaxf(fmaf(nx, r.ix, r.cnx), fmaf(ny, r.iy, r.cny)),
-                                 fmaxf(fmaf(nz, r.iz, r.cnz), r.tn));
-        const float tmax = fminf(fminf(fmaf(fx, r.ix, r.cfx), fmaf(fy, r.iy, r.cfy)),
-                                 fminf(fmaf(fz, r.iz, r.cfz), tcap));
+        const float tmin = qmax3(fmaf(nx, r.ix, r.cnx), fmaf(ny, r.iy, r.cny), qmax_u(fmaf(nz, r.iz, r.cnz), r.tn));
+        const float tmax = qmin3(fmaf(fx, r.ix, r.cfx), fmaf(fy, r.iy, r.cfy), qmin(fmaf(fz, r.iz, r.cfz), tcap));
         tenter = tmin;
         return tmin <= tmax * kBoxGrow;
     }
