@@ -286,7 +286,7 @@ rc_status rebuild_items(rc_context *c, Sensors &se)
     for (int64_t s = 0; s < S; ++s)
         se.item_off[s + 1] = se.item_off[s] + models[se.si_model[s]].tiles;
     se.n_items = se.item_off[S];
-    RC_CHECK(se.n_items < INT32_MAX, "too many tiles");
+    RC_CHECK(se.n_items < kPairFlag, "too many tiles");  // tile indices leave kPairFlag free
     std::vector<int2> items(se.n_items);
     for (int64_t s = 0; s < S; ++s)
         for (int64_t k = se.item_off[s]; k < se.item_off[s + 1]; ++k)
@@ -310,6 +310,17 @@ rc_status rebuild_items(rc_context *c, Sensors &se)
         tiles[s] = se.item_off[s + 1] - se.item_off[s];
     std::vector<int2> lpt;
     deal_queues(order, tiles, lpt, se.qoff);
+    // output pairs (kPairFlag): a 16-column tile and its right-hand
+    // neighbour at an even offset from the queue's start, so that a pop of
+    // an even number of tiles always holds both
+    if ((1 << c->tuning.tw_shift) == kPairCols && c->tuning.chunk % 2 == 0)
+        for (int q = 0; q < kQueues; ++q)
+            for (int64_t j = se.qoff[q]; j + 1 < se.qoff[q + 1]; j += 2) {
+                const int2 a = lpt[j], b = lpt[j + 1];
+                const int tiles_x = models[se.si_model[a.x]].tiles_x, tx = a.y % tiles_x;
+                if (b.x == a.x && b.y == a.y + 1 && tx % 2 == 0 && tx + 1 < tiles_x)
+                    lpt[j].y |= kPairFlag;
+            }
     RC_HIP(hipStreamSynchronize(st));  // previous users of the old lists are done
     RC_TRY(upload(c, se.models, models.data(), models.size(), st));
     RC_TRY(upload(c, se.tables, tables.data(), tables.size(), st));

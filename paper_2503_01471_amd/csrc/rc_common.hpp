@@ -250,8 +250,16 @@ hipError_t launch_render_flat(const SceneView &sc, const SensorView &se, const O
 // next queue when its own is empty.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 64;
+// Output pairs: with 16-column tiles and an even pop size, the queue marks a
+// tile whose right-hand neighbour (same sensor instance, same tile row)
+// follows it at an even offset from the queue's start, so that both are
+// always popped together: kPairFlag set in the first tile's index.  The
+// render then writes the two tiles' depth and segmentation rows together,
+// as whole 128-byte lines.
+constexpr int kPairCols = 16;
+constexpr int kPairFlag = 1 << 30;
 struct QueueView {
-    const int2 *items;          // kQueues consecutive ranges of (sensor instance, tile)
+    const int2 *items;          // kQueues consecutive ranges of (sensor instance, tile [| kPairFlag])
     int64_t off[kQueues + 1];   // range q = [off[q], off[q+1])
     unsigned int *head;         // kQueues * kQueueStride counters
     int chunk;                  // tiles per pop

@@ -48,6 +48,43 @@ def test_every_tuning_is_bit_exact():
     R.close()
 
 
+def test_output_pairs_ragged_widths():
+    """16-column tiles popped in pairs write their depth and segmentation
+    together (the left tile's values wait in LDS): widths that are not a
+    multiple of 32 (a right-hand tile partly or wholly past the edge, an odd
+    count of tiles per row), ragged heights, pairs split by the end of a pop,
+    and every output, against the flat form bit for bit and the oracle."""
+    _need_gpu()
+    box, quad = S.box_mesh(), S.quad_mesh()
+    sensors = [S.pinhole(20, 7, 80.0, 0.1, 40.0), S.pinhole(33, 9, 90.0, 0.1, 40.0),
+               S.pinhole(48, 4, 70.0, 0.1, 40.0), S.pinhole(17, 13, 60.0, 0.1, 40.0),
+               S.lidar(40, 6, 60.0, 0.2, 40.0), S.pinhole(64, 5, 75.0, 0.1, 40.0)]
+    T = lambda s, t: S.affine(np.diag(s), t)
+    rng = np.random.default_rng(3)
+    envs = []
+    for e in range(5):
+        insts = [(0, k + 1, T([0.4, 0.4, 0.4 + 0.2 * k], (1.5 + 0.7 * k, rng.uniform(-1, 1), 0.0)), 0, (0, 0, 0))
+                 for k in range(4 + e)]
+        insts.append((1, 0, T([20, 20, 1], (-10, -10, -0.5)), 0, (0, 0, 0)))
+        pose = S.sensor_pose(S.rot_zyx(0.2 * e, 5 * S.DEG), (0.0, 0.1 * e, 0.4))
+        envs.append((insts, [((e + j) % len(sensors), pose) for j in range(3)]))
+    scene = S.custom_scene([box, quad], envs, sensors, name="ragged")
+    R = _R(scene)
+    kw = dict(depth=True, seg=True, tri=True, hit=True)
+    ref = _host(R.render(mode=rc.RC_RENDER_FLAT, **kw))
+    for gs in (1, 2, 4, 16):
+        for lpt in (0, 1):
+            _say(f"pairs: chunk {gs} lpt {lpt}")
+            rc.rc_tuning_set(R.ctx, 16, gs, lpt, 2)
+            got = _host(R.render(mode=rc.RC_RENDER_BATCHED, **kw))
+            for k in ("depth", "seg", "tri", "hit_xyz"):
+                assert np.array_equal(got[k], ref[k], equal_nan=True), (gs, lpt, k)
+            only = _host(R.render(mode=rc.RC_RENDER_BATCHED, depth=True, seg=False, tri=False))
+            assert np.array_equal(only["depth"], ref["depth"]), (gs, lpt)
+    parity.assert_contract(parity.compare(ref, O.render(scene)))
+    R.close()
+
+
 def test_wide_nodes_equal_binary():
     """The four-wide records give the binary traversal's outputs bit for bit
     (and the oracle's under the contract) after builds with either builder,
