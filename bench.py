@@ -136,9 +136,45 @@ def cpu_baseline(cfg, seconds):
         O.render(sc, nthreads=cores)
         dt = time.perf_counter() - t0
     rays = sc.total_rays()
+    # the same oracle on one thread, over the first 8192 rays of the first environment
+    import numpy as np
+    one = S.make(cfg, env_ids=[0]) if cfg != 1 else S.make_cfg1()
+    n1 = min(8192, one.total_rays())
+    t0 = time.perf_counter()
+    O.render(one, nthreads=1, sensor_inst=np.zeros(n1, np.int64), ray_idx=np.arange(n1, dtype=np.int64))
+    dt1 = time.perf_counter() - t0
     return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_env} env(s) of cfg{cfg}, all {rays} rays, brute-force FP64, {dt:.1f} s",
-            "env_steps_per_s": n_env / dt}
+            "env_steps_per_s": n_env / dt, "cpu": cpu_model(),
+            "single_thread": {"Mrays_s": n1 / dt1 / 1e6, "sample": f"{n1} rays of 1 env of cfg{cfg}, {dt1:.2f} s"}}
+
+
+def per_step(fn, k):
+    """Each of k calls of fn timed by its own pair of HIP events (recorded on
+    the current stream, read after one synchronisation at the end): the
+    distribution of the step time."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    pick = lambda q: t[min(len(t) - 1, int(round(q * (len(t) - 1))))]
+    return {"steps": k, "median": pick(0.5), "p90": pick(0.9), "min": t[0], "max": t[-1]}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def timed(fn, k):
@@ -203,6 +239,8 @@ def bench_step(args):
     ms = timed(step, args.steps)
     ms_render = timed(render, args.steps)
     ms_refit = timed(lambda: rc.rc_refit(ctx), args.steps)
+    dist = per_step(step, args.steps)
+    log(f"per step: median {dist['median']:.3f} ms, p90 {dist['p90']:.3f} ms")
     widths = None
     if tuning is not None:
         # the same launch shape with the other node width (binary nodes / four-wide records)
@@ -319,6 +357,7 @@ def bench_step(args):
                    "step": "sensor + instance poses, transform of every instance, refit of every env's BVH, "
                            "batched render"},
         "env_steps_per_s": n_envs / (ms * 1e-3),
+        "per_step_ms": dist,
         "render_ms": ms_render,
         "render_Mrays_s": rays / ms_render / 1e3,
         "transform_refit_ms": ms_refit,
@@ -406,7 +445,9 @@ def bench_graph(args):
         rc.rc_graph_launch(g)
     rc.rc_graph_set_step(g, 0)
     ms = timed(lambda: rc.rc_graph_launch(g), n_steps)
-    log(f"graph step {ms:.3f} ms")
+    rc.rc_graph_set_step(g, 0)
+    dist = per_step(lambda: rc.rc_graph_launch(g), n_steps)
+    log(f"graph step {ms:.3f} ms (per step: median {dist['median']:.3f} ms, p90 {dist['p90']:.3f} ms)")
 
     step = [0]
 
@@ -441,6 +482,7 @@ def bench_graph(args):
             "config": {"workload": f"cfg4: {WORKLOADS[4]}", "envs": scene.n_envs, "rays_per_step": rays,
                        "tuning": tuning, "step": "move + transform + refit + queue reset + batched render (graph)"},
             "env_steps_per_s": scene.n_envs / (ms * 1e-3),
+            "per_step_ms": dist,
             "plain": {"ms_per_step": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_graph_vs_plain":
                       ms_plain / ms},
             "two_level": {"ms_per_step": ms2, "Mrays_s": rays / ms2 / 1e3, "tuning": tuning2,
@@ -619,9 +661,9 @@ def main():
             r4 = bench_graph(args)
             result["other_workloads"] = {
                 "cfg2": {k: r2[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "render_ms",
-                                            "render_Mrays_s", "transform_refit_ms", "flat", "two_level", "plain",
+                                            "render_Mrays_s", "transform_refit_ms", "per_step_ms", "flat", "two_level", "plain",
                                             "traversal", "node_width", "further_outputs")},
-                "cfg4": {k: r4[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "plain",
+                "cfg4": {k: r4[k] for k in ("value", "unit", "ms_per_step", "config", "env_steps_per_s", "per_step_ms", "plain",
                                             "two_level")}}
     if not args.no_cpu and args.cfg in (1, 2, 3, 4):
         log("cpu baseline")
