@@ -95,7 +95,7 @@ rc_status rc_mesh_add(rc_context *ctx, const float *xyz, int32_t n_verts, const 
 /* Environment-local triangle numbering: instances in CSR order, then the    */
 /* prototype's triangle order.  Replaces any previous scene atomically: on   */
 /* error the previous scene (and its BVH) is untouched.  Sensors must be     */
-/* attached again after a new scene.  An environment holds at most 2^25     */
+/* attached again after a new scene.  An environment holds at most 2^21     */
 /* triangles (the BVH depth bound that sizes the traversal stack), the      */
 /* whole scene fewer than 2^31; larger inputs are RC_E_INVALID.             */
 /* ------------------------------------------------------------------------ */

@@ -15,11 +15,12 @@ namespace rc {
 // environment's leaf-ordered triangle records.
 // ---------------------------------------------------------------------------
 // The depth bound sizes the per-lane traversal stack in LDS, and that stack
-// is what limits how many render waves a CU holds: 22 keeps six waves per
-// SIMD resident (24 KB of stack per 256-thread block) and still admits
-// 2^25 triangles per environment.
+// is what limits how many render waves a CU holds: 18 keeps seven waves per
+// SIMD resident (20 KB of stack and 2 KB of output-pair slots per 256-thread
+// block, seven blocks in a CU's 160 KB) and still admits 2^21 triangles per
+// environment.
 #ifndef RC_MAX_NODE_DEPTH
-#define RC_MAX_NODE_DEPTH 22
+#define RC_MAX_NODE_DEPTH 18
 #endif
 constexpr int kLeafMax = 4;                        // triangles per leaf (<= 8 by the encoding)
 constexpr int kMaxNodeDepth = RC_MAX_NODE_DEPTH;   // internal-node depth bound enforced by the builder
@@ -105,7 +106,11 @@ struct SensorModel {
 // as a triangle and the environment-local instance index as its id.
 constexpr int kTopDepth = 10;     // top-level internal-node depth bound (<= 4 << 11 instances per env)
 constexpr int kBottomDepth = 11;  // bottom-level bound (<= 4 << 12 triangles per mesh)
-static_assert((kTopDepth + 1) + (kBottomDepth + 1) <= kStack, "both levels share the traversal stack");
+// The two-level kernels run at four waves per SIMD (their registers, not LDS,
+// bound them) and have a deeper stack of their own.
+constexpr int kStackTwo = 24;
+static_assert((kTopDepth + 1) + (kBottomDepth + 1) <= kStackTwo, "both levels share the traversal stack");
+static_assert(kTopDepth <= kMaxNodeDepth && kBottomDepth <= kMaxNodeDepth, "levels within the builder's bound");
 struct InstView {
     const Node *tnodes = nullptr;        // top level; tnodes == nullptr: a flat scene
     const TriRec *trecs = nullptr;       // top-level leaf records, env e from inst_off[e]

@@ -26,10 +26,11 @@ constexpr float kU = 0x1p-24f;              // unit roundoff
 constexpr float kErr = 0x1p-17f;            // triple-product error factor (>= 48 u)
 constexpr float kBoxGrow = 1.0f + 0x1p-20f;  // >= 1 + 4 gamma_3 (robust slab test)
 constexpr int kBlock = 256;
-// Render kernels are latency bound at low occupancy: ask for at least six
-// waves per SIMD (80 VGPRs), which the LDS stack also admits.
+// Render kernels are latency bound: ask for seven waves per SIMD (72 VGPRs),
+// which the LDS stack also admits (six waves measured 23 % slower than seven
+// on the LiDAR forest; five, 23 % slower than six).
 #ifndef RC_MIN_WAVES
-#define RC_MIN_WAVES 6
+#define RC_MIN_WAVES 7
 #endif
 #define RC_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(RC_MIN_WAVES, 8)))
 // Two-level scenes keep a second (object-space) ray in registers: four waves
@@ -542,8 +543,12 @@ __device__ __forceinline__ void descend_wide(const Ray &r, Rsrc wide, int *stk, 
 }
 
 // nodes: the binary node array, or with WIDE the four-wide records.
+// The ray is updated in place: knd is set before each leaf phase and the slab
+// constants are computed again after it, from opaque copies of the direction
+// and its inverse, so neither stays in registers through the other phase
+// (that keeps the kernel within the 72 registers of seven waves per SIMD).
 template <bool STATS, bool WIDE>
-__device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, const TriRec *__restrict__ recs, int root,
+__device__ __forceinline__ void traverse(Ray &r, Rsrc nodes, Rsrc rv, const TriRec *__restrict__ recs, int root,
                                          int *stk, Best &b, Stats &st)
 {
     const int oct = wave_octant(r);
@@ -611,6 +616,11 @@ __device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, cons
                 descend<STATS, kMixed>(r, nodes, stk, b.hi, sp, ref, leaf, st);
             break;
         }
+        {
+            float ax = r.dx, ay = r.dy, az = r.dz;
+            asm volatile("" : "+v"(ax), "+v"(ay), "+v"(az));
+            r.knd = kErr * fmaxf(fmaxf(fabsf(ax), fabsf(ay)), fabsf(az));
+        }
         while (leaf != kDone) {
             const int code = ~leaf;
             const int first = code >> 3, cnt = (code & 7) + 1;
@@ -630,6 +640,8 @@ __device__ __forceinline__ void traverse(const Ray &r, Rsrc nodes, Rsrc rv, cons
         }
         if (ref == kDone)
             break;
+        asm volatile("" : "+v"(r.ix), "+v"(r.iy), "+v"(r.iz));
+        slab_consts(r);
     }
 }
 
@@ -1118,7 +1130,7 @@ template <bool TWO, bool WIDE>
 __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_flat(SceneView sc, SensorView se, OutView o, int64_t item_begin,
                                                         int64_t n_items)
 {
-    __shared__ int s_stack[kStack * kBlock];
+    __shared__ int s_stack[(TWO ? kStackTwo : kStack) * kBlock];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t k = lb * (kBlock / 64) + uniform(threadIdx.x >> 6);
     if (k >= n_items)
@@ -1131,7 +1143,7 @@ template <bool TWO, bool WIDE>
 __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_stats(SceneView sc, SensorView se, OutView o, int64_t n_items,
                                                          unsigned long long *counters)
 {
-    __shared__ int s_stack[kStack * kBlock];
+    __shared__ int s_stack[(TWO ? kStackTwo : kStack) * kBlock];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t k = lb * (kBlock / 64) + uniform(threadIdx.x >> 6);
     if (k >= n_items)
@@ -1158,7 +1170,7 @@ template <bool TWO, bool WIDE>
 __global__ __launch_bounds__(kBlock) RC_WAVES_PER_EU_T void k_render_batched(SceneView sc, SensorView se, OutView o,
                                                                            QueueView q)
 {
-    __shared__ int s_stack[kStack * kBlock];
+    __shared__ int s_stack[(TWO ? kStackTwo : kStack) * kBlock];
     __shared__ int2 s_pair[kBlock];
     const int lane = threadIdx.x & 63;
     int qi = blockIdx.x & (kQueues - 1);

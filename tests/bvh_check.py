@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import numpy as np
 
-MAX_NODE_DEPTH = 22
+MAX_NODE_DEPTH = 18
 
 
 def _expand_lo(x):

@@ -18,7 +18,7 @@ that harmless)."""
 import numpy as np
 import pytest
 
-DEPTH = 22              # internal-node depth bound of the builder
+DEPTH = 18              # internal-node depth bound of the builder
 STACK = DEPTH + 2       # entries of the traversal stack
 
 
