@@ -1730,8 +1730,9 @@ __global__ __launch_bounds__(kRefitBlock) void k_wide_fill(BuildView v)
 // prefix lengths.  A range of at most kLeafMax keys is a leaf, node ids are
 // the radix-tree indices (those absorbed into leaves stay unused), and each
 // kept node's depth is the length of its parent chain.  Bounds are left to the
-// refit.  An environment outside that size range, or whose tree would be
-// deeper than kMaxNodeDepth, is flagged in sah_mask for the SAH kernels.
+// refit.  A tree that would be deeper than kMaxNodeDepth is replaced by
+// index-median splits of the same sorted order; an environment outside the
+// size range is flagged in sah_mask for the SAH kernels.
 // ---------------------------------------------------------------------------
 constexpr int kLbvhMax = 8192;  // 64 KB of sort keys + 16 KB of parent links in LDS (40 KB up to 4096)
 static_assert(kLbvhMax <= 32768, "parent links are 16-bit");
@@ -1898,15 +1899,43 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
     }
     atomicMax(&s_depth, dmax);
     __syncthreads();
-    if (tid == 0) {
-        if (s_depth > kMaxNodeDepth) {  // too deep for the traversal stack: SAH instead
-            sah_mask[e] = 1;
-        } else {
-            sah_mask[e] = 0;
-            v.env_root[e] = 0;
-            v.env_nodes[e] = n - 1;
-            v.env_micro[e] = 0;
+    if (s_depth > kMaxNodeDepth) {
+        // Too deep for the traversal stack: the same sorted order split at
+        // index medians instead (balanced, depth below log2(n / kLeafMax)).
+        // Heap numbering: node h (root 1) has id h - 1 and children 2h,
+        // 2h + 1; its range comes from halving [0, n) along the bits of h.
+        // Every id 0 .. n - 2 is rewritten: internal node or hole.
+        for (int h = tid + 1; h <= n - 1; h += NT) {
+            const int d = 31 - __clz(h);
+            int f = 0, l = n;
+            bool exists = true;
+            for (int b = d - 1; b >= 0; --b) {
+                if (l - f <= kLeafMax) {  // an ancestor is a leaf
+                    exists = false;
+                    break;
+                }
+                const int mid = f + (l - f) / 2;
+                if ((h >> b) & 1)
+                    f = mid;
+                else
+                    l = mid;
+            }
+            Node &nd = nodes[h - 1];
+            nd.xy0 = nd.xy1 = nd.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (!exists || l - f <= kLeafMax) {
+                nd.ch = make_int4(0, 0, -1, -1);
+                continue;
+            }
+            const int mid = f + (l - f) / 2, nl = mid - f, nr = l - mid;
+            nd.ch = make_int4(nl > kLeafMax ? 2 * h - 1 : leaf_ref(f, nl), nr > kLeafMax ? 2 * h : leaf_ref(mid, nr),
+                              h == 1 ? -1 : h / 2 - 1, d);
         }
+    }
+    if (tid == 0) {
+        sah_mask[e] = 0;
+        v.env_root[e] = 0;
+        v.env_nodes[e] = n - 1;
+        v.env_micro[e] = 0;
     }
 }
 

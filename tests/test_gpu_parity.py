@@ -547,7 +547,8 @@ def _comb_scene():
 def test_lbvh_builder():
     """RC_BUILD_LBVH: every environment's BVH is valid and renders bit-identical
     to the SAH build in every mode.  Covers environments above 4096 triangles
-    (cfg2, built by SAH), the Morton comb (radix tree too deep: SAH), tiny and
+    (cfg2, built by SAH), the Morton comb (radix tree too deep: index-median
+    splits of the Morton order), tiny and
     single-leaf environments, a masked LBVH rebuild, and a refit of an LBVH
     tree against the oracle at moved poses."""
     from paper_2503_01471_amd import rc
