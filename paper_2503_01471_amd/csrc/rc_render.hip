@@ -1387,7 +1387,7 @@ constexpr float kShadowS0 = 0x1p-13f;  // lower end of the segment parameter
 // nodes until every active lane holds a leaf, then the leaves), with the
 // node loop specialised on the wavefront's direction octant; a lane that
 // finds an occluder stops.  The answer does not depend on the order.
-__device__ __forceinline__ bool any_hit(const Ray &r, Rsrc nodes, Rsrc rv, int root, int *stk)
+__device__ __forceinline__ bool any_hit(Ray &r, Rsrc nodes, Rsrc rv, int root, int *stk)
 {
     const int oct = wave_octant(r);
     Stats st{0, 0, 0};
@@ -1411,6 +1411,11 @@ __device__ __forceinline__ bool any_hit(const Ray &r, Rsrc nodes, Rsrc rv, int r
         case 7: descend<false, 7>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
         default: descend<false, kMixed>(r, nodes, stk, r.tf, sp, ref, leaf, st); break;
         }
+        {  // as in traverse: knd for the leaf phase only
+            float ax = r.dx, ay = r.dy, az = r.dz;
+            asm volatile("" : "+v"(ax), "+v"(ay), "+v"(az));
+            r.knd = kErr * fmaxf(fmaxf(fabsf(ax), fabsf(ay)), fabsf(az));
+        }
         while (leaf != kDone) {
             const int code = ~leaf;
             const int first = code >> 3, cnt = (code & 7) + 1;
@@ -1433,6 +1438,8 @@ __device__ __forceinline__ bool any_hit(const Ray &r, Rsrc nodes, Rsrc rv, int r
         }
         if (ref == kDone)
             break;
+        asm volatile("" : "+v"(r.ix), "+v"(r.iy), "+v"(r.iz));  // slab constants for the next node phase
+        slab_consts(r);
     }
     return hit;
 }
@@ -1441,7 +1448,10 @@ __device__ __forceinline__ bool any_hit(const Ray &r, Rsrc nodes, Rsrc rv, int r
 // winner read from the tri output, rounded as the hit output is), the second
 // centre c2 = pose applied to the baseline (FP32, the transform's fma order),
 // the segment p + s (c2 - p), s in [kShadowS0, 1].
-__global__ __launch_bounds__(kBlock) void k_stereo_shadow(SceneView sc, SensorView se, OutView o, int64_t n_items)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_stereo_shadow(SceneView sc,
+                                                                                                   SensorView se,
+                                                                                                   OutView o,
+                                                                                                   int64_t n_items)
 {
     __shared__ int s_stack[kStack * kBlock];
     // each XCD walks a contiguous range of tiles (environments stay in one L2)
