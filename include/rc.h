@@ -171,11 +171,11 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /*   RC_BUILD_SAH   surface-area heuristic (binned splits for large nodes,   */
 /*                  exact sweeps below), one wavefront per environment; the  */
 /*                  faster trees to render.                                  */
-/*   RC_BUILD_LBVH  linear BVH (Morton order, radix tree as in Karras 2012),  */
-/*                  one workgroup per environment of 5..8192 triangles; the  */
-/*                  faster build.  A radix tree that would exceed the depth  */
-/*                  bound is replaced by index-median splits of the same     */
-/*                  order; other environments get the SAH build.            */
+/*   RC_BUILD_LBVH  linear BVH (Morton order, the radix splits of Karras      */
+/*                  2012, built top-down; a subtree that could exceed the    */
+/*                  depth bound splits at index medians instead), one        */
+/*                  workgroup per environment of 5..8192 triangles; the      */
+/*                  faster build.  Other environments get the SAH build.     */
 /* Every builder gives the same render results (the nearest hit is exact).  */
 /* rc_refit re-transforms the dynamic instances and recomputes the bounds    */
 /* bottom-up on the fixed topology.  Both are asynchronous on `stream`.      */

@@ -1723,19 +1723,20 @@ __global__ __launch_bounds__(kRefitBlock) void k_wide_fill(BuildView v)
 // K6: linear BVH (builder RC_BUILD_LBVH), one workgroup per environment of
 // kLeafMax + 1 .. kLbvhMax triangles.  Centroids are quantised to 10 bits per
 // axis inside the environment's centroid bounds and bit-interleaved (Morton
-// order), and the (code, triangle id) keys are sorted in LDS.  Over the sorted
-// keys the radix tree of Karras (2012) has one internal node per adjacent key
-// pair: node i finds the far end of its key range and the position where the
-// range's highest differing bit changes, both by binary search on common
-// prefix lengths.  A range of at most kLeafMax keys is a leaf, node ids are
-// the radix-tree indices (those absorbed into leaves stay unused), and each
-// kept node's depth is the length of its parent chain.  Bounds are left to the
-// refit.  A tree that would be deeper than kMaxNodeDepth is replaced by
-// index-median splits of the same sorted order; an environment outside the
-// size range is flagged in sah_mask for the SAH kernels.
+// order), and the (code, triangle id) keys are sorted in LDS.  The tree is
+// then built top-down, one level per step: a node over the sorted keys
+// first .. last splits where the range's highest differing key bit changes
+// (the split of the radix tree of Karras 2012, found by binary search on
+// common prefix lengths), unless a subtree that deep could exceed
+// kMaxNodeDepth, in which case it splits at the index median (the SAH
+// builder's rule), so the depth bound always holds.  A node's id is its split
+// position (the last key of its left part): unique, and deterministic
+// whatever the order the level's ranges are processed in; ids that no node
+// takes stay holes.  Bounds are left to the refit.  An environment outside
+// the size range is flagged in sah_mask for the SAH kernels.
 // ---------------------------------------------------------------------------
-constexpr int kLbvhMax = 8192;  // 64 KB of sort keys + 16 KB of parent links in LDS (40 KB up to 4096)
-static_assert(kLbvhMax <= 32768, "parent links are 16-bit");
+constexpr int kLbvhMax = 8192;  // 64 KB of sort keys + 16 KB of level lists in LDS (40 KB up to 4096)
+static_assert(kLbvhMax <= 65536, "ranges are packed as two 16-bit key positions");
 
 __device__ __forceinline__ uint32_t spread3(uint32_t x)  // bit b of a 10-bit value -> bit 3b
 {
@@ -1762,9 +1763,15 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
 {
     static_assert(MAXN <= kLbvhMax, "above the LBVH size limit");
     __shared__ uint64_t key[MAXN];
-    __shared__ short par[MAXN];  // parent of each kept node (-2: absorbed), fits 16 bits
+    // ranges of one level and of the next: (first, last) as 16-bit halves and
+    // 2 * parent id + side (the root's parent is -1); a range holds at least
+    // kLeafMax + 1 keys, so a level has at most MAXN / 5 of them
+    constexpr int kList = MAXN / 5 + 1;
+    __shared__ uint32_t wr[2][kList];
+    __shared__ int wp[2][kList];
+    __shared__ int wcnt[2];
     __shared__ float red[6][NT / 64];
-    __shared__ int s_depth;
+    __shared__ int s_root;
     const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t base = v.env_tri_off[e];
     const int n = (int)(v.env_tri_off[e + 1] - base);
@@ -1796,8 +1803,6 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
             red[3 + k][wave] = hi[k];
         }
     }
-    if (tid == 0)
-        s_depth = 0;
     __syncthreads();
     float scale[3];
 #pragma unroll
@@ -1824,7 +1829,6 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
             k64 = ((uint64_t)code << 32) | (uint32_t)i;
         }
         key[i] = k64;
-        par[i] = 0;
     }
     __syncthreads();
     // bitonic sort: pair (i, i + j), i with bit j clear, ascending where bit k of i is clear
@@ -1845,95 +1849,79 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
     int32_t *prim = v.prim + base;
     for (int i = tid; i < n; i += NT)
         prim[i] = (int)(uint32_t)key[i];
-    // radix tree; delta = common prefix length of two keys, -1 outside the keys
+    // top-down construction; delta = common prefix length of two keys
     Node *nodes = v.nodes + node_base(base, e);
-    auto delta = [&](int a, int b) -> int { return (b < 0 || b >= n) ? -1 : __clzll(key[a] ^ key[b]); };
-    for (int i = tid; i < n - 1; i += NT) {
-        const int d = delta(i, i + 1) > delta(i, i - 1) ? 1 : -1;
-        const int dmin = delta(i, i - d);
-        int lmax = 2;
-        while (delta(i, i + lmax * d) > dmin)
-            lmax <<= 1;
-        int l = 0;
-        for (int t = lmax >> 1; t > 0; t >>= 1)
-            if (delta(i, i + (l + t) * d) > dmin)
-                l += t;
-        const int j = i + l * d;
-        const int dnode = delta(i, j);
-        int s = 0, t = l;
-        do {
-            t = (t + 1) >> 1;
-            if (delta(i, i + (s + t) * d) > dnode)
-                s += t;
-        } while (t > 1);
-        const int g = i + s * d + (d < 0 ? -1 : 0);  // the left part ends at key g
-        const int first = i < j ? i : j, last = i < j ? j : i;
+    auto delta = [&](int a, int b) -> int { return __clzll(key[a] ^ key[b]); };
+    for (int i = tid; i < n - 1; i += NT) {  // every id a hole until a node takes it
         Node &nd = nodes[i];
-        if (last - first + 1 <= kLeafMax) {  // absorbed into its parent's leaf
-            nd.xy0 = nd.xy1 = nd.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
-            nd.ch = make_int4(0, 0, -1, -1);
-            par[i] = -2;  // no other thread writes par[i]: the parent links kept children only
-            continue;
-        }
-        const int nl = g - first + 1, nr = last - g;
-        nd.ch.x = nl > kLeafMax ? g : leaf_ref(first, nl);
-        nd.ch.y = nr > kLeafMax ? g + 1 : leaf_ref(g + 1, nr);
-        if (nl > kLeafMax)
-            par[g] = i;
-        if (nr > kLeafMax)
-            par[g + 1] = i;
+        nd.xy0 = nd.xy1 = nd.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
+        nd.ch = make_int4(0, 0, -1, -1);
+    }
+    if (tid == 0) {
+        wr[0][0] = (uint32_t)(n - 1) << 16;  // keys 0 .. n - 1
+        wp[0][0] = -2;                        // parent -1, side 0
+        wcnt[0] = 1;
+        wcnt[1] = 0;
     }
     __syncthreads();
-    // depths from the parent chains (node 0 is the root)
-    int dmax = 0;
-    for (int i = tid; i < n - 1; i += NT) {
-        if (par[i] == -2)
-            continue;  // unused id
-        int dep = 0;
-        for (int p = i; p > 0 && dep <= kLevels; p = par[p])
-            ++dep;
-        Node &nd = nodes[i];
-        nd.ch.z = i == 0 ? -1 : par[i];
-        nd.ch.w = dep;
-        dmax = dep > dmax ? dep : dmax;
-    }
-    atomicMax(&s_depth, dmax);
-    __syncthreads();
-    if (s_depth > kMaxNodeDepth) {
-        // Too deep for the traversal stack: the same sorted order split at
-        // index medians instead (balanced, depth below log2(n / kLeafMax)).
-        // Heap numbering: node h (root 1) has id h - 1 and children 2h,
-        // 2h + 1; its range comes from halving [0, n) along the bits of h.
-        // Every id 0 .. n - 2 is rewritten: internal node or hole.
-        for (int h = tid + 1; h <= n - 1; h += NT) {
-            const int d = 31 - __clz(h);
-            int f = 0, l = n;
-            bool exists = true;
-            for (int b = d - 1; b >= 0; --b) {
-                if (l - f <= kLeafMax) {  // an ancestor is a leaf
-                    exists = false;
-                    break;
+    int cur = 0;
+    for (int depth = 0; depth <= kMaxNodeDepth; ++depth) {
+        const int cnt = wcnt[cur], nxt = cur ^ 1;
+        if (cnt == 0)
+            break;
+        for (int t = tid; t < cnt; t += NT) {
+            const int first = (int)(wr[cur][t] & 0xffffu), last = (int)(wr[cur][t] >> 16);
+            const int pw = wp[cur][t], parent = pw >> 1, side = pw & 1;
+            const int size = last - first + 1;
+            int g;  // the left part ends at key g
+            if (depth + levels_needed(size) - 1 >= v.max_depth) {
+                g = first + size / 2 - 1;
+            } else {
+                const int dnode = delta(first, last);
+                int lo = first, hi = last - 1;  // largest g with delta(first, g) > dnode
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (delta(first, mid) > dnode)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
                 }
-                const int mid = f + (l - f) / 2;
-                if ((h >> b) & 1)
-                    f = mid;
-                else
-                    l = mid;
+                g = lo;
             }
-            Node &nd = nodes[h - 1];
-            nd.xy0 = nd.xy1 = nd.z01 = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (!exists || l - f <= kLeafMax) {
-                nd.ch = make_int4(0, 0, -1, -1);
-                continue;
+            Node &nd = nodes[g];
+            nd.ch.z = parent;
+            nd.ch.w = depth;
+            if (parent < 0)
+                s_root = g;
+            else if (side == 0)
+                nodes[parent].ch.x = g;
+            else
+                nodes[parent].ch.y = g;
+            const int nl = g - first + 1, nr = last - g;
+            if (nl > kLeafMax) {
+                const int q = atomicAdd(&wcnt[nxt], 1);
+                wr[nxt][q] = (uint32_t)first | ((uint32_t)g << 16);
+                wp[nxt][q] = 2 * g;
+            } else {
+                nd.ch.x = leaf_ref(first, nl);
             }
-            const int mid = f + (l - f) / 2, nl = mid - f, nr = l - mid;
-            nd.ch = make_int4(nl > kLeafMax ? 2 * h - 1 : leaf_ref(f, nl), nr > kLeafMax ? 2 * h : leaf_ref(mid, nr),
-                              h == 1 ? -1 : h / 2 - 1, d);
+            if (nr > kLeafMax) {
+                const int q = atomicAdd(&wcnt[nxt], 1);
+                wr[nxt][q] = (uint32_t)(g + 1) | ((uint32_t)last << 16);
+                wp[nxt][q] = 2 * g + 1;
+            } else {
+                nd.ch.y = leaf_ref(g + 1, nr);
+            }
         }
+        __syncthreads();
+        if (tid == 0)
+            wcnt[cur] = 0;
+        cur = nxt;
+        __syncthreads();
     }
     if (tid == 0) {
         sah_mask[e] = 0;
-        v.env_root[e] = 0;
+        v.env_root[e] = s_root;
         v.env_nodes[e] = n - 1;
         v.env_micro[e] = 0;
     }
