@@ -27,8 +27,8 @@ constexpr float kErr = 0x1p-17f;            // triple-product error factor (>= 4
 constexpr float kBoxGrow = 1.0f + 0x1p-20f;  // >= 1 + 4 gamma_3 (robust slab test)
 constexpr int kBlock = 256;
 // Render kernels are latency bound: ask for seven waves per SIMD (72 VGPRs),
-// which the LDS stack also admits (six waves measured 23 % slower than seven
-// on the LiDAR forest; five, 23 % slower than six).
+// which the LDS stack also admits (on the LiDAR forest six waves measured
+// 4 % slower than seven, and five 23 % slower than six).
 #ifndef RC_MIN_WAVES
 #define RC_MIN_WAVES 7
 #endif
