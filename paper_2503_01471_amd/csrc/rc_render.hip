@@ -13,9 +13,10 @@
 // every BVH returns the exact nearest hit up to FP64 rounding, with the
 // lowest-id tie break, and all modes are bit-identical.
 //
-// Layout.  A wavefront (64 lanes) takes one tile of 8 x 8 rays of one sensor
-// instance; a 256-lane workgroup holds four such tiles.  The traversal stack
-// lives in LDS (kStack entries per lane, lane-interleaved).
+// Layout.  A wavefront (64 lanes) takes one tile of 64 rays of one sensor
+// instance (4, 8, 16 or 32 columns by 16, 8, 4 or 2 rows, a tuning choice);
+// a 256-lane workgroup holds four such tiles.  The traversal stack lives in
+// LDS (kStack entries per lane, lane-interleaved).
 #include "rc_common.hpp"
 
 namespace rc {
@@ -1066,7 +1067,7 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
     }
 }
 
-// One 8x8 tile per wavefront.
+// One 64-ray tile per wavefront; pair: the tile's role in an output pair.
 template <bool STATS, bool TWO, bool WIDE>
 __device__ __forceinline__ void render_tile(const SceneView &sc, const SensorView &se, const OutView &o, int2 item,
                                             int *stk, Stats &st, int pair = kPairNone, int2 *slot = nullptr)
