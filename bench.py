@@ -420,7 +420,41 @@ def bench_two_level(args, R, render, step, mode, ms_step, ms_render):
                          "fp64_evals_per_ray": stats[2] / rays}}
     log(f"two-level: build {ms_build:.3f} ms, step {ms:.3f} ms, render {ms_r:.3f} ms, refit {ms_refit:.3f} ms, "
         f"+{added / 2**20:.1f} MiB")
+    out["two_level_only"] = bench_two_level_only(args, R, rays)
     return out
+
+
+def bench_two_level_only(args, R, rays):
+    """The same scene loaded with RC_SCENE_TWO_LEVEL_ONLY in a context of its
+    own (no per-triangle arrays of the single-level form): library memory,
+    step and render (autotuned as the first context)."""
+    import torch
+    from paper_2503_01471_amd import rc
+    from paper_2503_01471_amd.renderer import Renderer
+    B = Renderer(R.scene, scene_flags=rc.RC_SCENE_TWO_LEVEL_ONLY)
+    torch.cuda.synchronize()
+    used = rc.rc_memory_used(B.ctx)
+    out_b = B.alloc(depth=True, seg=True)
+    ctx = B.ctx
+    tuning = rc.rc_autotune(ctx, args.tune_cache) if not args.no_autotune else None
+
+    def render():
+        rc.rc_render(ctx, out_b["depth"], out_b["seg"], None, None, rc.RC_RENDER_BATCHED, None, rays)
+
+    def step():
+        rc.rc_set_sensor_poses(ctx, B.sensor_T)
+        rc.rc_set_instance_poses(ctx, B.inst_T)
+        rc.rc_refit(ctx)
+        render()
+
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps)
+    ms_r = timed(render, args.steps)
+    B.close()
+    log(f"two-level only: library {used / 2**20:.1f} MiB, step {ms:.3f} ms, render {ms_r:.3f} ms")
+    return {"library_bytes": used, "ms_per_step": ms, "render_ms": ms_r, "tuning": tuning,
+            "Mrays_s": rays / ms / 1e3}
 
 
 # --------------------------------------------------------------------------

@@ -103,6 +103,24 @@ rc_status rc_scene_load(rc_context *ctx, int32_t n_envs, const int64_t *inst_off
                         const int32_t *inst_mesh, const int32_t *inst_seg, const uint8_t *inst_dynamic);
 
 /* ------------------------------------------------------------------------ */
+/* Scene options, read by every later rc_scene_load (flags 0: the default).  */
+/*   RC_SCENE_TWO_LEVEL_ONLY  the scene is only ever built two-level         */
+/*     (Sec. III-D sub-meshes kept in their own frames, see                 */
+/*     RC_BUILD_TWO_LEVEL): the per-triangle arrays of the single-level      */
+/*     form (world copy, leaf records, nodes and build lists, about 255     */
+/*     bytes per triangle) are not allocated, so the library holds the      */
+/*     meshes, the per-instance tables and the two BVH levels only, and the  */
+/*     2^21-triangle limit per environment does not apply.  With such a      */
+/*     scene RC_BUILD_SAH / RC_BUILD_LBVH, RC_RENDER_BRUTE, the further      */
+/*     outputs, stereo shadows and rc_debug_world / rc_debug_bvh return      */
+/*     RC_E_STATE; render results equal those of the same scene loaded       */
+/*     without the option and built two-level.                              */
+/* Unknown bits are RC_E_INVALID.                                            */
+/* ------------------------------------------------------------------------ */
+#define RC_SCENE_TWO_LEVEL_ONLY 1
+rc_status rc_scene_options(rc_context *ctx, int32_t flags);
+
+/* ------------------------------------------------------------------------ */
 /* Sensor models.                                                            */
 /*  RC_PINHOLE: width x height pixels, horizontal field of view hfov, square */
 /*    pixels (focal length (W/2)/tan(hfov/2)), pixel centres at +1/2; the    */

@@ -155,6 +155,7 @@ SceneView Scene::sview() const
         v.broot = bottom->env_root.as<int32_t>();
         v.mesh_tri_off = bottom->d_env_tri_off.as<int64_t>();
         v.inst_info = inst_info.as<int4>();
+        v.inst_seg = top->tri_seg.as<int32_t>();  // one primitive per instance, in instance order
         v.inv = inst_inv.as<double>();
         v.n_inst = n_inst;
         v.bnode_count = node_base(bottom->n_tris, bottom->n_envs) + 16;
@@ -262,7 +263,7 @@ rc_status set_node_width(rc_context *c, int width)
     if (!c->scene)
         return RC_OK;
     Scene &sc = *c->scene;
-    if (width != 4) {
+    if (width != 4 || sc.two_only) {  // (two-level scenes never traverse the four-wide records)
         sc.wide_on = false;
         return RC_OK;
     }
@@ -455,9 +456,11 @@ rc_status rc_mesh_add(rc_context *c, const float *xyz, int32_t n_verts, const in
 // mesh's triangles, or one primitive each with one_prim (a two-level scene's
 // top level: one box per instance, built like triangles).  `prim_limit`
 // bounds the primitives per environment.
+// per_tri = false (RC_SCENE_TWO_LEVEL_ONLY): no per-triangle array is
+// allocated, only the meshes and the per-instance and per-environment tables.
 static rc_status make_scene(rc_context *c, int32_t n_envs, const int64_t *inst_offsets, const int32_t *inst_mesh,
                             const int32_t *inst_seg, const uint8_t *inst_dynamic, bool one_prim, int64_t prim_limit,
-                            std::unique_ptr<Scene> &out)
+                            std::unique_ptr<Scene> &out, bool per_tri = true)
 {
     hipStream_t st = c->stream;
     const int64_t n_inst = inst_offsets[n_envs];
@@ -477,11 +480,17 @@ static rc_status make_scene(rc_context *c, int32_t n_envs, const int64_t *inst_o
     const int64_t N = sc->env_tri_off[n_envs];
     RC_CHECK(N < INT32_MAX, "too many triangles");
     sc->n_tris = N;
-    std::vector<int32_t> tri_env(N), tri_seg(N), dyn;
-    std::vector<int2> tri_src(N);
+    sc->two_only = !per_tri;
+    std::vector<int32_t> tri_env, tri_seg, dyn;
+    std::vector<int2> tri_src;
+    if (per_tri) {
+        tri_env.resize(N);
+        tri_seg.resize(N);
+        tri_src.resize(N);
+    }
     std::vector<uint8_t> dynf(n_inst, 0);
     std::vector<int32_t> inst_env(n_inst, 0);
-    int64_t g = 0;
+    int64_t g = 0, n_dyn = 0;
     for (int32_t e = 0; e < n_envs; ++e) {
         for (int64_t i = inst_offsets[e]; i < inst_offsets[e + 1]; ++i) {
             const Mesh &m = c->meshes[inst_mesh[i]];
@@ -489,6 +498,12 @@ static rc_status make_scene(rc_context *c, int32_t n_envs, const int64_t *inst_o
             dynf[i] = d;
             inst_env[i] = e;
             const int64_t n = one_prim ? 1 : m.n_tris;
+            if (d)
+                n_dyn += n;
+            if (!per_tri) {
+                g += n;
+                continue;
+            }
             for (int64_t k = 0; k < n; ++k, ++g) {
                 tri_env[g] = e;
                 tri_seg[g] = inst_seg[i];
@@ -498,41 +513,51 @@ static rc_status make_scene(rc_context *c, int32_t n_envs, const int64_t *inst_o
             }
         }
     }
-    sc->n_dyn = (int64_t)dyn.size();
+    sc->n_dyn = n_dyn;
     RC_TRY(upload(c, sc->proto_xyz, c->mesh_xyz.data(), c->mesh_xyz.size(), st));
     RC_TRY(upload(c, sc->proto_tri, c->mesh_tri.data(), c->mesh_tri.size(), st));
     RC_TRY(upload(c, sc->d_env_tri_off, sc->env_tri_off.data(), sc->env_tri_off.size(), st));
-    RC_TRY(upload(c, sc->tri_env, tri_env.data(), N, st));
-    RC_TRY(upload(c, sc->tri_seg, tri_seg.data(), N, st));
-    RC_TRY(upload(c, sc->tri_src, tri_src.data(), N, st));
     RC_TRY(upload(c, sc->inst_dyn, dynf.data(), n_inst, st));
     RC_TRY(upload(c, sc->inst_env, inst_env.data(), n_inst, st));
-    RC_TRY(upload(c, sc->dyn_tris, dyn.data(), dyn.size(), st));
     RC_TRY(c->pool.alloc(sc->inst_T, 48 * n_inst));
     RC_TRY(c->pool.alloc(sc->inst_T0, 48 * n_inst));
     RC_TRY(c->pool.alloc(sc->inst_Tw, 48 * n_inst));
     RC_TRY(c->pool.alloc(sc->stale_env, 4 * stale_words(n_envs)));
     RC_HIP(launch_fill_u32(sc->stale_env.as<unsigned int>(), stale_words(n_envs), 0u, st));
-    RC_TRY(c->pool.alloc(sc->world, 36 * N));
-    RC_TRY(c->pool.alloc(sc->box_lo, 16 * N));
-    RC_TRY(c->pool.alloc(sc->box_hi, 16 * N));
-    RC_TRY(c->pool.alloc(sc->prim, 4 * N));
-    RC_TRY(c->pool.alloc(sc->tmp, 4 * N));
-    RC_TRY(c->pool.alloc(sc->nodes, sizeof(Node) * (size_t)(node_base(N, n_envs) + 16)));
-    RC_TRY(c->pool.alloc(sc->recs, sizeof(TriRec) * N));
-    RC_TRY(c->pool.alloc(sc->pos_of, 4 * N));
     RC_TRY(c->pool.alloc(sc->env_root, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->env_nodes, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->env_micro, 4 * (size_t)n_envs));
-    RC_TRY(c->pool.alloc(sc->micro, 16 * N));
-    RC_TRY(c->pool.alloc(sc->level_nodes, 4 * (size_t)(node_base(N, n_envs) + 16)));
     RC_TRY(c->pool.alloc(sc->level_off, 4 * (size_t)n_envs * (kLevels + 1)));
     RC_TRY(c->pool.alloc(sc->micro_off, 8 * ((size_t)n_envs + 1)));
     RC_TRY(c->pool.alloc(sc->env_local, 4 * (size_t)n_envs));
     RC_TRY(c->pool.alloc(sc->local_off, 8 * ((size_t)n_envs + 1)));
     RC_TRY(c->pool.alloc(sc->sah_mask, (size_t)n_envs + 16));
-    RC_TRY(c->pool.alloc(sc->leaf_src, 16 * N));
+    if (per_tri) {
+        RC_TRY(upload(c, sc->tri_env, tri_env.data(), N, st));
+        RC_TRY(upload(c, sc->tri_seg, tri_seg.data(), N, st));
+        RC_TRY(upload(c, sc->tri_src, tri_src.data(), N, st));
+        RC_TRY(upload(c, sc->dyn_tris, dyn.data(), dyn.size(), st));
+        RC_TRY(c->pool.alloc(sc->world, 36 * N));
+        RC_TRY(c->pool.alloc(sc->box_lo, 16 * N));
+        RC_TRY(c->pool.alloc(sc->box_hi, 16 * N));
+        RC_TRY(c->pool.alloc(sc->prim, 4 * N));
+        RC_TRY(c->pool.alloc(sc->tmp, 4 * N));
+        RC_TRY(c->pool.alloc(sc->nodes, sizeof(Node) * (size_t)(node_base(N, n_envs) + 16)));
+        RC_TRY(c->pool.alloc(sc->recs, sizeof(TriRec) * N));
+        RC_TRY(c->pool.alloc(sc->pos_of, 4 * N));
+        RC_TRY(c->pool.alloc(sc->micro, 16 * N));
+        RC_TRY(c->pool.alloc(sc->level_nodes, 4 * (size_t)(node_base(N, n_envs) + 16)));
+        RC_TRY(c->pool.alloc(sc->leaf_src, 16 * N));
+    }
     out = std::move(sc);
+    return RC_OK;
+}
+
+rc_status rc_scene_options(rc_context *c, int32_t flags)
+{
+    RC_CHECK(c, "NULL context");
+    RC_CHECK((flags & ~RC_SCENE_TWO_LEVEL_ONLY) == 0, "unknown scene option bits 0x%x", (unsigned)flags);
+    c->scene_flags = flags;
     return RC_OK;
 }
 
@@ -554,7 +579,9 @@ rc_status rc_scene_load(rc_context *c, int32_t n_envs, const int64_t *inst_offse
                  (long long)i, inst_mesh[i]);
     RC_TRY(set_device(c));
     std::unique_ptr<Scene> sc;
-    RC_TRY(make_scene(c, n_envs, inst_offsets, inst_mesh, inst_seg, inst_dynamic, false, kMaxEnvTris, sc));
+    const bool two_only = (c->scene_flags & RC_SCENE_TWO_LEVEL_ONLY) != 0;
+    RC_TRY(make_scene(c, n_envs, inst_offsets, inst_mesh, inst_seg, inst_dynamic, false,
+                      two_only ? INT32_MAX : kMaxEnvTris, sc, !two_only));
     sc->inst_mesh.assign(inst_mesh, inst_mesh + n_inst);
     sc->inst_seg_h.assign(inst_seg, inst_seg + n_inst);
     RC_HIP(hipStreamSynchronize(c->stream));
@@ -851,13 +878,16 @@ rc_status rc_build(rc_context *c, const uint8_t *d_env_mask, int32_t builder, vo
         return fail(RC_E_STATE, "a masked rc_build needs a full build first");
     if (d_env_mask && two != sc.two_level)
         return fail(RC_E_STATE, "a masked rc_build must use the form (two-level or not) of the last full build");
+    if (sc.two_only && !two)
+        return fail(RC_E_STATE, "a scene loaded with RC_SCENE_TWO_LEVEL_ONLY builds with RC_BUILD_TWO_LEVEL only");
     RC_TRY(set_device(c));
     hipStream_t st = pick(c, stream);
     if (two)  // before any work is queued: this may fail on the mesh size limit
         RC_TRY(two_level_tables(c, sc, st));
     BuildView v = sc.view();
     v.env_mask = d_env_mask;
-    RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
+    if (!sc.two_only)  // the world copy
+        RC_HIP(launch_transform(v, nullptr, sc.n_tris, false, st));
     // the rebuilt environments' world triangles and records use these poses
     RC_HIP(launch_pose_snapshot(sc.n_inst, sc.inst_env.as<int32_t>(), sc.inst_dyn.as<uint8_t>(), d_env_mask, false,
                                 sc.inst_T.as<float>(), sc.inst_Tw.as<float>(), nullptr, st));
@@ -967,6 +997,9 @@ static rc_status render_on(rc_context *c, const rc_outputs *out, int32_t mode, h
     RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
     if (out->shadow && sc.two_level)
         return fail(RC_E_STATE, "stereo shadows need the single-level BVH (rc_build with RC_BUILD_SAH or LBVH)");
+    if (sc.two_only && (mode == RC_RENDER_BRUTE || extras))
+        return fail(RC_E_STATE, "the brute-force render and the further outputs read the world copy, which a scene "
+                                "loaded with RC_SCENE_TWO_LEVEL_ONLY does not keep");
     if (mode == RC_RENDER_BRUTE || extras || out->shadow)
         RC_TRY(fresh_world(c, st));
     switch (mode) {
@@ -1044,6 +1077,8 @@ rc_status rc_debug_world(rc_context *c, float *tris9)
     RC_CHECK(c && tris9, "NULL argument");
     if (!c->scene || !c->scene->built)
         return fail(RC_E_STATE, "no built scene");
+    if (c->scene->two_only)
+        return fail(RC_E_STATE, "a scene loaded with RC_SCENE_TWO_LEVEL_ONLY keeps no world copy");
     RC_TRY(set_device(c));
     RC_TRY(fresh_world(c, c->stream));
     RC_HIP(hipStreamSynchronize(c->stream));

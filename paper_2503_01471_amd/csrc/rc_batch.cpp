@@ -188,6 +188,9 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
     RC_CHECK(!(extras || out->shadow) || out->tri, "normal, bary, point, vert and shadow need the tri output");
     if (out->shadow && sc.two_level)
         return fail(RC_E_STATE, "stereo shadows need the single-level BVH (rc_build with RC_BUILD_SAH or LBVH)");
+    if (extras && sc.two_only)
+        return fail(RC_E_STATE, "the further outputs read the world copy, which a scene loaded with "
+                                "RC_SCENE_TWO_LEVEL_ONLY does not keep");
     RC_TRY(set_device(c));
     auto g = new rc_graph;
     g->ctx = c;

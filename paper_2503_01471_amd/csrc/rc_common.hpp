@@ -121,6 +121,7 @@ struct InstView {
     const int32_t *broot = nullptr;      // [M]
     const int64_t *mesh_tri_off = nullptr;  // [M+1]
     const int4 *inst_info = nullptr;     // [I] mesh, environment-local id of the instance's first triangle
+    const int32_t *inst_seg = nullptr;   // [I] segment label of each instance
     const double *inv = nullptr;         // [I][12] FP64 rows (M_r0 M_r1 M_r2 p_r) with M the inverse of
                                          // the pose's linear part and p its translation
     int64_t n_inst = 0, bnode_count = 0, brec_count = 0;  // sizes of the arrays above (range-checked loads)

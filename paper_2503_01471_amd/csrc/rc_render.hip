@@ -1014,7 +1014,8 @@ __device__ __forceinline__ void write_out(const OutView &o, const SceneView &sc,
         hy = (float)((double)r.oy + t * (double)r.dy);
         hz = (float)((double)r.oz + t * (double)r.dz);
         tri = b.id;
-        seg = sc.tri_seg[sc.env_tri_off[env] + b.id];
+        // two-level scenes: the winner's instance (a global index) carries the label
+        seg = sc.inst.tnodes ? sc.inst.inst_seg[b.inst] : sc.tri_seg[sc.env_tri_off[env] + b.id];
     }
     if (o.depth_tab) {  // per-request buffers (served batches)
         float *dp = o.depth_tab[tl.s];

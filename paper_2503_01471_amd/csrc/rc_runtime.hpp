@@ -79,6 +79,9 @@ struct Scene {
     DBuf leaf_src;  // leaf order: instance, prototype triangle, env-local id, 0 (written by the build)
     bool poses_set = false;
     bool built = false;
+    // RC_SCENE_TWO_LEVEL_ONLY: the per-triangle arrays of the single-level
+    // form (world copy, records, nodes, build lists) were not allocated
+    bool two_only = false;
     // The per-step transform writes the leaf-ordered records only; the
     // original-order world copy (read by the brute-force render, the further
     // outputs, the stereo shadows and the debug readback) is then stale until
@@ -163,6 +166,7 @@ struct rc_context {
     rc::Tuning tuning;
     int n_cu = 0, blocks_per_cu = 1, blocks_per_cu_two = 1;
     uint64_t generation = 0;   // bumped whenever scene or sensors are replaced
+    int32_t scene_flags = 0;   // rc_scene_options, read by the next rc_scene_load
     std::atomic<int> servers{0};  // live request servers (scene is read-only meanwhile)
     int batched_grid() const { return n_cu * (scene && scene->two_level ? blocks_per_cu_two : blocks_per_cu); }
 };

@@ -21,12 +21,13 @@ RC_PINHOLE, RC_LIDAR, RC_TABLE = 0, 1, 2
 RC_BUILD_SAH = 0
 RC_BUILD_LBVH = 1
 RC_BUILD_TWO_LEVEL = 2
+RC_SCENE_TWO_LEVEL_ONLY = 1
 RC_RENDER_PLAIN, RC_RENDER_FLAT, RC_RENDER_BATCHED, RC_RENDER_BRUTE = 0, 1, 2, 3
 
 # Every function declared in include/rc.h.
 ABI = [
     "rc_status_string", "rc_last_error", "rc_create", "rc_destroy", "rc_memory_used", "rc_mesh_add",
-    "rc_scene_load", "rc_sensor_add", "rc_sensors_attach", "rc_ray_layout", "rc_env_tri_offsets",
+    "rc_scene_load", "rc_scene_options", "rc_sensor_add", "rc_sensors_attach", "rc_ray_layout", "rc_env_tri_offsets",
     "rc_set_instance_poses", "rc_set_sensor_poses", "rc_move_instances", "rc_build", "rc_refit", "rc_render",
     "rc_render_noalloc", "rc_render_stats", "rc_debug_world", "rc_debug_rays", "rc_debug_bvh", "rc_autotune", "rc_tuning_set", "rc_step_graph_create",
     "rc_graph_set_step", "rc_graph_launch", "rc_graph_destroy", "rc_server_create", "rc_server_submit",
@@ -113,6 +114,7 @@ def lib():
             "rc_memory_used": (I32, [P, C.POINTER(SZ)]),
             "rc_mesh_add": (I32, [P, P, I32, P, I32, C.POINTER(I32)]),
             "rc_scene_load": (I32, [P, I32, P, P, P, P]),
+            "rc_scene_options": (I32, [P, I32]),
             "rc_sensor_add": (I32, [P, C.POINTER(rc_sensor_desc), C.POINTER(I32)]),
             "rc_sensors_attach": (I32, [P, P, P]),
             "rc_ray_layout": (I32, [P, P, C.POINTER(I64)]),
@@ -225,6 +227,10 @@ def rc_scene_load(ctx, inst_offsets, inst_mesh, inst_seg, inst_dynamic=None) -> 
     iseg = _host(inst_seg, np.int32)
     idyn = None if inst_dynamic is None else _host(inst_dynamic, np.uint8)
     _check(lib().rc_scene_load(ctx, len(io) - 1, _ptr(io), _ptr(im), _ptr(iseg), _ptr(idyn)))
+
+
+def rc_scene_options(ctx, flags) -> None:
+    _check(lib().rc_scene_options(ctx, int(flags)))
 
 
 def rc_sensor_add(ctx, kind, width, height, hfov=0.0, vmin=0.0, vmax=0.0, hmin=0.0, hmax=0.0, near=0.0,

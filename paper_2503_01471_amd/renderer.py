@@ -14,15 +14,19 @@ from . import rc
 
 
 class Renderer:
-    def __init__(self, scene, device: int = 0, hbm_budget: int = 0, build: bool = True, allocator: str = "torch"):
+    def __init__(self, scene, device: int = 0, hbm_budget: int = 0, build: bool = True, allocator: str = "torch",
+                 scene_flags: int = 0):
         """allocator: "torch" (library memory from torch's caching allocator) or
-        "hip" (the library's own hipMalloc)."""
+        "hip" (the library's own hipMalloc); scene_flags: rc_scene_options
+        (RC_SCENE_TWO_LEVEL_ONLY: build with RC_BUILD_TWO_LEVEL)."""
         self.scene = scene
         self.device = torch.device("cuda", device)
         hook = {"torch": lambda: rc.torch_allocator(device), "hip": lambda: None}[allocator]()
         self.ctx = rc.rc_create(device, None, hbm_budget, allocator=hook)
         for v, t in scene.protos:
             rc.rc_mesh_add(self.ctx, v, t)
+        if scene_flags:
+            rc.rc_scene_options(self.ctx, scene_flags)
         rc.rc_scene_load(self.ctx, scene.inst_offsets, scene.inst_mesh, scene.inst_seg, scene.inst_dynamic)
         for desc in scene.sensors:
             rc.rc_sensor_add(self.ctx, desc.kind, desc.width, desc.height, desc.hfov, desc.vmin, desc.vmax,
@@ -44,7 +48,7 @@ class Renderer:
         else:
             rc.rc_set_sensor_poses(self.ctx, torch.zeros(12, device=self.device))
         if build:
-            self.build()
+            self.build(builder=rc.RC_BUILD_TWO_LEVEL if scene_flags & rc.RC_SCENE_TWO_LEVEL_ONLY else rc.RC_BUILD_SAH)
 
     # -- acceleration structure --------------------------------------------
     def _mask(self, envs):

@@ -203,3 +203,65 @@ def test_two_level_full_size_sampled(cfg):
     rc.rc_autotune(R.ctx, None)
     _check(scene, R=R, sample=12000)
     R.close()
+
+
+def test_two_level_only_scene():
+    """RC_SCENE_TWO_LEVEL_ONLY: the renders of a two-level build of the same
+    scene loaded normally (every form, refits of moving boxes, a step graph)
+    and the oracle's, a fraction of the library memory, and RC_E_STATE for
+    what needs the single-level arrays."""
+    _need_gpu()
+    scene = S.make_cfg4(n_envs=6)
+    A = _R(scene, build=False)
+    rc.rc_build(A.ctx, rc.RC_BUILD_TWO_LEVEL)
+    B = _R(scene, scene_flags=rc.RC_SCENE_TWO_LEVEL_ONLY)
+    ma, mb = rc.rc_memory_used(A.ctx), rc.rc_memory_used(B.ctx)
+    print(f"library bytes: normal load {ma}, two-level only {mb}", flush=True)
+    assert mb < ma
+    ref = _render(A, rc.RC_RENDER_FLAT)
+    for mode in (rc.RC_RENDER_PLAIN, rc.RC_RENDER_FLAT, rc.RC_RENDER_BATCHED):
+        got = _render(B, mode)
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(got[k], ref[k]), (mode, k)
+        assert np.array_equal(np.nan_to_num(got["hit_xyz"]), np.nan_to_num(ref["hit_xyz"])), mode
+    parity.assert_contract(parity.compare(ref, O.render(scene, O.world64(scene))))
+    for step in (3, 40):
+        _say(f"two-level only, step {step}")
+        for R in (A, B):
+            R.move(step)
+            R.refit()
+        a, b = _render(A, rc.RC_RENDER_BATCHED), _render(B, rc.RC_RENDER_BATCHED)
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(a[k], b[k]), (step, k)
+    n = B.total_rays
+    gout = dict(depth=torch.empty(n, device="cuda"), seg=torch.empty(n, dtype=torch.int32, device="cuda"),
+                tri=torch.empty(n, dtype=torch.int32, device="cuda"))
+    g = rc.rc_step_graph_create(B.ctx, B.inst_vel, float(scene.dt), depth=gout["depth"], seg=gout["seg"],
+                                tri=gout["tri"], total_rays=n)
+    rc.rc_graph_set_step(g, 5)
+    rc.rc_graph_launch(g)
+    torch.cuda.synchronize()
+    A.move(5)
+    A.refit()
+    a = _render(A, rc.RC_RENDER_BATCHED)
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(gout[k].cpu().numpy(), a[k]), ("graph", k)
+    rc.rc_graph_destroy(g)
+    # what needs the single-level arrays
+    for call in (lambda: rc.rc_build(B.ctx, rc.RC_BUILD_SAH), lambda: rc.rc_build(B.ctx, rc.RC_BUILD_LBVH),
+                 lambda: B.render(mode=rc.RC_RENDER_BRUTE),
+                 lambda: B.render(mode=rc.RC_RENDER_BATCHED, depth=True, seg=True, tri=True, normal=True),
+                 lambda: B.render(out=B.alloc(depth=True, seg=True, tri=True, shadow=True), mode=rc.RC_RENDER_FLAT),
+                 lambda: rc.rc_debug_world(B.ctx, B.n_tris)):
+        with pytest.raises(rc.RCError) as ei:
+            call()
+        assert ei.value.status == -4
+    with pytest.raises(rc.RCError) as ei:
+        rc.rc_scene_options(B.ctx, 2)
+    assert ei.value.status == -1
+    # still usable after the refusals
+    b = _render(B, rc.RC_RENDER_BATCHED)
+    for k in ("depth", "seg", "tri"):
+        assert np.array_equal(b[k], a[k]), ("after errors", k)
+    A.close()
+    B.close()
