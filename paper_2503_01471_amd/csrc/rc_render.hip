@@ -1280,70 +1280,62 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
 
 // Further data types of the nearest hit: unit normal facing the sensor,
 // barycentric (u, v), sensor-frame point t * local direction, global vertex
-// ids; FP64 from the winner's FP32 world vertices (g: global original-order
-// triangle index, -1 on a miss).
-__device__ __forceinline__ void write_extras(const OutView &o, const SceneView &sc, int64_t g, int64_t idx, float ox,
-                                             float oy, float oz, float dxf, float dyf, float dzf, float lx, float ly,
-                                             float lz, double t, bool t_ok)
+// ids.  One FP64 Moller-Trumbore solve on the winner's FP32 world vertices
+// gives all of them: its t = W / det is the render's FP64 t bit for bit (the
+// same expressions in the same order; negating both W and det, as the
+// render's test does, leaves the quotient unchanged), u and v take one
+// reciprocal of det, the normal one reciprocal of its length.  g: global
+// original-order triangle index, -1 on a miss (NaN outputs, vertex ids -1).
+// Each output is one vector store per ray, so a wavefront writes whole
+// contiguous runs.
+__device__ __forceinline__ void write_extras(const OutView &o, const SceneView &sc, int64_t g, int64_t idx,
+                                             const Ray &r, float lx, float ly, float lz)
 {
-    if (g < 0) {
-        const float nan = __builtin_nanf("");
-        for (int k = 0; k < 3; ++k) {
-            if (o.normal)
-                o.normal[3 * idx + k] = nan;
-            if (o.point)
-                o.point[3 * idx + k] = nan;
-            if (o.vert)
-                o.vert[3 * idx + k] = -1;
-            if (o.bary && k < 2)
-                o.bary[2 * idx + k] = nan;
-        }
-        return;
-    }
-    const float *w = sc.world + 9 * g;
-    const double ax = w[0], ay = w[1], az = w[2];
-    const double e1x = (double)w[3] - ax, e1y = (double)w[4] - ay, e1z = (double)w[5] - az;
-    const double e2x = (double)w[6] - ax, e2y = (double)w[7] - ay, e2z = (double)w[8] - az;
-    const double dx = dxf, dy = dyf, dz = dzf;
-    if (o.normal) {
+    const float nan = __builtin_nanf("");
+    float3 nrm = make_float3(nan, nan, nan), pt = nrm;
+    float2 uv = make_float2(nan, nan);
+    int3 vid = make_int3(-1, -1, -1);
+    if (g >= 0) {
+        const float *w = sc.world + 9 * g;
+        const double ax = w[0], ay = w[1], az = w[2];
+        const double e1x = (double)w[3] - ax, e1y = (double)w[4] - ay, e1z = (double)w[5] - az;
+        const double e2x = (double)w[6] - ax, e2y = (double)w[7] - ay, e2z = (double)w[8] - az;
+        const double dx = r.dx, dy = r.dy, dz = r.dz;
+        const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+        const double det = e1x * px + e1y * py + e1z * pz;
+        const double Tx = (double)r.ox - ax, Ty = (double)r.oy - ay, Tz = (double)r.oz - az;
+        const double qx = Ty * e1z - Tz * e1y, qy = Tz * e1x - Tx * e1z, qz = Tx * e1y - Ty * e1x;
+        const double U = Tx * px + Ty * py + Tz * pz;
+        const double V = dx * qx + dy * qy + dz * qz;
+        const double W = e2x * qx + e2y * qy + e2z * qz;
+        const double t = W / det;
+        const double rdet = 1.0 / det;
+        uv = make_float2((float)(U * rdet), (float)(V * rdet));
+        pt = make_float3((float)(t * (double)lx), (float)(t * (double)ly), (float)(t * (double)lz));
         double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-        const double len = sqrt(nx * nx + ny * ny + nz * nz);
-        if (nx * dx + ny * dy + nz * dz > 0.0) {
-            nx = -nx;
-            ny = -ny;
-            nz = -nz;
+        double rl = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+        if (nx * dx + ny * dy + nz * dz > 0.0)
+            rl = -rl;
+        nrm = make_float3((float)(nx * rl), (float)(ny * rl), (float)(nz * rl));
+        if (o.vert) {
+            const int32_t *pv = sc.proto_tri + 3 * (int64_t)sc.tri_src[g].y;
+            vid = make_int3(pv[0], pv[1], pv[2]);
         }
-        o.normal[3 * idx + 0] = (float)(nx / len);
-        o.normal[3 * idx + 1] = (float)(ny / len);
-        o.normal[3 * idx + 2] = (float)(nz / len);
     }
-    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
-    const double det = e1x * px + e1y * py + e1z * pz;
-    const double Tx = (double)ox - ax, Ty = (double)oy - ay, Tz = (double)oz - az;
-    const double qx = Ty * e1z - Tz * e1y, qy = Tz * e1x - Tx * e1z, qz = Tx * e1y - Ty * e1x;
-    if (o.bary) {
-        o.bary[2 * idx + 0] = (float)((Tx * px + Ty * py + Tz * pz) / det);
-        o.bary[2 * idx + 1] = (float)((dx * qx + dy * qy + dz * qz) / det);
-    }
-    if (!t_ok)  // the certified winner always passes the FP64 test; plane t otherwise
-        t = (e2x * qx + e2y * qy + e2z * qz) / det;
-    if (o.point) {
-        o.point[3 * idx + 0] = (float)(t * (double)lx);
-        o.point[3 * idx + 1] = (float)(t * (double)ly);
-        o.point[3 * idx + 2] = (float)(t * (double)lz);
-    }
-    if (o.vert) {
-        const int2 src = sc.tri_src[g];
-        for (int k = 0; k < 3; ++k)
-            o.vert[3 * idx + k] = sc.proto_tri[3 * (int64_t)src.y + k];
-    }
+    if (o.normal)
+        *reinterpret_cast<float3 *>(o.normal + 3 * idx) = nrm;
+    if (o.bary)
+        *reinterpret_cast<float2 *>(o.bary + 2 * idx) = uv;
+    if (o.point)
+        *reinterpret_cast<float3 *>(o.point + 3 * idx) = pt;
+    if (o.vert)
+        *reinterpret_cast<int3 *>(o.vert + 3 * idx) = vid;
 }
 
 // Second pass for the further data types: one wavefront per 64-ray tile
-// reads the winner's id from the tri output, re-evaluates the winner's FP64
-// t exactly as the render did (the same Moller-Trumbore on the same FP32
-// values) and writes the requested buffers.  Kept apart from the traversal
-// kernels so that they carry none of its registers.
+// reads the winner's id from the tri output and writes the requested
+// buffers.  Kept apart from the traversal kernels so that they carry none of
+// its registers.
 __global__ __launch_bounds__(kBlock) void k_hit_extras(SceneView sc, SensorView se, OutView o, int64_t n_items)
 {
     const int64_t k = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + uniform(threadIdx.x >> 6);
@@ -1357,22 +1349,13 @@ __global__ __launch_bounds__(kBlock) void k_hit_extras(SceneView sc, SensorView 
     const int row = ty * (64 >> t.tw_shift) + (lane >> t.tw_shift), col = tx * tw + (lane & (tw - 1));
     if (row >= t.H || col >= t.W)
         return;
+    const int64_t idx = t.ray_base + (int64_t)row * t.W + col;
+    const int id = o.tri[idx];  // in flight while the ray is generated
     Ray r;
     gen_ray(se, t, row, col, r);
     float lx, ly, lz;
     local_dir(se, t, row, col, lx, ly, lz);
-    const int64_t idx = t.ray_base + (int64_t)row * t.W + col;
-    const int id = o.tri[idx];
-    int64_t g = -1;
-    double tt = 0.0;
-    bool ok = false;
-    if (id >= 0) {
-        g = sc.env_tri_off[t.env] + id;
-        const float *w = sc.world + 9 * g;
-        ok = mt64(r, make_float4(w[0], w[1], w[2], w[3]), make_float4(w[4], w[5], w[6], w[7]),
-                  make_float4(w[8], 0.f, 0.f, 0.f), tt);
-    }
-    write_extras(o, sc, g, idx, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, lx, ly, lz, tt, ok);
+    write_extras(o, sc, id >= 0 ? sc.env_tri_off[t.env] + id : -1, idx, r, lx, ly, lz);
 }
 
 
