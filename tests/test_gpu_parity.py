@@ -358,6 +358,11 @@ def test_hit_extras():
             for k in ref:
                 if ref[k] is not None:
                     assert np.array_equal(got[k], ref[k], equal_nan=ref[k].dtype.kind == "f"), (mode, k)
+        # any subset of the further outputs: each buffer holds what it holds when all are requested
+        for sub in (dict(point=True), dict(vert=True, bary=True), dict(normal=True, point=True)):
+            got = _host(R.render(mode=rc.RC_RENDER_BATCHED, depth=True, tri=True, **sub))
+            for k in sub:
+                assert np.array_equal(got[k], ref[k], equal_nan=ref[k].dtype.kind == "f"), (sorted(sub), k)
         ora = O.render(scene)
         rep = parity.compare_extras(ref, ora)
         print(rep, flush=True)
