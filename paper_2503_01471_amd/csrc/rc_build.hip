@@ -1723,7 +1723,11 @@ __global__ __launch_bounds__(kRefitBlock) void k_wide_fill(BuildView v)
 // K6: linear BVH (builder RC_BUILD_LBVH), one workgroup per environment of
 // kLeafMax + 1 .. kLbvhMax triangles.  Centroids are quantised to 10 bits per
 // axis inside the environment's centroid bounds and bit-interleaved (Morton
-// order), and the (code, triangle id) keys are sorted in LDS.  The tree is
+// order); a triangle whose box has a side above a quarter of the widest
+// centroid extent also sets the key's top bit, so the large triangles (a
+// ground plane, the walls of a room) form a subtree of their own beside the
+// root instead of widening the boxes of every subtree their centroids fall
+// in.  The (code, triangle id) keys are sorted in LDS.  The tree is
 // then built top-down, one level per step: a node over the sorted keys
 // first .. last splits where the range's highest differing key bit changes
 // (the split of the radix tree of Karras 2012, found by binary search on
@@ -1804,7 +1808,7 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
         }
     }
     __syncthreads();
-    float scale[3];
+    float scale[3], ext = 0.0f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         float a = red[k][0], b = red[3 + k][0];
@@ -1814,7 +1818,9 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
         }
         lo[k] = a;
         scale[k] = b > a ? 1024.0f / (b - a) : 0.0f;
+        ext = fmaxf(ext, b - a);
     }
+    const float big = 0.25f * ext;  // "large": a box side above a quarter of the widest centroid extent
     // keys, padded to a power of two with the largest key
     int P = 8;
     while (P < n)
@@ -1823,9 +1829,11 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
         uint64_t k64 = ~0ull;
         if (i < n) {
             const float4 a = blo[i], b = bhi[i];
+            const float size = fmaxf(fmaxf(b.x - a.x, b.y - a.y), b.z - a.z);
             const uint32_t code = (spread3(quant10(0.5f * (a.x + b.x), lo[0], scale[0])) << 2) |
                                   (spread3(quant10(0.5f * (a.y + b.y), lo[1], scale[1])) << 1) |
-                                  spread3(quant10(0.5f * (a.z + b.z), lo[2], scale[2]));
+                                  spread3(quant10(0.5f * (a.z + b.z), lo[2], scale[2])) |
+                                  (size > big ? 0x80000000u : 0u);
             k64 = ((uint64_t)code << 32) | (uint32_t)i;
         }
         key[i] = k64;
