@@ -189,14 +189,14 @@ rc_status rc_move_instances(rc_context *ctx, const float *d_vel, int32_t step, f
 /*   RC_BUILD_SAH   surface-area heuristic (binned splits for large nodes,   */
 /*                  exact sweeps below), one wavefront per environment; the  */
 /*                  faster trees to render.                                  */
-/*   RC_BUILD_LBVH  linear BVH (Morton order, the radix splits of Karras      */
-/*                  2012, built top-down; a subtree that could exceed the    */
-/*                  depth bound splits at index medians instead; triangles   */
-/*                  with a box side above a quarter of the environment's     */
-/*                  centroid extent sort after all others, so they form one  */
-/*                  subtree), one workgroup per environment of 5..8192       */
-/*                  triangles; the faster build.  Other environments get     */
-/*                  the SAH build.                                           */
+/*   RC_BUILD_LBVH  linear BVH (Morton order on cubic cells, the radix       */
+/*                  splits of Karras 2012, built top-down; a subtree that    */
+/*                  could exceed the depth bound splits at index medians     */
+/*                  instead; triangles with a box side above a quarter of    */
+/*                  the environment's centroid extent sort after all         */
+/*                  others, so they form one subtree), one workgroup per     */
+/*                  environment of 5..8192 triangles; the faster build.      */
+/*                  Other environments get the SAH build.                    */
 /* Every builder gives the same render results (the nearest hit is exact).  */
 /* rc_refit re-transforms the dynamic instances and recomputes the bounds    */
 /* bottom-up on the fixed topology.  Both are asynchronous on `stream`.      */

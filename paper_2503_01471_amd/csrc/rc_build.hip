@@ -1722,8 +1722,8 @@ __global__ __launch_bounds__(kRefitBlock) void k_wide_fill(BuildView v)
 // ---------------------------------------------------------------------------
 // K6: linear BVH (builder RC_BUILD_LBVH), one workgroup per environment of
 // kLeafMax + 1 .. kLbvhMax triangles.  Centroids are quantised to 10 bits per
-// axis inside the environment's centroid bounds and bit-interleaved (Morton
-// order); a triangle whose box has a side above a quarter of the widest
+// axis on a grid of cubic cells over the environment's centroid bounds (1024
+// cells along the widest axis) and bit-interleaved (Morton order); a triangle whose box has a side above a quarter of the widest
 // centroid extent also sets the key's top bit, so the large triangles (a
 // ground plane, the walls of a room) form a subtree of their own beside the
 // root instead of widening the boxes of every subtree their centroids fall
@@ -1817,9 +1817,13 @@ __global__ __launch_bounds__(NT) void k_lbvh(BuildView v, uint8_t *sah_mask)
             b = fmaxf(b, red[3 + k][w]);
         }
         lo[k] = a;
-        scale[k] = b > a ? 1024.0f / (b - a) : 0.0f;
         ext = fmaxf(ext, b - a);
     }
+    // cubic cells: every axis quantised at the step of the widest one, so a
+    // flat environment's first splits cut across its wide axes, not its height
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        scale[k] = ext > 0.0f ? 1024.0f / ext : 0.0f;
     const float big = 0.25f * ext;  // "large": a box side above a quarter of the widest centroid extent
     // keys, padded to a power of two with the largest key
     int P = 8;
