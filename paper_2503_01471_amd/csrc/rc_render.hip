@@ -1288,12 +1288,18 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
 // original-order triangle index, -1 on a miss (NaN outputs, vertex ids -1).
 // Each output is one vector store per ray, so a wavefront writes whole
 // contiguous runs.
+// (u, v) pair for the store: four-byte alignment, like the float buffer it
+// goes to (HIP's float2 would assume eight).
+struct alignas(4) UV {
+    float u, v;
+};
+
 __device__ __forceinline__ void write_extras(const OutView &o, const SceneView &sc, int64_t g, int64_t idx,
                                              const Ray &r, float lx, float ly, float lz)
 {
     const float nan = __builtin_nanf("");
     float3 nrm = make_float3(nan, nan, nan), pt = nrm;
-    float2 uv = make_float2(nan, nan);
+    UV uv{nan, nan};
     int3 vid = make_int3(-1, -1, -1);
     if (g >= 0) {
         const float *w = sc.world + 9 * g;
@@ -1310,7 +1316,7 @@ __device__ __forceinline__ void write_extras(const OutView &o, const SceneView &
         const double W = e2x * qx + e2y * qy + e2z * qz;
         const double t = W / det;
         const double rdet = 1.0 / det;
-        uv = make_float2((float)(U * rdet), (float)(V * rdet));
+        uv = UV{(float)(U * rdet), (float)(V * rdet)};
         pt = make_float3((float)(t * (double)lx), (float)(t * (double)ly), (float)(t * (double)lz));
         double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
         double rl = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
@@ -1325,7 +1331,7 @@ __device__ __forceinline__ void write_extras(const OutView &o, const SceneView &
     if (o.normal)
         *reinterpret_cast<float3 *>(o.normal + 3 * idx) = nrm;
     if (o.bary)
-        *reinterpret_cast<float2 *>(o.bary + 2 * idx) = uv;
+        *reinterpret_cast<UV *>(o.bary + 2 * idx) = uv;
     if (o.point)
         *reinterpret_cast<float3 *>(o.point + 3 * idx) = pt;
     if (o.vert)
