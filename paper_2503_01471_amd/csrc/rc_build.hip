@@ -1723,12 +1723,13 @@ __global__ __launch_bounds__(kRefitBlock) void k_wide_fill(BuildView v)
 // K6: linear BVH (builder RC_BUILD_LBVH), one workgroup per environment of
 // kLeafMax + 1 .. kLbvhMax triangles.  Centroids are quantised to 10 bits per
 // axis on a grid of cubic cells over the environment's centroid bounds (1024
-// cells along the widest axis) and bit-interleaved (Morton order); a triangle whose box has a side above a quarter of the widest
-// centroid extent also sets the key's top bit, so the large triangles (a
-// ground plane, the walls of a room) form a subtree of their own beside the
-// root instead of widening the boxes of every subtree their centroids fall
-// in.  The (code, triangle id) keys are sorted in LDS.  The tree is
-// then built top-down, one level per step: a node over the sorted keys
+// cells along the widest axis) and bit-interleaved (Morton order); a
+// triangle whose box has a side above a quarter of the widest centroid
+// extent also sets the key's top bit, so the large triangles (a ground
+// plane, the walls of a room) form a subtree of their own beside the root
+// instead of widening the boxes of every subtree their centroids fall in.
+// The (code, triangle id) keys are sorted in LDS.  The tree is then built
+// top-down, one level per step: a node over the sorted keys
 // first .. last splits where the range's highest differing key bit changes
 // (the split of the radix tree of Karras 2012, found by binary search on
 // common prefix lengths), unless a subtree that deep could exceed

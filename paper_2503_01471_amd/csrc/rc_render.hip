@@ -1278,6 +1278,10 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
     write_out(o, sc, se, t, row, col, r, nullptr, b);
 }
 
+struct alignas(4) UV {
+    float u, v;
+};
+
 // Further data types of the nearest hit: unit normal facing the sensor,
 // barycentric (u, v), sensor-frame point t * local direction, global vertex
 // ids.  One FP64 Moller-Trumbore solve on the winner's FP32 world vertices
@@ -1287,13 +1291,8 @@ __global__ __launch_bounds__(kBlock) void k_render_brute(SceneView sc, SensorVie
 // reciprocal of det, the normal one reciprocal of its length.  g: global
 // original-order triangle index, -1 on a miss (NaN outputs, vertex ids -1).
 // Each output is one vector store per ray, so a wavefront writes whole
-// contiguous runs.
-// (u, v) pair for the store: four-byte alignment, like the float buffer it
-// goes to (HIP's float2 would assume eight).
-struct alignas(4) UV {
-    float u, v;
-};
-
+// contiguous runs; the (u, v) pair goes out as UV, aligned to four bytes like
+// the float buffer it lands in (HIP's float2 would assume eight).
 __device__ __forceinline__ void write_extras(const OutView &o, const SceneView &sc, int64_t g, int64_t idx,
                                              const Ray &r, float lx, float ly, float lz)
 {
