@@ -303,7 +303,8 @@ rc_status rc_render(rc_context *ctx, const rc_outputs *out, int32_t mode, void *
 /* device memory (code under HIP graph capture, tight serving loops,         */
 /* harnesses that forbid allocation): the persistent launch's work-queue     */
 /* heads live in a fixed 2 KiB device array of the library (one per GPU,     */
-/* held until the process ends) instead of context memory, and the call      */
+/* held until the process ends) instead of context memory (under the        */
+/* one-launch tuning, tiles per pop 0, no queue is used), and the call       */
 /* makes no allocation of any kind.  Outputs, their layout, the further      */
 /* outputs and the shadow mask are those of rc_render and bit-identical to   */
 /* it.  Every call on one GPU, from any context, shares that array and       */
@@ -323,7 +324,8 @@ rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
 /* Batched form: launch choices and one captured graph per simulation step.  */
 /* ------------------------------------------------------------------------ */
 /* Choose the ray-tile shape (columns x rows of one 64-lane wavefront: 4x16, */
-/* 8x8, 16x4 or 32x2), the tiles taken per work-queue pop (2, 4 or 16), the */
+/* 8x8, 16x4 or 32x2), the tiles taken per work-queue pop (2, 4 or 16, or  */
+/* 0: no queue, one launch over every tile as RC_RENDER_FLAT), the         */
 /* queue order (largest estimated cost first, or natural) and the node     */
 /* width (2 or 4; single-level scenes) of the batched render by timing each */
 /* combination on the loaded scene, sensors and poses (temporary outputs   */
@@ -335,12 +337,14 @@ rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
 /* Synchronous.                                                              */
 rc_status rc_autotune(rc_context *ctx, const char *cache_path, int32_t *choice);
 /* Set those choices directly: choice host int32[4] = tile columns (4, 8,   */
-/* 16 or 32), tiles per pop (1..64), cost order (0 or 1), node width (2 or  */
-/* 4).  Node width 4 traverses four-wide records of the same BVH (for each  */
-/* internal node, the boxes one level below its children, 128 bytes, kept   */
-/* beside the binary nodes and refreshed by every single-level build and    */
-/* refit; allocated on first use, 128 bytes per node slot, RC_E_OOM beyond  */
-/* the budget): half the dependent node fetches per ray.                    */
+/* 16 or 32), tiles per pop (0..64, 0 = no queue), cost order (0 or 1),    */
+/* node width (2 or 4).  The request server always uses the queue (4 tiles  */
+/* per pop when the choice is 0).  Node width 4 traverses four-wide         */
+/* records of the same BVH (for each internal node, the boxes one level     */
+/* below its children, 128 bytes, kept beside the binary nodes and          */
+/* refreshed by every single-level build and refit; allocated on first      */
+/* use, 128 bytes per node slot, RC_E_OOM beyond the budget): half the      */
+/* dependent node fetches per ray.                                          */
 rc_status rc_tuning_set(rc_context *ctx, const int32_t *choice);
 
 typedef struct rc_graph rc_graph;

@@ -314,7 +314,7 @@ rc_status rebuild_items(rc_context *c, Sensors &se)
     // output pairs (kPairFlag): a 16-column tile and its right-hand
     // neighbour at an even offset from the queue's start, so that a pop of
     // an even number of tiles always holds both
-    if ((1 << c->tuning.tw_shift) == kPairCols && c->tuning.chunk % 2 == 0)
+    if ((1 << c->tuning.tw_shift) == kPairCols && c->tuning.chunk > 0 && c->tuning.chunk % 2 == 0)
         for (int q = 0; q < kQueues; ++q)
             for (int64_t j = se.qoff[q]; j + 1 < se.qoff[q + 1]; j += 2) {
                 const int2 a = lpt[j], b = lpt[j + 1];
@@ -1011,6 +1011,10 @@ static rc_status render_on(rc_context *c, const rc_outputs *out, int32_t mode, h
         RC_HIP(launch_render_flat(sv, ev, ov, 0, se.n_items, st));
         break;
     case RC_RENDER_BATCHED: {
+        if (c->tuning.chunk == 0) {  // the tuned choice: one launch over every tile, no queue
+            RC_HIP(launch_render_flat(sv, ev, ov, 0, se.n_items, st));
+            break;
+        }
         QueueView q = se.queue(c->tuning.chunk);
         q.head = heads;
         RC_HIP(launch_render_batched(sv, ev, ov, q, c->batched_grid(), st));

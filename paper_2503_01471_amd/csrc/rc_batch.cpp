@@ -78,7 +78,7 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
             while (fgets(line, sizeof line, f)) {
                 if (sscanf(line, "%1023s %d %d %d %d", k, &tw, &ch, &lpt, &width) != 5)
                     continue;  // a line of another format
-                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && ch >= 1 && ch <= 64 &&
+                if (key == k && (tw == 4 || tw == 8 || tw == 16 || tw == 32) && ch >= 0 && ch <= 64 &&
                     (width == 2 || width == 4)) {
                     best.tw_shift = __builtin_ctz(tw);
                     best.chunk = ch;
@@ -102,12 +102,12 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
         RC_HIP(hipEventCreate(&e0));
         RC_HIP(hipEventCreate(&e1));
         float best_ms = 1e30f;
-        const int chunks[3] = {2, 4, 16};
+        const int chunks[4] = {0, 2, 4, 16};  // 0: one launch over every tile, no queue
         // node width 4 (four-wide records) for single-level scenes only
         for (int width = 2; width <= (sc.two_level ? 2 : 4); width += 2)
         for (int tws = 2; tws <= 5; ++tws)
-            for (int ci = 0; ci < 3; ++ci)
-                for (int lpt = 1; lpt >= 0; --lpt) {
+            for (int ci = 0; ci < 4; ++ci)
+                for (int lpt = 1; lpt >= (chunks[ci] == 0 ? 1 : 0); --lpt) {  // without a queue, no order
                     c->tuning = Tuning{tws, chunks[ci], lpt != 0, width};
                     rc_status s = set_node_width(c, width);
                     if (s == RC_OK)
@@ -122,8 +122,11 @@ rc_status rc_autotune(rc_context *c, const char *cache_path, int32_t *choice)
                     for (int rep = 0; rep < 4; ++rep) {
                         if (rep == 1)
                             RC_HIP(hipEventRecord(e0, st));
-                        RC_HIP(launch_render_batched(sc.sview(), ev, ov, se.queue(c->tuning.chunk),
-                                                     c->batched_grid(), st));
+                        if (c->tuning.chunk == 0)
+                            RC_HIP(launch_render_flat(sc.sview(), ev, ov, 0, se.n_items, st));
+                        else
+                            RC_HIP(launch_render_batched(sc.sview(), ev, ov, se.queue(c->tuning.chunk),
+                                                         c->batched_grid(), st));
                     }
                     RC_HIP(hipEventRecord(e1, st));
                     RC_HIP(hipEventSynchronize(e1));
@@ -163,7 +166,7 @@ rc_status rc_tuning_set(rc_context *c, const int32_t *choice)
         return fail(RC_E_BUSY, "a request server is using this context");
     const int tw = choice[0];
     RC_CHECK(tw == 4 || tw == 8 || tw == 16 || tw == 32, "tile columns must be 4, 8, 16 or 32");
-    RC_CHECK(choice[1] >= 1 && choice[1] <= 64, "tiles per pop must be in [1, 64]");
+    RC_CHECK(choice[1] >= 0 && choice[1] <= 64, "tiles per pop must be in [0, 64] (0: no queue)");
     RC_CHECK(choice[2] == 0 || choice[2] == 1, "cost order must be 0 or 1");
     RC_CHECK(choice[3] == 2 || choice[3] == 4, "node width must be 2 or 4");
     c->tuning = Tuning{__builtin_ctz(tw), choice[1], choice[2] != 0, choice[3]};
@@ -251,7 +254,9 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
         if (k == hipSuccess)
             k = launch_refit(sc.two_level ? sc.top->view() : v, cs);
         if (k == hipSuccess)
-            k = launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk), c->batched_grid(), cs);
+            k = c->tuning.chunk == 0
+                    ? launch_render_flat(sc.sview(), se.view(), ov, 0, se.n_items, cs)
+                    : launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk), c->batched_grid(), cs);
         if (k == hipSuccess && extras)
             k = launch_hit_extras(sc.sview(), se.view(), ov, se.n_items, cs);
         if (k == hipSuccess && out->shadow)

@@ -1562,6 +1562,8 @@ hipError_t launch_render_batched(const SceneView &sc, const SensorView &se, cons
 {
     if (q.off[kQueues] == 0)
         return hipSuccess;
+    if (q.chunk < 1)  // a pop must take at least one tile, or the queue never drains
+        return hipErrorInvalidValue;
     hipError_t err = launch_fill_u32(q.head, kQueues * kQueueStride, 0u, st);
     if (err != hipSuccess)
         return err;

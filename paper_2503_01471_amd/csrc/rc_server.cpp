@@ -252,7 +252,7 @@ rc_status launch(rc_server *sv, Slot &sl)
         for (int i = 0; i <= kQueues; ++i)
             qv.off[i] = qoff[i];
         qv.head = sl.head.as<unsigned int>();
-        qv.chunk = c->tuning.chunk;
+        qv.chunk = c->tuning.chunk > 0 ? c->tuning.chunk : 4;  // the server always pops from its queue
         RC_HIP(launch_render_batched(sc.sview(), ev, ov, qv, c->batched_grid(), st));
     } else {
         for (int64_t s = 0; s < S; ++s)

@@ -37,7 +37,7 @@ def test_every_tuning_is_bit_exact():
     ref = _host(R.render(mode=rc.RC_RENDER_FLAT))
     for width in (2, 4):
         for tw in (4, 8, 16, 32):
-            for gs in (1, 2, 4, 16):
+            for gs in (0, 1, 2, 4, 16):  # 0: the batched mode's one-launch choice (no queue)
                 for lpt in (0, 1):
                     _say(f"tuning tile {tw} chunk {gs} lpt {lpt} width {width}")
                     rc.rc_tuning_set(R.ctx, tw, gs, lpt, width)
@@ -146,7 +146,7 @@ def test_autotune_and_cache(tmp_path):
     cache = str(tmp_path / "tune.txt")
     _say("autotune")
     ch = rc.rc_autotune(R.ctx, cache)
-    assert ch[0] in (4, 8, 16, 32) and ch[1] in (2, 4, 16) and ch[2] in (0, 1) and ch[3] in (2, 4)
+    assert ch[0] in (4, 8, 16, 32) and ch[1] in (0, 2, 4, 16) and ch[2] in (0, 1) and ch[3] in (2, 4)
     got = _host(R.render(mode=rc.RC_RENDER_BATCHED))
     for k in ("depth", "seg", "tri"):
         assert np.array_equal(got[k], ref[k])
@@ -192,6 +192,22 @@ def test_step_graph_replays_match_eager():
     with pytest.raises(rc.RCError) as ei:
         rc.rc_graph_launch(g)
     assert ei.value.status == -4
+    rc.rc_graph_destroy(g)
+    # the one-launch choice (no queue) inside a graph
+    rc.rc_tuning_set(R.ctx, 8, 0, 1)
+    g = rc.rc_step_graph_create(R.ctx, R.inst_vel, float(scene.dt), depth=gout["depth"], seg=gout["seg"],
+                                tri=gout["tri"], total_rays=n)
+    rc.rc_graph_set_step(g, 6)
+    for step in (6, 7):
+        _say(f"one-launch graph replay step {step}")
+        rc.rc_graph_launch(g)
+        torch.cuda.synchronize()
+        got = {k: gout[k].cpu().numpy() for k in ("depth", "seg", "tri")}
+        R.move(step)
+        R.refit()
+        ref = _host(R.render(mode=rc.RC_RENDER_FLAT, depth=True, seg=True, tri=True))
+        for k in ("depth", "seg", "tri"):
+            assert np.array_equal(got[k], ref[k]), (step, k)
     rc.rc_graph_destroy(g)
     R.close()
 
@@ -242,6 +258,11 @@ def test_server_alone_equals_mix_and_plain():
     mix, lat = _serve(R, reqs, rc.RC_SERVE_BATCHED)
     _say("server plain")
     plain, _ = _serve(R, reqs, rc.RC_SERVE_PLAIN)
+    _say("server mix under the one-launch tuning (its queue pops 4 tiles)")
+    rc.rc_tuning_set(R.ctx, 8, 0, 1)
+    mix0, _ = _serve(R, reqs, rc.RC_SERVE_BATCHED)
+    for (d0, s0), (d1, s1) in zip(mix0, alone):
+        assert np.array_equal(d0, d1) and np.array_equal(s0, s1)
     for i in range(len(reqs)):
         for j in range(2):
             assert np.array_equal(alone[i][j], mix[i][j]), i

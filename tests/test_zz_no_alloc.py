@@ -72,9 +72,11 @@ def test_noalloc_matches_batched_then_smaller():
     assert RS.total_rays < RB.total_rays
     gs = _render_both(RS, 4)
     _oracle_check(small, gs)
-    # and back on the first context with another pop size
+    # and back on the first context with another pop size, then without a queue
     _say("noalloc: first context again, 16 tiles per pop")
     _render_both(RB, 16)
+    _say("noalloc: first context, one-launch tuning")
+    _render_both(RB, 0)
     with pytest.raises(rc.RCError) as ei:
         rc.rc_render_noalloc(RB.ctx, None, None, None, None, None, 0, normal=torch.empty(3, device="cuda"))
     assert ei.value.status == -1
