@@ -336,7 +336,9 @@ def bench_step(args):
     stats = R.stats()
     from bytemodel import bytemodel
     b_ray = bytemodel.load()[f"cfg{args.cfg}"]["bytes_per_ray"]
-    kernel = "k_render_batched" if mode == rc.RC_RENDER_BATCHED else "k_render_flat"
+    # the batched mode's autotuned launch form: the persistent queue, or one launch without it (tiles per pop 0)
+    kernel = "k_render_batched" if mode == rc.RC_RENDER_BATCHED and (tuning is None or tuning[1] > 0) \
+        else "k_render_flat"
     if args.calib:
         calibration_copy()
     result = {
@@ -514,7 +516,7 @@ def bench_graph(args):
             "warmup": 10, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"cfg4: {WORKLOADS[4]}", "envs": scene.n_envs, "rays_per_step": rays,
-                       "tuning": tuning, "step": "move + transform + refit + queue reset + batched render (graph)"},
+                       "tuning": tuning, "step": "move + transform + refit + batched render in the autotuned launch form (graph)"},
             "env_steps_per_s": scene.n_envs / (ms * 1e-3),
             "per_step_ms": dist,
             "plain": {"ms_per_step": ms_plain, "Mrays_s": rays / ms_plain / 1e3, "speedup_graph_vs_plain":
