@@ -254,9 +254,9 @@ rc_status rc_step_graph_create(rc_context *c, const rc_outputs *out, const float
         if (k == hipSuccess)
             k = launch_refit(sc.two_level ? sc.top->view() : v, cs);
         if (k == hipSuccess)
-            k = c->tuning.chunk == 0
-                    ? launch_render_flat(sc.sview(), se.view(), ov, 0, se.n_items, cs)
-                    : launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk), c->batched_grid(), cs);
+            k = c->tuning.chunk == 0 ? launch_render_flat(sc.sview(), se.view(), ov, 0, se.n_items, cs)
+                                     : launch_render_batched(sc.sview(), se.view(), ov, se.queue(c->tuning.chunk),
+                                                             c->batched_grid(), cs);
         if (k == hipSuccess && extras)
             k = launch_hit_extras(sc.sview(), se.view(), ov, se.n_items, cs);
         if (k == hipSuccess && out->shadow)
