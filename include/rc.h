@@ -338,13 +338,12 @@ rc_status rc_render_stats(rc_context *ctx, void *stream, int64_t *counters);
 rc_status rc_autotune(rc_context *ctx, const char *cache_path, int32_t *choice);
 /* Set those choices directly: choice host int32[4] = tile columns (4, 8,   */
 /* 16 or 32), tiles per pop (0..64, 0 = no queue), cost order (0 or 1),    */
-/* node width (2 or 4).  The request server always uses the queue (4 tiles  */
-/* per pop when the choice is 0).  Node width 4 traverses four-wide         */
-/* records of the same BVH (for each internal node, the boxes one level     */
-/* below its children, 128 bytes, kept beside the binary nodes and          */
-/* refreshed by every single-level build and refit; allocated on first      */
-/* use, 128 bytes per node slot, RC_E_OOM beyond the budget): half the      */
-/* dependent node fetches per ray.                                          */
+/* node width (2 or 4); the request server follows the same choice.  Node  */
+/* width 4 traverses four-wide records of the same BVH (for each internal   */
+/* node, the boxes one level below its children, 128 bytes, kept beside     */
+/* the binary nodes and refreshed by every single-level build and refit;    */
+/* allocated on first use, 128 bytes per node slot, RC_E_OOM beyond the     */
+/* budget): half the dependent node fetches per ray.                        */
 rc_status rc_tuning_set(rc_context *ctx, const int32_t *choice);
 
 typedef struct rc_graph rc_graph;
@@ -388,8 +387,9 @@ rc_status rc_graph_destroy(rc_graph *graph);
 /* within the budget and every library block finds room in the slab.  A     */
 /* caller that never releases library outputs can hold the budget and stall  */
 /* later requests.  In RC_SERVE_BATCHED mode every admission round merges    */
-/* the admitted requests into one persistent launch on one of n_streams      */
-/* streams, so batches that arrive while others run overlap on the device    */
+/* the admitted requests into one batched launch (in the launch form of the */
+/* context's tuning) on one of n_streams streams, so batches that arrive     */
+/* while others run overlap on the device                                    */
 /* (continuous batching); RC_SERVE_PLAIN renders requests one at a time,     */
 /* one launch per environment (the per-environment reference path).  While  */
 /* a server exists the context's scene, sensors and tuning are read-only     */

@@ -246,13 +246,15 @@ rc_status launch(rc_server *sv, Slot &sl)
     ov.seg_tab = sl.stab.as<int32_t *>();
     ov.tri_tab = sl.ttab.as<int32_t *>();
     ov.hit_tab = sl.htab.as<float *>();
-    if (sv->mode == RC_SERVE_BATCHED) {
+    if (sv->mode == RC_SERVE_BATCHED && c->tuning.chunk == 0) {  // the tuned one-launch form, no queue
+        RC_HIP(launch_render_flat(sc.sview(), ev, ov, 0, n_items, st));
+    } else if (sv->mode == RC_SERVE_BATCHED) {
         QueueView qv;
         qv.items = ev.items;
         for (int i = 0; i <= kQueues; ++i)
             qv.off[i] = qoff[i];
         qv.head = sl.head.as<unsigned int>();
-        qv.chunk = c->tuning.chunk > 0 ? c->tuning.chunk : 4;  // the server always pops from its queue
+        qv.chunk = c->tuning.chunk;
         RC_HIP(launch_render_batched(sc.sview(), ev, ov, qv, c->batched_grid(), st));
     } else {
         for (int64_t s = 0; s < S; ++s)

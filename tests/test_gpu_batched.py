@@ -258,7 +258,7 @@ def test_server_alone_equals_mix_and_plain():
     mix, lat = _serve(R, reqs, rc.RC_SERVE_BATCHED)
     _say("server plain")
     plain, _ = _serve(R, reqs, rc.RC_SERVE_PLAIN)
-    _say("server mix under the one-launch tuning (its queue pops 4 tiles)")
+    _say("server mix under the one-launch tuning")
     rc.rc_tuning_set(R.ctx, 8, 0, 1)
     mix0, _ = _serve(R, reqs, rc.RC_SERVE_BATCHED)
     for (d0, s0), (d1, s1) in zip(mix0, alone):
