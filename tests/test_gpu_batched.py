@@ -45,6 +45,10 @@ def test_every_tuning_is_bit_exact():
                         got = _host(R.render(mode=mode))
                         for k in ("depth", "seg", "tri"):
                             assert np.array_equal(got[k], ref[k]), (tw, gs, lpt, width, mode, k)
+    for bad in ((8, -1, 1, 2), (8, 65, 1, 2), (12, 4, 1, 2), (8, 4, 2, 2), (8, 4, 1, 3)):
+        with pytest.raises(rc.RCError) as ei:
+            rc.rc_tuning_set(R.ctx, *bad)
+        assert ei.value.status == -1, bad
     R.close()
 
 
